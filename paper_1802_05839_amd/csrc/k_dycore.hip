@@ -1,0 +1,307 @@
+// Dynamical core kernels: periodic halo fill and one RK3 stage.
+//
+// Method (readings of section "The ASUCA Weather Prediction Model", which
+// fixes a C-grid finite-volume discretisation with I/J horizontal and K
+// separate, and a third-order Runge-Kutta long step):
+//   face values   third-order upwind, weights (-1, 5, 2)/6 toward the wind,
+//                 in k centred next to the ground and lid, no flux through them;
+//   mass flux     F = wind * rho*_face;
+//   density       rho_new = rho_n - h div(F);
+//   tracers       phi_new = phi_n + h (A + B) / rho_new with the increment form
+//                 A = -sum_faces +-F (phi*_face - phi_n) / spacing and the
+//                 density-weighted biharmonic B = -div(K4 rho*_face grad Lap(phi*)).
+//
+// GPU design (section "Architecture-Dependent Storage Order": i stride-1 on
+// GPUs; K marched sequentially inside each thread as in the paper's generated
+// kernels, appendix "Reduced Weather: Diffusion"):
+//   * a 256-thread block owns a 64 x 4 column tile and marches k = 0..nz-1;
+//   * each k-plane of rho*, theta*, q* is staged once into LDS as a 68 x 8
+//     tile (2-cell halo), giving all horizontal neighbours; a 4-deep LDS ring
+//     (planes k..k+3) lets the vertical stencil read k+1, k+2 and the global
+//     loads of plane k+3 overlap the arithmetic of plane k, with one barrier
+//     per plane;
+//   * the vertical window (k-2, k-1) and the lower face flux are carried in
+//     registers, so every face in k is computed once;
+//   * a block's linear id is remapped so that each of the 8 XCDs works on a
+//     contiguous band of tiles (neighbouring tiles share their halo rows in
+//     the same L2);
+//   * the output's periodic halo images are written by the cell that owns
+//     them, so no separate halo pass runs between stages.
+#include "wx_internal.h"
+
+namespace wx {
+namespace {
+
+constexpr int BX = 64, BY = 4;
+constexpr int TW = BX + 4, TH = BY + 4, TN = TW * TH;  // 68 x 8 tile
+constexpr int NT = BX * BY;
+constexpr int NLOAD = (TN + NT - 1) / NT;               // tile elements per thread
+constexpr int NBUF = 4;
+
+// Workgroups are dispatched round-robin over the 8 XCDs; map them so that XCD
+// x receives the contiguous logical range [x*q + min(x, r), ...).
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int q = n >> 3, r = n & 7;
+  const int x = b & 7, slot = b >> 3;
+  return x * q + min(x, r) + slot;
+}
+
+// Third-order upwind face value from the far-upstream, upstream and
+// downstream cells: b + (2 (c - b) + (b - a)) / 6.
+template <typename T>
+__device__ __forceinline__ T face3(T a, T b, T c) {
+  return b + (T(2) * (c - b) + (b - a)) * T(1.0 / 6.0);
+}
+
+template <typename T>
+__global__ void k_halo(T *f0, T *f1, T *f2, T *f3, T *f4, int nx, int ny, long long sj,
+                       long long sk, long long origin) {
+  const int ring = 4 * (nx + 4) + 4 * ny;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ring) return;
+  T *f = blockIdx.z == 0 ? f0 : blockIdx.z == 1 ? f1 : blockIdx.z == 2 ? f2 : blockIdx.z == 3 ? f3 : f4;
+  int i, j;
+  if (r < 4 * (nx + 4)) {
+    const int row = r / (nx + 4);
+    j = row < 2 ? row - 2 : ny + row - 2;
+    i = r % (nx + 4) - 2;
+  } else {
+    const int rr = r - 4 * (nx + 4);
+    j = rr >> 2;
+    const int c = rr & 3;
+    i = c < 2 ? c - 2 : nx + c - 2;
+  }
+  const int si = (i + nx) % nx, sjj = (j + ny) % ny;
+  const long long pl = (long long)blockIdx.y * sk + origin;
+  f[pl + i + j * sj] = f[pl + si + sjj * sj];
+}
+
+template <typename T, int STAGE>
+__global__ __launch_bounds__(NT) void k_stage(StageArgs<T> a) {
+  __shared__ T s_r[NBUF][TN];
+  __shared__ T s_t[NBUF][TN];
+  __shared__ T s_q[NBUF][TN];
+
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
+  const int L = xcd_remap(blockIdx.x, a.nblocks);
+  const int i0 = (L % a.nbx) * BX, j0 = (L / a.nbx) * BY;
+  const int i = i0 + tx, j = j0 + ty;
+  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  const long long sj = a.g.sj, sk = a.g.sk;
+  const bool active = (i < nx) && (j < ny);
+
+  // This thread's share of the (BX+4) x (BY+4) plane tile.
+  long long toff[NLOAD];
+  bool tok[NLOAD];
+#pragma unroll
+  for (int n = 0; n < NLOAD; ++n) {
+    const int e = tid + n * NT;
+    const int gi = i0 - 2 + e % TW, gj = j0 - 2 + e / TW;
+    tok[n] = (e < TN) && (gi < nx + 2) && (gj < ny + 2);
+    toff[n] = a.g.origin + gi + (long long)gj * sj;
+  }
+  T pr[NLOAD], pt[NLOAD], pq[NLOAD];
+  auto fetch = [&](int p) {
+    const long long base = (long long)p * sk;
+#pragma unroll
+    for (int n = 0; n < NLOAD; ++n) {
+      pr[n] = tok[n] ? a.in_r[base + toff[n]] : T(0);
+      pt[n] = tok[n] ? a.in_t[base + toff[n]] : T(0);
+      pq[n] = tok[n] ? a.in_q[base + toff[n]] : T(0);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int n = 0; n < NLOAD; ++n) {
+      const int e = tid + n * NT;
+      if (e < TN) {
+        s_r[buf][e] = pr[n];
+        s_t[buf][e] = pt[n];
+        s_q[buf][e] = pq[n];
+      }
+    }
+  };
+
+  const int npre = nz < 3 ? nz : 3;
+  for (int p = 0; p < npre; ++p) {
+    fetch(p);
+    stash(p);
+  }
+  if (nz > 3) fetch(3);
+  __syncthreads();
+
+  const int c0 = (ty + 2) * TW + (tx + 2);
+  // vertical window of this column: planes k-2 .. k+2
+  T rm2 = 0, rm1 = 0, r0 = s_r[0][c0], rp1 = s_r[1][c0], rp2 = 0;
+  T tm2 = 0, tm1 = 0, t0 = s_t[0][c0], tp1 = s_t[1][c0], tp2 = 0;
+  T qm2 = 0, qm1 = 0, q0 = s_q[0][c0], qp1 = s_q[1][c0], qp2 = 0;
+  (void)rm2; (void)tm2; (void)qm2;
+  // flux and face values at the face below the current level
+  T fzb = 0, tfb = 0, qfb = 0;
+
+  const long long col = a.g.origin + i + (long long)j * sj;
+  T wb = 0;
+  const T h = a.h, rdx = a.rdx, k4 = a.k4;
+  const T r2 = rdx * rdx;
+
+  for (int k = 0; k < nz; ++k) {
+    if (k > 0) __syncthreads();
+    const int b = k & (NBUF - 1);
+    if (k + 2 < nz) {
+      const int b2 = (k + 2) & (NBUF - 1);
+      rp2 = s_r[b2][c0];
+      tp2 = s_t[b2][c0];
+      qp2 = s_q[b2][c0];
+    }
+    if (active) {
+      const T *R = s_r[b] + c0;
+      const T *Th = s_t[b] + c0;
+      const T *Q = s_q[b] + c0;
+      const long long gc = col + (long long)k * sk;
+      const T uE = a.u[gc], uW = a.u[gc - 1], vN = a.v[gc], vS = a.v[gc - sj];
+      const T wt = (k + 1 < nz) ? a.w[gc + sk] : T(0);
+      const T rdz = a.rdz[k];
+
+      // --- density: face values and mass fluxes
+      const T rxm2 = R[-2], rxm1 = R[-1], rxp1 = R[1], rxp2 = R[2];
+      const T rym2 = R[-2 * TW], rym1 = R[-TW], ryp1 = R[TW], ryp2 = R[2 * TW];
+      const T rfE = uE >= T(0) ? face3(rxm1, r0, rxp1) : face3(rxp2, rxp1, r0);
+      const T rfW = uW >= T(0) ? face3(rxm2, rxm1, r0) : face3(rxp1, r0, rxm1);
+      const T rfN = vN >= T(0) ? face3(rym1, r0, ryp1) : face3(ryp2, ryp1, r0);
+      const T rfS = vS >= T(0) ? face3(rym2, rym1, r0) : face3(ryp1, r0, rym1);
+      T rfT = 0, tfT = 0, qfT = 0;
+      const bool top = (k + 1 >= nz);
+      const bool centred = (k == 0) || (k + 2 == nz);
+      if (!top) {
+        if (centred) {
+          rfT = r0 + (rp1 - r0) * T(0.5);
+          tfT = t0 + (tp1 - t0) * T(0.5);
+          qfT = q0 + (qp1 - q0) * T(0.5);
+        } else if (wt >= T(0)) {
+          rfT = face3(rm1, r0, rp1);
+          tfT = face3(tm1, t0, tp1);
+          qfT = face3(qm1, q0, qp1);
+        } else {
+          rfT = face3(rp2, rp1, r0);
+          tfT = face3(tp2, tp1, t0);
+          qfT = face3(qp2, qp1, q0);
+        }
+      }
+      const T fxE = uE * rfE, fxW = uW * rfW, fyN = vN * rfN, fyS = vS * rfS;
+      const T fzT = top ? T(0) : wt * rfT;
+      const T div = (fxE - fxW) * rdx + (fyN - fyS) * rdx + (fzT - fzb) * rdz;
+
+      T br, bt, bq;
+      if (STAGE == 1) {
+        br = r0;
+        bt = t0;
+        bq = q0;
+      } else {
+        br = a.bs_r[gc];
+        bt = a.bs_t[gc];
+        bq = a.bs_q[gc];
+      }
+      const T rnew = br - h * div;
+      const T rinv = T(1) / rnew;
+
+      // density at the four horizontal faces (biharmonic weighting)
+      const T rhE = (r0 + rxp1) * T(0.5), rhW = (rxm1 + r0) * T(0.5);
+      const T rhN = (r0 + ryp1) * T(0.5), rhS = (rym1 + r0) * T(0.5);
+
+      auto tracer = [&](const T *P, T pc, T pm1, T pp1, T pp2, T fzfT, T fzfB, T base) -> T {
+        (void)pp2;
+        const T xm2 = P[-2], xm1 = P[-1], xp1 = P[1], xp2 = P[2];
+        const T ym2 = P[-2 * TW], ym1 = P[-TW], yp1 = P[TW], yp2 = P[2 * TW];
+        const T dpp = P[TW + 1], dpm = P[-TW + 1], dmp = P[TW - 1], dmm = P[-TW - 1];
+        const T fE = uE >= T(0) ? face3(xm1, pc, xp1) : face3(xp2, xp1, pc);
+        const T fW = uW >= T(0) ? face3(xm2, xm1, pc) : face3(xp1, pc, xm1);
+        const T fN = vN >= T(0) ? face3(ym1, pc, yp1) : face3(yp2, yp1, pc);
+        const T fS = vS >= T(0) ? face3(ym2, ym1, pc) : face3(yp1, pc, ym1);
+        const T ax = (fxE * (fE - base) - fxW * (fW - base)) * rdx;
+        const T ay = (fyN * (fN - base) - fyS * (fS - base)) * rdx;
+        const T az = (fzT * (fzfT - base) - fzb * (fzfB - base)) * rdz;
+        const T A = -(ax + ay + az);
+        const T lc = ((xp1 - T(2) * pc + xm1) + (yp1 - T(2) * pc + ym1)) * r2;
+        const T le = ((xp2 - T(2) * xp1 + pc) + (dpp - T(2) * xp1 + dpm)) * r2;
+        const T lw = ((pc - T(2) * xm1 + xm2) + (dmp - T(2) * xm1 + dmm)) * r2;
+        const T ln = ((dpp - T(2) * yp1 + dmp) + (yp2 - T(2) * yp1 + pc)) * r2;
+        const T ls = ((dpm - T(2) * ym1 + dmm) + (pc - T(2) * ym1 + ym2)) * r2;
+        const T gE = k4 * rhE * (le - lc) * rdx, gW = k4 * rhW * (lc - lw) * rdx;
+        const T gN = k4 * rhN * (ln - lc) * rdx, gS = k4 * rhS * (lc - ls) * rdx;
+        const T B = -((gE - gW) * rdx + (gN - gS) * rdx);
+        (void)pm1; (void)pp1;
+        return base + h * (A + B) * rinv;
+      };
+      const T tnew = tracer(Th, t0, tm1, tp1, tp2, tfT, tfb, bt);
+      const T qnew = tracer(Q, q0, qm1, qp1, qp2, qfT, qfb, bq);
+
+      // store the cell and its periodic images in the halo ring
+      a.out_r[gc] = rnew;
+      a.out_t[gc] = tnew;
+      a.out_q[gc] = qnew;
+      const long long di = i < 2 ? nx : (i >= nx - 2 ? -nx : 0);
+      const long long dj = j < 2 ? (long long)ny * sj : (j >= ny - 2 ? -(long long)ny * sj : 0);
+      if (di != 0) {
+        a.out_r[gc + di] = rnew;
+        a.out_t[gc + di] = tnew;
+        a.out_q[gc + di] = qnew;
+      }
+      if (dj != 0) {
+        a.out_r[gc + dj] = rnew;
+        a.out_t[gc + dj] = tnew;
+        a.out_q[gc + dj] = qnew;
+        if (di != 0) {
+          a.out_r[gc + dj + di] = rnew;
+          a.out_t[gc + dj + di] = tnew;
+          a.out_q[gc + dj + di] = qnew;
+        }
+      }
+      fzb = fzT;
+      tfb = tfT;
+      qfb = qfT;
+      wb = wt;
+    }
+    // shift the vertical window
+    rm2 = rm1; rm1 = r0; r0 = rp1; rp1 = rp2;
+    tm2 = tm1; tm1 = t0; t0 = tp1; tp1 = tp2;
+    qm2 = qm1; qm1 = q0; q0 = qp1; qp1 = qp2;
+    // move plane k+3 into the ring and start loading plane k+4
+    if (k + 3 < nz) {
+      stash((k + 3) & (NBUF - 1));
+      if (k + 4 < nz) fetch(k + 4);
+    }
+  }
+  (void)wb;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_halo(T *const *fields, int nf, int nplanes, const Geom &g, hipStream_t s) {
+  if (nf < 1 || nf > 5) return hipErrorInvalidValue;
+  const int ring = 4 * (g.nx + 4) + 4 * g.ny;
+  dim3 grid((ring + 255) / 256, nplanes, nf);
+  T *f[5];
+  for (int n = 0; n < 5; ++n) f[n] = fields[n < nf ? n : 0];
+  hipLaunchKernelGGL(k_halo<T>, grid, dim3(256), 0, s, f[0], f[1], f[2], f[3], f[4], g.nx, g.ny,
+                     g.sj, g.sk, g.origin);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stage(const StageArgs<T> &a, int stage, hipStream_t s) {
+  dim3 block(BX, BY);
+  dim3 grid(a.nblocks);
+  if (stage == 1)
+    hipLaunchKernelGGL((k_stage<T, 1>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_stage<T, 2>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_halo<float>(float *const *, int, int, const Geom &, hipStream_t);
+template hipError_t launch_halo<double>(double *const *, int, int, const Geom &, hipStream_t);
+template hipError_t launch_stage<float>(const StageArgs<float> &, int, hipStream_t);
+template hipError_t launch_stage<double>(const StageArgs<double> &, int, hipStream_t);
+
+}  // namespace wx

@@ -1,0 +1,503 @@
+// C ABI (include/wx.h): state, validation, workspace layout and launch plan.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "wx.h"
+#include "wx_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define WX_HIP(call)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) return fail(WX_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+// Default constants (the readings; see wx_param in wx.h).
+const double kDefaults[WX_PARAM_COUNT] = {1.0 / 256.0, 0.1, 50.0, 0.02, 1004.0, 64.0, 0.0, 1.0};
+
+struct Impl {
+  std::vector<double> dz;
+  double param[WX_PARAM_COUNT];
+  std::vector<unsigned char> host_consts[2];  // per dtype, uploaded into the workspace
+  const void *uploaded_ws[2] = {nullptr, nullptr};
+  bool dirty[2] = {true, true};
+};
+
+Impl *impl_of(const wx_state *s) { return static_cast<Impl *>(s->impl); }
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace layout for element size es:
+//   [s1 rho, theta, q][s2 rho, theta, q]   6 cell fields
+//   consts: dz, 1/dz, 1/dz_{k+1/2} (dtype), vol (double)
+//   column scratch: 3 * nz * nx * ny doubles
+//   mass partials: 6 doubles per physics block
+struct Layout {
+  size_t field, stage, consts, scratch, partials, total;
+};
+
+Layout layout(const wx_state *s, size_t es) {
+  Layout L{};
+  L.field = align256(size_t(s->field_elems) * es);
+  L.stage = 0;
+  size_t off = 6 * L.field;
+  L.consts = off;
+  off += align256(3 * size_t(s->nz) * es) + align256(size_t(s->nz) * 8);
+  L.scratch = off;
+  off += align256(3 * size_t(s->nz) * size_t(s->nx) * size_t(s->ny) * 8);
+  L.partials = off;
+  off += align256(size_t(wx::phys_blocks(s->nx, s->ny)) * 6 * 8);
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+void build_consts(const wx_state *s, std::vector<unsigned char> &out) {
+  const int nz = s->nz;
+  const size_t es = sizeof(T);
+  out.assign(align256(3 * nz * es) + align256(nz * 8), 0);
+  T *dz = reinterpret_cast<T *>(out.data());
+  T *rdz = dz + nz;
+  T *rdzi = dz + 2 * nz;
+  const std::vector<double> &d = impl_of(s)->dz;
+  for (int k = 0; k < nz; ++k) {
+    dz[k] = T(d[k]);
+    rdz[k] = T(1.0 / d[k]);
+    rdzi[k] = k + 1 < nz ? T(2.0 / (d[k] + d[k + 1])) : T(0);
+  }
+  double *vol = reinterpret_cast<double *>(out.data() + align256(3 * nz * es));
+  for (int k = 0; k < nz; ++k) vol[k] = s->dx * s->dx * d[k];
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+int check_fields(const wx_state *s, bool need_phys) {
+  if (s->dtype != WX_F32 && s->dtype != WX_F64) return fail(WX_E_INVAL, "dtype %d is not WX_F32/WX_F64", s->dtype);
+  const void *req[] = {s->rho, s->theta, s->q, s->u, s->v, s->w, s->workspace, s->mass_out, s->flags_out};
+  const char *names[] = {"rho", "theta", "q", "u", "v", "w", "workspace", "mass_out", "flags_out"};
+  for (int n = 0; n < 9; ++n) {
+    if (!req[n]) return fail(WX_E_STATE, "state pointer '%s' is NULL", names[n]);
+    if (!aligned16(req[n])) return fail(WX_E_INVAL, "state pointer '%s' is not 16-byte aligned", names[n]);
+  }
+  if (need_phys) {
+    const void *p2[] = {s->theta_s, s->q_s, s->f0, s->ch};
+    const char *n2[] = {"theta_s", "q_s", "f0", "ch"};
+    for (int n = 0; n < 4; ++n) {
+      if (!p2[n]) return fail(WX_E_STATE, "state pointer '%s' is NULL", n2[n]);
+      if (!aligned16(p2[n])) return fail(WX_E_INVAL, "state pointer '%s' is not 16-byte aligned", n2[n]);
+    }
+  }
+  return WX_OK;
+}
+
+wx::Geom geom(const wx_state *s) { return wx::Geom{s->nx, s->ny, s->nz, s->stride_j, s->stride_k, s->origin}; }
+
+// Upload the per-dtype constants into the workspace when they changed.
+template <typename T>
+int ensure_consts(wx_state *s, hipStream_t st) {
+  Impl *im = impl_of(s);
+  const int d = sizeof(T) == 4 ? 0 : 1;
+  if (!im->dirty[d] && im->uploaded_ws[d] == s->workspace) return WX_OK;
+  build_consts<T>(s, im->host_consts[d]);
+  const Layout L = layout(s, sizeof(T));
+  WX_HIP(hipMemcpyAsync(static_cast<unsigned char *>(s->workspace) + L.consts, im->host_consts[d].data(),
+                        im->host_consts[d].size(), hipMemcpyHostToDevice, st));
+  im->uploaded_ws[d] = s->workspace;
+  im->dirty[d] = false;
+  im->dirty[1 - d] = true;
+  return WX_OK;
+}
+
+// Launch-class timing hook used by wx_profile_step.
+struct Timer {
+  std::vector<hipEvent_t> *ev = nullptr;
+  std::vector<int> *cls = nullptr;
+  hipStream_t st = nullptr;
+  int begin(int c) {
+    if (!ev) return WX_OK;
+    hipEvent_t e;
+    WX_HIP(hipEventCreate(&e));
+    WX_HIP(hipEventRecord(e, st));
+    ev->push_back(e);
+    cls->push_back(c);
+    return WX_OK;
+  }
+  int end() {
+    if (!ev) return WX_OK;
+    hipEvent_t e;
+    WX_HIP(hipEventCreate(&e));
+    WX_HIP(hipEventRecord(e, st));
+    ev->push_back(e);
+    cls->push_back(-1);
+    return WX_OK;
+  }
+};
+
+#define WX_TRY(x)          \
+  do {                     \
+    int r_ = (x);          \
+    if (r_ != WX_OK) return r_; \
+  } while (0)
+
+template <typename T>
+struct Plan {
+  wx_state *s;
+  hipStream_t st;
+  Layout L;
+  T *s1[3], *s2[3], *base[3];
+  const T *dz, *rdz, *rdzi;
+  const double *vol;
+  double *scratch, *partials;
+
+  Plan(wx_state *s_, hipStream_t st_) : s(s_), st(st_) {
+    L = layout(s, sizeof(T));
+    unsigned char *ws = static_cast<unsigned char *>(s->workspace);
+    for (int f = 0; f < 3; ++f) {
+      s1[f] = reinterpret_cast<T *>(ws + size_t(f) * L.field);
+      s2[f] = reinterpret_cast<T *>(ws + size_t(3 + f) * L.field);
+    }
+    base[0] = static_cast<T *>(s->rho);
+    base[1] = static_cast<T *>(s->theta);
+    base[2] = static_cast<T *>(s->q);
+    dz = reinterpret_cast<const T *>(ws + L.consts);
+    rdz = dz + s->nz;
+    rdzi = dz + 2 * s->nz;
+    vol = reinterpret_cast<const double *>(ws + L.consts + align256(3 * size_t(s->nz) * sizeof(T)));
+    scratch = reinterpret_cast<double *>(ws + L.scratch);
+    partials = reinterpret_cast<double *>(ws + L.partials);
+  }
+
+  int halo(Timer &tm) {
+    T *f[5] = {base[0], base[1], base[2], static_cast<T *>(s->u), static_cast<T *>(s->v)};
+    WX_TRY(tm.begin(0));
+    WX_HIP(wx::launch_halo<T>(f, 5, s->nz, geom(s), st));
+    return tm.end();
+  }
+
+  int stage(int n, T *const *in, T *const *out, T h, Timer &tm) {
+    const Impl *im = impl_of(s);
+    wx::StageArgs<T> a;
+    a.in_r = in[0]; a.in_t = in[1]; a.in_q = in[2];
+    a.bs_r = base[0]; a.bs_t = base[1]; a.bs_q = base[2];
+    a.out_r = out[0]; a.out_t = out[1]; a.out_q = out[2];
+    a.u = static_cast<const T *>(s->u);
+    a.v = static_cast<const T *>(s->v);
+    a.w = static_cast<const T *>(s->w);
+    a.rdz = rdz;
+    a.g = geom(s);
+    a.h = h;
+    a.rdx = T(1.0 / s->dx);
+    a.k4 = T(im->param[WX_PARAM_GAMMA4] * std::pow(s->dx, 4) / s->dt);
+    a.nbx = wx::stage_tiles_x(s->nx);
+    a.nblocks = a.nbx * wx::stage_tiles_y(s->ny);
+    WX_TRY(tm.begin(n));
+    WX_HIP(wx::launch_stage<T>(a, n, st));
+    return tm.end();
+  }
+
+  wx::PhysArgs<T> phys_args(int mode, int do_mass, T *tt, T *tq) {
+    const Impl *im = impl_of(s);
+    wx::PhysArgs<T> a;
+    a.rho = base[0]; a.th = base[1]; a.q = base[2];
+    a.u = static_cast<const T *>(s->u);
+    a.v = static_cast<const T *>(s->v);
+    a.th_s = static_cast<const T *>(s->theta_s);
+    a.q_s = static_cast<const T *>(s->q_s);
+    a.f0 = static_cast<const T *>(s->f0);
+    a.ch = static_cast<const T *>(s->ch);
+    a.tend_t = tt;
+    a.tend_q = tq;
+    a.dz = dz;
+    a.rdzi = rdzi;
+    a.vol = vol;
+    a.scratch = scratch;
+    a.partials = partials;
+    a.flags = s->flags_out;
+    a.g = geom(s);
+    a.dt = T(s->dt);
+    a.kmin = T(im->param[WX_PARAM_KMIN]);
+    a.l2 = T(im->param[WX_PARAM_MIXLEN] * im->param[WX_PARAM_MIXLEN]);
+    a.kappa = T(im->param[WX_PARAM_KAPPA_Q]);
+    a.cp = T(im->param[WX_PARAM_CP]);
+    a.tdd = T(im->param[WX_PARAM_TDD]);
+    a.theta_off = im->param[WX_PARAM_THETA_OFFSET];
+    a.mode = mode;
+    a.do_mass = do_mass;
+    a.use_lds = (sizeof(T) == 4 && s->nz <= wx::PHYS_LDS_NZ_MAX) ? 1 : 0;
+    return a;
+  }
+
+  int physics(int do_mass, Timer &tm) {
+    WX_TRY(tm.begin(4));
+    WX_HIP(wx::launch_physics<T>(phys_args(0, do_mass, nullptr, nullptr), st));
+    return tm.end();
+  }
+
+  int mass(Timer &tm) {
+    wx::MassArgs<T> a;
+    a.rho = base[0]; a.th = base[1]; a.q = base[2];
+    a.vol = vol;
+    a.partials = partials;
+    a.flags = s->flags_out;
+    a.g = geom(s);
+    a.theta_off = impl_of(s)->param[WX_PARAM_THETA_OFFSET];
+    WX_TRY(tm.begin(4));
+    WX_HIP(wx::launch_mass<T>(a, st));
+    return tm.end();
+  }
+
+  int mass_final(Timer &tm) {
+    WX_TRY(tm.begin(5));
+    WX_HIP(wx::launch_mass_final(partials, wx::phys_blocks(s->nx, s->ny), s->mass_out, st));
+    return tm.end();
+  }
+
+  int run(int nsteps, Timer &tm) {
+    WX_TRY(ensure_consts<T>(s, st));
+    WX_HIP(wx::launch_fill_i32(s->flags_out, WX_NFLAGS, 0, st));
+    WX_TRY(halo(tm));
+    const int every = int(impl_of(s)->param[WX_PARAM_MASS_EVERY]);
+    const T dt = T(s->dt);
+    for (int n = 1; n <= nsteps; ++n) {
+      WX_TRY(stage(1, base, s1, dt / T(3), tm));
+      WX_TRY(stage(2, s1, s2, dt / T(2), tm));
+      WX_TRY(stage(3, s2, base, dt, tm));
+      const int do_mass = every > 0 && (n % every == 0 || n == nsteps);
+      if (s->phys_mode == WX_PHYS_PLAIN) {
+        WX_TRY(physics(do_mass, tm));
+      } else if (do_mass) {
+        WX_TRY(mass(tm));
+      }
+      if (do_mass) WX_TRY(mass_final(tm));
+    }
+    return WX_OK;
+  }
+};
+
+int validate_for_step(wx_state *s) {
+  if (!s || !s->impl) return fail(WX_E_INVAL, "state is NULL");
+  WX_TRY(check_fields(s, s->phys_mode == WX_PHYS_PLAIN));
+  if (s->phys_mode != WX_PHYS_OFF && s->phys_mode != WX_PHYS_PLAIN)
+    return fail(WX_E_UNSUPPORTED, "phys_mode %d is not supported", s->phys_mode);
+  return WX_OK;
+}
+
+int run_steps(wx_state *s, int nsteps, hipStream_t st, Timer &tm) {
+  if (s->dtype == WX_F32) {
+    Plan<float> p(s, st);
+    return p.run(nsteps, tm);
+  }
+  Plan<double> p(s, st);
+  return p.run(nsteps, tm);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *wx_last_error(void) { return g_err.c_str(); }
+
+wx_state *wx_create(int nx, int ny, int nz, double dt, double dx, const double *dz) {
+  if (nx < 4 || ny < 4 || nz < 3 || nz > 1024) {
+    fail(WX_E_INVAL, "grid %d x %d x %d outside nx, ny >= 4, 3 <= nz <= 1024", nx, ny, nz);
+    return nullptr;
+  }
+  if (!(dt > 0) || !std::isfinite(dt) || !(dx > 0) || !std::isfinite(dx)) {
+    fail(WX_E_INVAL, "dt and dx must be finite and > 0");
+    return nullptr;
+  }
+  if (!dz) {
+    fail(WX_E_INVAL, "dz is NULL");
+    return nullptr;
+  }
+  for (int k = 0; k < nz; ++k)
+    if (!(dz[k] > 0) || !std::isfinite(dz[k])) {
+      fail(WX_E_INVAL, "dz[%d] must be finite and > 0", k);
+      return nullptr;
+    }
+  const long long sj = ((long long)nx + 2 * WX_HALO + 63) / 64 * 64;
+  const long long sk = sj * (ny + 2 * WX_HALO);
+  if (sk * (long long)(nz + 1) > (1LL << 40)) {
+    fail(WX_E_INVAL, "grid too large");
+    return nullptr;
+  }
+  wx_state *s = new (std::nothrow) wx_state();
+  Impl *im = new (std::nothrow) Impl();
+  if (!s || !im) {
+    delete s;
+    delete im;
+    fail(WX_E_INVAL, "out of host memory");
+    return nullptr;
+  }
+  im->dz.assign(dz, dz + nz);
+  for (int p = 0; p < WX_PARAM_COUNT; ++p) im->param[p] = kDefaults[p];
+  s->nx = nx;
+  s->ny = ny;
+  s->nz = nz;
+  s->halo = WX_HALO;
+  s->stride_j = sj;
+  s->stride_k = sk;
+  s->origin = WX_HALO + WX_HALO * sj;
+  s->field_elems = sk * nz;
+  s->wfield_elems = sk * (nz + 1);
+  s->dt = dt;
+  s->dx = dx;
+  s->dtype = WX_F32;
+  s->phys_mode = WX_PHYS_PLAIN;
+  s->impl = im;
+  g_err.clear();
+  return s;
+}
+
+void wx_destroy(wx_state *s) {
+  if (!s) return;
+  delete impl_of(s);
+  delete s;
+}
+
+size_t wx_workspace_bytes(const wx_state *s, int dtype) {
+  if (!s || (dtype != WX_F32 && dtype != WX_F64)) return 0;
+  return layout(s, dtype == WX_F32 ? 4 : 8).total;
+}
+
+int wx_set_param(wx_state *s, int param, double value) {
+  if (!s || !s->impl) return fail(WX_E_INVAL, "state is NULL");
+  if (param < 0 || param >= WX_PARAM_COUNT) return fail(WX_E_INVAL, "unknown param %d", param);
+  if (!std::isfinite(value)) return fail(WX_E_INVAL, "param value must be finite");
+  if (param == WX_PARAM_CP && !(value > 0)) return fail(WX_E_INVAL, "cp must be > 0");
+  if (param != WX_PARAM_THETA_OFFSET && value < 0) return fail(WX_E_INVAL, "param %d must be >= 0", param);
+  if (param == WX_PARAM_MASS_EVERY && value != std::floor(value))
+    return fail(WX_E_INVAL, "mass_every must be an integer");
+  impl_of(s)->param[param] = value;
+  return WX_OK;
+}
+
+int wx_get_param(const wx_state *s, int param, double *value) {
+  if (!s || !s->impl || !value) return fail(WX_E_INVAL, "NULL argument");
+  if (param < 0 || param >= WX_PARAM_COUNT) return fail(WX_E_INVAL, "unknown param %d", param);
+  *value = impl_of(s)->param[param];
+  return WX_OK;
+}
+
+int wx_halo(wx_state *s, void *stream) {
+  if (!s || !s->impl) return fail(WX_E_INVAL, "state is NULL");
+  const void *req[] = {s->rho, s->theta, s->q, s->u, s->v};
+  for (const void *p : req)
+    if (!p) return fail(WX_E_STATE, "a field pointer is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (s->dtype == WX_F32) {
+    float *f[5] = {(float *)s->rho, (float *)s->theta, (float *)s->q, (float *)s->u, (float *)s->v};
+    WX_HIP(wx::launch_halo<float>(f, 5, s->nz, geom(s), st));
+  } else if (s->dtype == WX_F64) {
+    double *f[5] = {(double *)s->rho, (double *)s->theta, (double *)s->q, (double *)s->u, (double *)s->v};
+    WX_HIP(wx::launch_halo<double>(f, 5, s->nz, geom(s), st));
+  } else {
+    return fail(WX_E_INVAL, "bad dtype %d", s->dtype);
+  }
+  return WX_OK;
+}
+
+int wx_step(wx_state *s, int nsteps, void *stream) {
+  WX_TRY(validate_for_step(s));
+  if (nsteps < 0) return fail(WX_E_INVAL, "nsteps must be >= 0");
+  s->stream = stream;
+  Timer tm;
+  return run_steps(s, nsteps, static_cast<hipStream_t>(stream), tm);
+}
+
+int wx_physics(wx_state *s, wx_tend *t, int mode) {
+  if (!s || !s->impl) return fail(WX_E_INVAL, "state is NULL");
+  if (mode != WX_PHYS_PLAIN) return fail(WX_E_UNSUPPORTED, "wx_physics mode %d is not supported", mode);
+  if (!t || !t->dtheta || !t->dq) return fail(WX_E_INVAL, "tendency buffers are NULL");
+  if (!aligned16(t->dtheta) || !aligned16(t->dq)) return fail(WX_E_INVAL, "tendency buffers must be 16-byte aligned");
+  WX_TRY(check_fields(s, true));
+  hipStream_t st = static_cast<hipStream_t>(s->stream);
+  if (s->dtype == WX_F32) {
+    Plan<float> p(s, st);
+    WX_TRY(ensure_consts<float>(s, st));
+    WX_HIP(wx::launch_physics<float>(p.phys_args(1, 0, (float *)t->dtheta, (float *)t->dq), st));
+  } else {
+    Plan<double> p(s, st);
+    WX_TRY(ensure_consts<double>(s, st));
+    WX_HIP(wx::launch_physics<double>(p.phys_args(1, 0, (double *)t->dtheta, (double *)t->dq), st));
+  }
+  return WX_OK;
+}
+
+int wx_mass(wx_state *s) {
+  if (!s || !s->impl) return fail(WX_E_INVAL, "state is NULL");
+  WX_TRY(check_fields(s, false));
+  hipStream_t st = static_cast<hipStream_t>(s->stream);
+  Timer tm;
+  if (s->dtype == WX_F32) {
+    Plan<float> p(s, st);
+    WX_TRY(ensure_consts<float>(s, st));
+    WX_TRY(p.mass(tm));
+    return p.mass_final(tm);
+  }
+  Plan<double> p(s, st);
+  WX_TRY(ensure_consts<double>(s, st));
+  WX_TRY(p.mass(tm));
+  return p.mass_final(tm);
+}
+
+int wx_profile_step(wx_state *s, int nsteps, void *stream, double *ms_out, int n_out) {
+  WX_TRY(validate_for_step(s));
+  if (nsteps < 1) return fail(WX_E_INVAL, "nsteps must be >= 1");
+  if (!ms_out || n_out < 1) return fail(WX_E_INVAL, "ms_out must hold at least one value");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  s->stream = stream;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> cls;
+  Timer tm;
+  tm.ev = &ev;
+  tm.cls = &cls;
+  tm.st = st;
+  int rc = run_steps(s, nsteps, st, tm);
+  hipError_t se = hipStreamSynchronize(st);
+  double sum[8] = {0};
+  int cnt[8] = {0};
+  if (rc == WX_OK && se == hipSuccess) {
+    for (size_t n = 0; n + 1 < ev.size(); ++n) {
+      if (cls[n] < 0 || cls[n + 1] != -1) continue;
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, ev[n], ev[n + 1]) == hipSuccess) {
+        sum[cls[n]] += ms;
+        cnt[cls[n]] += 1;
+      }
+    }
+  }
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  if (rc != WX_OK) return rc;
+  if (se != hipSuccess) return fail(WX_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(se));
+  for (int c = 0; c < n_out; ++c) ms_out[c] = (c < 8 && cnt[c]) ? sum[c] / cnt[c] : 0.0;
+  return WX_OK;
+}
+
+int wx_copy_probe(void *dst, const void *src, size_t bytes, void *stream) {
+  if (!dst || !src) return fail(WX_E_INVAL, "NULL pointer");
+  if (bytes % 16 || !aligned16(dst) || !aligned16(src)) return fail(WX_E_INVAL, "copy needs 16-byte multiples");
+  WX_HIP(wx::launch_copy(dst, src, bytes, static_cast<hipStream_t>(stream)));
+  return WX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+// Internal launch interface between the C-ABI host code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wx {
+
+// Geometry shared by every kernel.
+struct Geom {
+  int nx, ny, nz;
+  long long sj, sk, origin;  // element strides and offset of interior (0,0,0)
+};
+
+template <typename T>
+struct StageArgs {
+  const T *in_r, *in_t, *in_q;     // stage input (read with its 2-cell halo)
+  const T *bs_r, *bs_t, *bs_q;     // step base (read at the cell only)
+  T *out_r, *out_t, *out_q;        // stage output (cell + periodic halo images)
+  const T *u, *v, *w;              // frozen winds
+  const T *rdz;                    // 1/dz_k
+  Geom g;
+  T h, rdx, k4;                    // stage step, 1/dx, biharmonic coefficient
+  int nbx, nblocks;                // tiles in i, total tiles
+};
+
+template <typename T>
+struct PhysArgs {
+  T *rho, *th, *q;                 // post-dycore state (updated in place in mode 0)
+  const T *u, *v;
+  const T *th_s, *q_s, *f0, *ch;   // 2D surface fields (nx*ny)
+  T *tend_t, *tend_q;              // mode 1 outputs (nx*ny*nz) or null
+  const T *dz, *rdzi;              // dz_k; 1/dz_{k+1/2} (nz-1 used)
+  const double *vol;               // dx*dy*dz_k
+  double *scratch;                 // column elimination scratch [3][nz][nx*ny]
+  double *partials;                // mass partials, 6 per block
+  int *flags;                      // WX_NFLAGS counters
+  Geom g;
+  T dt, kmin, l2, kappa, cp, tdd;
+  double theta_off;
+  int mode;                        // 0: update state, 1: write tendencies
+  int do_mass;                     // mode 0: accumulate mass partials
+  int use_lds;                     // FP32 elimination stored in LDS
+};
+
+template <typename T>
+struct MassArgs {
+  const T *rho, *th, *q;
+  const double *vol;
+  double *partials;
+  int *flags;
+  Geom g;
+  double theta_off;
+};
+
+constexpr int PHYS_BX = 64;        // columns per physics block (one wave)
+constexpr int PHYS_LDS_NZ_MAX = 80;
+
+template <typename T>
+hipError_t launch_halo(T *const *fields, int nf, int nplanes, const Geom &g, hipStream_t s);
+template <typename T>
+hipError_t launch_stage(const StageArgs<T> &a, int stage, hipStream_t s);
+template <typename T>
+hipError_t launch_physics(const PhysArgs<T> &a, hipStream_t s);
+template <typename T>
+hipError_t launch_mass(const MassArgs<T> &a, hipStream_t s);
+hipError_t launch_mass_final(const double *partials, int nparts, double *out, hipStream_t s);
+hipError_t launch_fill_i32(int *p, int n, int value, hipStream_t s);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+inline int stage_tiles_x(int nx) { return (nx + 63) / 64; }
+inline int stage_tiles_y(int ny) { return (ny + 3) / 4; }
+inline int phys_blocks(int nx, int ny) { return ((nx + PHYS_BX - 1) / PHYS_BX) * ny; }
+
+}  // namespace wx

@@ -12,7 +12,7 @@ order the paper prescribes for GPUs (section "Architecture-Dependent Storage
 Order").  ``k = 0`` is the lowest level.
 
 Random streams: ``numpy.random.Generator(PCG64(SeedSequence([seed, sid])))``
-with stream ids psi=1, w=3, q=4, mode phases=5, C_h=6 (2 is unused).
+with stream ids psi_z=1, psi_x=2, psi_y=3, q=4, mode phases=5, C_h=6.
 
 Recipe (the paper gives only the problem class, a 2 km mesoscale C-grid with
 58 stretched levels, section "The ASUCA Weather Prediction Model"; the numbers
@@ -20,19 +20,20 @@ below are this implementation's choices):
 
 * ``dz_k = 50 * r**k`` with ``r = 20**(1/(nz-1))`` (50 m at the ground,
   1000 m at the top).
-* Horizontal winds at C-grid faces (u at east faces ``x=(i+1)dx``, v at north
-  faces ``y=(j+1)dy``) from a streamfunction psi at cell corners,
-  ``u = -d(psi)/dy``, ``v = d(psi)/dx``: white psi noise scaled so that u and v
-  are each N(0, 10^2) m/s, plus three 5 m/s sine modes with wave numbers (1,0),
-  (0,1), (1,1) over the domain and uniform random phases.
-* w at the ``nz+1`` face levels: N(0, 0.1^2) on interior faces with the mean of
-  each face level removed, 0 at the ground and the lid.
-* An irrotational correction ``grad(chi)`` (periodic Poisson solve per level)
-  absorbs the vertical divergence of w, so the discrete 3D divergence of the
-  frozen wind is zero to rounding.  Independent draws per face give a wind
-  whose convergence zones compound density exponentially (the exact solution
-  of the continuity equation under a frozen divergent wind is unbounded), so a
-  multi-hundred-step run could not stay finite under any scheme.
+* Winds at C-grid faces (u at east faces ``x=(i+1)dx``, v at north faces
+  ``y=(j+1)dy``, w at the ``nz+1`` face levels) are the discrete curl of an
+  edge-staggered vector potential ``(psi_x, psi_y, psi_z)``:
+  ``u = d(psi_z)/dy - d(psi_y)/dz``, ``v = d(psi_x)/dz - d(psi_z)/dx``,
+  ``w = d(psi_y)/dx - d(psi_x)/dy``.  psi_z is white noise scaled so that its
+  part of u and v is N(0, 10^2) m/s, plus three 5 m/s sine modes with wave
+  numbers (1,0), (0,1), (1,1) over the domain and uniform random phases.
+  psi_x, psi_y are white noise scaled so that w is N(0, 0.1^2) m/s, and zero
+  on the ground and lid edges so that w vanishes there.  The discrete 3D
+  divergence of such a wind is zero to rounding.  Independent draws per face
+  would give a wind whose convergence zones compound density exponentially
+  (the exact solution of the continuity equation under a frozen divergent
+  wind is unbounded), so a multi-hundred-step run could not stay finite under
+  any scheme.  The vertical part adds about 141/dz_k m/s rms to u and v.
 * theta = 300 + 2 sin(2 pi x/Lx) sin(2 pi y/Ly) exp(-((z-3000)/3000)^2) K.
 * q = min(0.02, lognormal(ln 0.006, 0.5)) kg/kg, independent per cell.
 * rho = 1.2 exp(-z/8000) kg/m^3.
@@ -47,7 +48,7 @@ from typing import Dict, Optional
 
 import numpy as np
 
-STREAM_PSI, STREAM_W, STREAM_Q, STREAM_PHASE, STREAM_CH = 1, 3, 4, 5, 6
+STREAM_PSI_Z, STREAM_PSI_X, STREAM_PSI_Y, STREAM_Q, STREAM_PHASE, STREAM_CH = 1, 2, 3, 4, 5, 6
 
 # Named grid configurations (the paper's 1581x1301x58 production grid and
 # smaller shares of it).
@@ -137,64 +138,94 @@ def cfl_dt(u: np.ndarray, v: np.ndarray, w: np.ndarray, dx: float, dy: float,
 
 def generate(nx: int, ny: int, nz: int, seed: int = 0, dx: float = DX_DEFAULT,
              dz: Optional[np.ndarray] = None, dt: Optional[float] = None,
-             cfl: float = CFL_DEFAULT) -> Inputs:
-    """Draw one seeded problem of the given size (all float64)."""
+             cfl: float = CFL_DEFAULT, dtype=np.float64) -> Inputs:
+    """Draw one seeded problem of the given size.
+
+    Values are computed in float64 one k-plane at a time and stored as
+    ``dtype`` (float64 by default; float32 halves the host memory of a
+    full-size problem and gives the same values as rounding the float64 draw).
+    """
     if dz is None:
         dz = stretched_dz(nz)
     dz = np.asarray(dz, dtype=np.float64)
     dy = dx
     lx, ly = nx * dx, ny * dy
     zc = level_centres(dz)
-
     i = np.arange(nx, dtype=np.float64)
     j = np.arange(ny, dtype=np.float64)
 
-    # streamfunction at corners (x=(i+1)dx, y=(j+1)dy): noise plus three modes
-    sig_psi = 10.0 * dy / np.sqrt(2.0)
-    psi = _rng(seed, STREAM_PSI).normal(0.0, sig_psi, size=(nz, ny, nx))
+    g_psi = _rng(seed, STREAM_PSI_Z)
+    g_px = _rng(seed, STREAM_PSI_X)
+    g_py = _rng(seed, STREAM_PSI_Y)
+    g_q = _rng(seed, STREAM_Q)
     phases = _rng(seed, STREAM_PHASE).uniform(0.0, 2.0 * np.pi, size=3)
+
+    # psi_z modes on vertical edges (x=(i+1)dx, y=(j+1)dy), same on every level
     xq, yq = (i + 1.0) * dx, (j + 1.0) * dy
+    modes = np.zeros((ny, nx))
     for (a, b), ph in zip(((1.0, 0.0), (0.0, 1.0), (1.0, 1.0)), phases):
         kmag = 2.0 * np.pi * np.hypot(a / lx, b / ly)
-        psi += ((5.0 / kmag) * np.sin(2.0 * np.pi * (a * xq[None, :] / lx + b * yq[:, None] / ly)
-                                      + ph))[None]
-    u = -(psi - np.roll(psi, 1, axis=1)) / dy
-    v = (psi - np.roll(psi, 1, axis=2)) / dx
-    del psi
+        modes += (5.0 / kmag) * np.sin(2.0 * np.pi * (a * xq[None, :] / lx + b * yq[:, None] / ly) + ph)
+    sig_psi = 10.0 * dy / np.sqrt(2.0)
+    sig = 0.1 * dx / 2.0               # psi_x, psi_y: w ~ N(0, 0.1^2)
 
-    w = np.zeros((nz + 1, ny, nx))
-    if nz > 1:
-        w[1:nz] = _rng(seed, STREAM_W).normal(0.0, 0.1, size=(nz - 1, ny, nx))
-        w[1:nz] -= w[1:nz].mean(axis=(1, 2), keepdims=True)
+    u = np.empty((nz, ny, nx), dtype=dtype)
+    v = np.empty((nz, ny, nx), dtype=dtype)
+    w = np.zeros((nz + 1, ny, nx), dtype=dtype)
+    theta = np.empty((nz, ny, nx), dtype=dtype)
+    q = np.empty((nz, ny, nx), dtype=dtype)
+    rho = np.empty((nz, ny, nx), dtype=dtype)
 
-    # irrotational part: (d2/dx2 + d2/dy2) chi = -(w_top - w_bottom)/dz per level
-    src = -(w[1:] - w[:-1]) / dz[:, None, None]
-    lam = (-(4.0 / dx ** 2) * np.sin(np.pi * np.arange(nx // 2 + 1) / nx) ** 2)[None, :] \
-        + (-(4.0 / dy ** 2) * np.sin(np.pi * np.fft.fftfreq(ny)) ** 2)[:, None]
-    lam[0, 0] = 1.0
-    chat = np.fft.rfft2(src) / lam[None]
-    chat[:, 0, 0] = 0.0
-    chi = np.fft.irfft2(chat, s=(ny, nx))
-    del chat, src
-    u += (np.roll(chi, -1, axis=2) - chi) / dx
-    v += (np.roll(chi, -1, axis=1) - chi) / dy
-    del chi
+    def dj_(a):                        # a[j] - a[j-1], periodic
+        return a - np.roll(a, 1, axis=0)
+
+    def di_(a):                        # a[i] - a[i-1], periodic
+        return a - np.roll(a, 1, axis=1)
 
     xc = (i + 0.5) * dx
     yc = (j + 0.5) * dy
     hpert = np.sin(2.0 * np.pi * yc / ly)[:, None] * np.sin(2.0 * np.pi * xc / lx)[None, :]
     vprof = np.exp(-((zc - 3000.0) / 3000.0) ** 2)
-    theta = 300.0 + 2.0 * vprof[:, None, None] * hpert[None]
-    q = np.minimum(0.02, np.exp(_rng(seed, STREAM_Q).normal(np.log(0.006), 0.5, size=(nz, ny, nx))))
-    rho = np.broadcast_to(1.2 * np.exp(-zc / 8000.0)[:, None, None], (nz, ny, nx)).copy()
 
-    theta_s = np.broadcast_to((301.0 + np.sin(2.0 * np.pi * j / ny))[:, None], (ny, nx)).copy()
-    q_s = np.full((ny, nx), 0.015)
-    f0 = 600.0 + 200.0 * np.cos(2.0 * np.pi * j / ny)[:, None] * np.sin(2.0 * np.pi * i / nx)[None, :]
-    ch = _rng(seed, STREAM_CH).uniform(0.005, 0.02, size=(ny, nx))
+    zero = np.zeros((ny, nx))
+    px_lo, py_lo = zero, zero          # psi_x, psi_y on the face below level k
+    rate = 0.0
+    for k in range(nz):
+        psi = g_psi.normal(0.0, sig_psi, size=(ny, nx)) + modes
+        if k + 1 < nz:
+            px_hi = g_px.normal(0.0, sig, size=(ny, nx))
+        else:
+            px_hi = zero
+        if k + 1 < nz:
+            py_hi = g_py.normal(0.0, sig, size=(ny, nx))
+        else:
+            py_hi = zero
+        uk = -dj_(psi) / dy - (py_hi - py_lo) / dz[k]
+        vk = di_(psi) / dx + (px_hi - px_lo) / dz[k]
+        if k + 1 < nz:
+            w[k + 1] = di_(py_hi) / dx - dj_(px_hi) / dy
+        u[k] = uk
+        v[k] = vk
+        theta[k] = 300.0 + 2.0 * vprof[k] * hpert
+        q[k] = np.minimum(0.02, np.exp(g_q.normal(np.log(0.006), 0.5, size=(ny, nx))))
+        rho[k] = 1.2 * np.exp(-zc[k] / 8000.0)
+        # summed Courant rate of the cells of this level
+        au = np.abs(u[k].astype(np.float64))
+        av = np.abs(v[k].astype(np.float64))
+        aw = np.maximum(np.abs(w[k].astype(np.float64)), np.abs(w[k + 1].astype(np.float64)))
+        lvl = (np.maximum(au, np.roll(au, 1, axis=1)) / dx + np.maximum(av, np.roll(av, 1, axis=0)) / dy
+               + aw / dz[k])
+        rate = max(rate, float(lvl.max()))
+        px_lo, py_lo = px_hi, py_hi
+
+    theta_s = np.broadcast_to((301.0 + np.sin(2.0 * np.pi * j / ny))[:, None], (ny, nx)).astype(dtype)
+    q_s = np.full((ny, nx), 0.015, dtype=dtype)
+    f0 = (600.0 + 200.0 * np.cos(2.0 * np.pi * j / ny)[:, None]
+          * np.sin(2.0 * np.pi * i / nx)[None, :]).astype(dtype)
+    ch = _rng(seed, STREAM_CH).uniform(0.005, 0.02, size=(ny, nx)).astype(dtype)
 
     if dt is None:
-        dt = cfl_dt(u, v, w, dx, dy, dz, cfl)
+        dt = cfl / rate
     return Inputs(nx=nx, ny=ny, nz=nz, dx=float(dx), dt=float(dt), dz=dz, u=u, v=v, w=w,
                   rho=rho, theta=theta, q=q, theta_s=theta_s, q_s=q_s, f0=f0, ch=ch, seed=seed)
 

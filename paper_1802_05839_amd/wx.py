@@ -1,0 +1,298 @@
+"""Python binding of ``libwx.so`` (include/wx.h): argument marshalling only.
+
+Every step of the weather step runs in the HIP library; this module allocates
+device buffers with torch (PyTorch is used for device memory and streams
+only), copies host arrays into the library's padded i-fastest layout, calls
+the C entry points and copies results back.  There is no fallback: if the
+library is missing or no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libwx.so")
+
+WX_OK, WX_E_INVAL, WX_E_HIP, WX_E_STATE, WX_E_UNSUPPORTED = 0, -1, -2, -3, -4
+WX_F32, WX_F64 = 0, 1
+WX_PHYS_OFF, WX_PHYS_PLAIN = 0, 1
+PARAMS = {"gamma4": 0, "k_min": 1, "mix_len": 2, "kappa_q": 3, "cp": 4, "t_dd": 5,
+          "theta_offset": 6, "mass_every": 7}
+FLAG_NAMES = ("nonfinite", "rho_le0", "fp64_columns", "reserved")
+HALO = 2
+
+EXPORTS = ("wx_create", "wx_destroy", "wx_last_error", "wx_workspace_bytes", "wx_set_param",
+           "wx_get_param", "wx_halo", "wx_step", "wx_physics", "wx_mass", "wx_profile_step",
+           "wx_copy_probe")
+
+
+class WxError(RuntimeError):
+    pass
+
+
+class _State(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("halo", ctypes.c_int32),
+        ("stride_j", ctypes.c_int64), ("stride_k", ctypes.c_int64), ("origin", ctypes.c_int64),
+        ("field_elems", ctypes.c_int64), ("wfield_elems", ctypes.c_int64),
+        ("dt", ctypes.c_double), ("dx", ctypes.c_double),
+        ("dtype", ctypes.c_int32), ("phys_mode", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+        ("rho", ctypes.c_void_p), ("theta", ctypes.c_void_p), ("q", ctypes.c_void_p),
+        ("u", ctypes.c_void_p), ("v", ctypes.c_void_p), ("w", ctypes.c_void_p),
+        ("theta_s", ctypes.c_void_p), ("q_s", ctypes.c_void_p), ("f0", ctypes.c_void_p),
+        ("ch", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("mass_out", ctypes.c_void_p), ("flags_out", ctypes.c_void_p),
+        ("impl", ctypes.c_void_p),
+    ]
+
+
+class _Tend(ctypes.Structure):
+    _fields_ = [("dtheta", ctypes.c_void_p), ("dq", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libwx.so and declare the C signatures (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise WxError(f"{path} is missing: build it with `python -m paper_1802_05839_amd._build`")
+    lib = ctypes.CDLL(path)
+    sp = ctypes.POINTER(_State)
+    lib.wx_create.restype = sp
+    lib.wx_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                              ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+    lib.wx_destroy.restype = None
+    lib.wx_destroy.argtypes = [sp]
+    lib.wx_last_error.restype = ctypes.c_char_p
+    lib.wx_last_error.argtypes = []
+    lib.wx_workspace_bytes.restype = ctypes.c_size_t
+    lib.wx_workspace_bytes.argtypes = [sp, ctypes.c_int]
+    lib.wx_set_param.argtypes = [sp, ctypes.c_int, ctypes.c_double]
+    lib.wx_get_param.argtypes = [sp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.wx_halo.argtypes = [sp, ctypes.c_void_p]
+    lib.wx_step.argtypes = [sp, ctypes.c_int, ctypes.c_void_p]
+    lib.wx_physics.argtypes = [sp, ctypes.POINTER(_Tend), ctypes.c_int]
+    lib.wx_mass.argtypes = [sp]
+    lib.wx_profile_step.argtypes = [sp, ctypes.c_int, ctypes.c_void_p,
+                                    ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+    lib.wx_copy_probe.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    for name in EXPORTS[4:]:
+        if name != "wx_workspace_bytes":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != WX_OK:
+        msg = _lib.wx_last_error().decode() if _lib is not None else ""
+        raise WxError(f"{what} failed ({rc}): {msg}")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise WxError("no GPU visible: the wx library runs on an MI355X only")
+    return torch
+
+
+def _stream_ptr(stream=None) -> int:
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+class State:
+    """A device-resident weather state borrowed by libwx (buffers owned here)."""
+
+    def __init__(self, nx: int, ny: int, nz: int, dt: float, dx: float, dz, dtype: str = "f32",
+                 phys_mode: int = WX_PHYS_PLAIN, device: str = "cuda:0"):
+        torch = _torch()
+        lib = load_library()
+        self.lib = lib
+        dz = np.ascontiguousarray(dz, dtype=np.float64)
+        if dz.shape != (nz,):
+            raise WxError("dz must have nz entries")
+        p = lib.wx_create(nx, ny, nz, float(dt), float(dx),
+                          dz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        if not p:
+            raise WxError("wx_create failed: " + lib.wx_last_error().decode())
+        self._p = p
+        s = p.contents
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.dt, self.dx, self.dz = float(dt), float(dx), dz.copy()
+        self.sj, self.sk = int(s.stride_j), int(s.stride_k)
+        self.field_elems, self.wfield_elems = int(s.field_elems), int(s.wfield_elems)
+        self.dtype = dtype
+        self.tdt = torch.float32 if dtype == "f32" else torch.float64
+        self.np_dtype = np.float32 if dtype == "f32" else np.float64
+        self.device = torch.device(device)
+        s.dtype = WX_F32 if dtype == "f32" else WX_F64
+        s.phys_mode = phys_mode
+        dev = self.device
+
+        def alloc(n):
+            return torch.zeros(n, dtype=self.tdt, device=dev)
+
+        self.t = {name: alloc(self.field_elems) for name in ("rho", "theta", "q", "u", "v")}
+        self.t["w"] = alloc(self.wfield_elems)
+        for name in ("theta_s", "q_s", "f0", "ch"):
+            self.t[name] = alloc(nx * ny)
+        wsb = int(lib.wx_workspace_bytes(p, s.dtype))
+        self.t["workspace"] = torch.zeros(wsb, dtype=torch.uint8, device=dev)
+        self.t["mass_out"] = torch.zeros(6, dtype=torch.float64, device=dev)
+        self.t["flags_out"] = torch.zeros(4, dtype=torch.int32, device=dev)
+        for name, ten in self.t.items():
+            setattr(s, name, ten.data_ptr())
+        self.theta_offset = 0.0
+
+    # ---- layout helpers -------------------------------------------------
+    def _padded(self, t, planes):
+        return t.view(planes, self.ny + 2 * HALO, self.sj)
+
+    def interior(self, name: str):
+        planes = self.nz + 1 if name == "w" else self.nz
+        return self._padded(self.t[name], planes)[:, HALO:HALO + self.ny, HALO:HALO + self.nx]
+
+    # ---- parameters ------------------------------------------------------
+    def set_param(self, name: str, value: float) -> None:
+        _check(self.lib.wx_set_param(self._p, PARAMS[name], float(value)), f"wx_set_param({name})")
+        if name == "theta_offset":
+            self.theta_offset = float(value)
+
+    def get_param(self, name: str) -> float:
+        out = ctypes.c_double()
+        _check(self.lib.wx_get_param(self._p, PARAMS[name], ctypes.byref(out)), "wx_get_param")
+        return out.value
+
+    # ---- data movement ---------------------------------------------------
+    def upload(self, inp, theta_offset: Optional[float] = None) -> None:
+        """Copy a host problem into the device buffers (halo filled by the library).
+
+        theta (and theta_s) are stored as theta - theta_offset; the default is
+        300 K for FP32 state and 0 for FP64.
+        """
+        torch = _torch()
+        if theta_offset is None:
+            theta_offset = 300.0 if self.dtype == "f32" else 0.0
+        self.set_param("theta_offset", theta_offset)
+        src = {"rho": inp.rho, "theta": inp.theta - theta_offset, "q": inp.q, "u": inp.u,
+               "v": inp.v, "w": inp.w}
+        for name, arr in src.items():
+            self.interior(name).copy_(torch.from_numpy(np.ascontiguousarray(arr, dtype=self.np_dtype)))
+        two = {"theta_s": inp.theta_s - theta_offset, "q_s": inp.q_s, "f0": inp.f0, "ch": inp.ch}
+        for name, arr in two.items():
+            self.t[name].copy_(torch.from_numpy(np.ascontiguousarray(arr, dtype=self.np_dtype).ravel()))
+        self.halo()
+
+    def download(self, names=("rho", "theta", "q")) -> Dict[str, np.ndarray]:
+        """Interior of the state as float64 arrays (theta with the offset added back)."""
+        torch = _torch()
+        torch.cuda.synchronize(self.device)
+        out = {}
+        for name in names:
+            a = self.interior(name).cpu().numpy().astype(np.float64)
+            if name == "theta":
+                a = a + self.theta_offset
+            out[name] = a
+        return out
+
+    def download_raw(self, name: str) -> np.ndarray:
+        """Whole padded buffer (halo included) in storage precision."""
+        torch = _torch()
+        torch.cuda.synchronize(self.device)
+        planes = self.nz + 1 if name == "w" else self.nz
+        return self._padded(self.t[name], planes).cpu().numpy()
+
+    # ---- entry points ----------------------------------------------------
+    def halo(self, stream=None) -> None:
+        _check(self.lib.wx_halo(self._p, _stream_ptr(stream)), "wx_halo")
+
+    def step(self, nsteps: int, stream=None) -> None:
+        _check(self.lib.wx_step(self._p, int(nsteps), _stream_ptr(stream)), "wx_step")
+
+    def set_phys_mode(self, mode: int) -> None:
+        self._p.contents.phys_mode = int(mode)
+
+    def tendencies(self, stream=None):
+        """Plain-physics tendencies (dtheta/dt, dq/dt) of the current state, (nz, ny, nx) float64."""
+        torch = _torch()
+        s = self._p.contents
+        s.stream = _stream_ptr(stream)
+        tt = torch.zeros(self.nx * self.ny * self.nz, dtype=self.tdt, device=self.device)
+        tq = torch.zeros_like(tt)
+        tend = _Tend(tt.data_ptr(), tq.data_ptr())
+        _check(self.lib.wx_physics(self._p, ctypes.byref(tend), WX_PHYS_PLAIN), "wx_physics")
+        torch.cuda.synchronize(self.device)
+        shp = (self.nz, self.ny, self.nx)
+        return (tt.cpu().numpy().astype(np.float64).reshape(shp),
+                tq.cpu().numpy().astype(np.float64).reshape(shp))
+
+    def mass(self, compute: bool = False, stream=None) -> np.ndarray:
+        """(M_rho, M_theta, M_q) as sum + compensation; ``compute`` runs wx_mass first."""
+        torch = _torch()
+        if compute:
+            self._p.contents.stream = _stream_ptr(stream)
+            _check(self.lib.wx_mass(self._p), "wx_mass")
+        torch.cuda.synchronize(self.device)
+        m = self.t["mass_out"].cpu().numpy()
+        return np.array([m[0] + m[1], m[2] + m[3], m[4] + m[5]])
+
+    def mass_raw(self) -> np.ndarray:
+        torch = _torch()
+        torch.cuda.synchronize(self.device)
+        return self.t["mass_out"].cpu().numpy().copy()
+
+    def flags(self) -> Dict[str, int]:
+        torch = _torch()
+        torch.cuda.synchronize(self.device)
+        f = self.t["flags_out"].cpu().numpy()
+        return {n: int(v) for n, v in zip(FLAG_NAMES, f)}
+
+    def profile(self, nsteps: int, stream=None) -> np.ndarray:
+        """Average ms per launch: halo, stage 1, stage 2, stage 3, physics, mass final."""
+        out = (ctypes.c_double * 6)()
+        _check(self.lib.wx_profile_step(self._p, int(nsteps), _stream_ptr(stream), out, 6),
+               "wx_profile_step")
+        return np.array(out[:])
+
+    def close(self) -> None:
+        if getattr(self, "_p", None):
+            _torch().cuda.synchronize(self.device)
+            self.lib.wx_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_p", None):
+                self.lib.wx_destroy(self._p)
+                self._p = None
+        except Exception:
+            pass
+
+
+def copy_probe(dst, src, stream=None) -> None:
+    """Run the library's plain copy kernel from one torch tensor to another."""
+    lib = load_library()
+    nbytes = src.numel() * src.element_size()
+    _check(lib.wx_copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, _stream_ptr(stream)),
+           "wx_copy_probe")
+
+
+def state_from_inputs(inp, dtype: str = "f32", phys_mode: int = WX_PHYS_PLAIN,
+                      theta_offset: Optional[float] = None, device: str = "cuda:0") -> State:
+    st = State(inp.nx, inp.ny, inp.nz, inp.dt, inp.dx, inp.dz, dtype=dtype, phys_mode=phys_mode,
+               device=device)
+    st.upload(inp, theta_offset=theta_offset)
+    return st

@@ -1,0 +1,107 @@
+"""The C ABI: exports and host-side validation (CPU only, no kernel launches)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1802_05839_amd import wx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+           if f.endswith(".h")]
+
+
+def _declared():
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b(wx_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(wx.LIB_PATH):
+        pytest.skip("libwx.so is not built (run __graft_entry__.build())")
+    return wx.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    declared = _declared()
+    assert {"wx_create", "wx_step", "wx_physics", "wx_destroy"} <= declared
+    missing = [n for n in sorted(declared) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(wx.EXPORTS) <= declared
+
+
+def _dz(nz):
+    return (ctypes.c_double * nz)(*np.geomspace(50.0, 1000.0, nz))
+
+
+def test_create_validates_and_reports_layout(lib):
+    p = lib.wx_create(5, 4, 3, 2.0, 100.0, _dz(3))
+    assert p
+    s = p.contents
+    assert (s.nx, s.ny, s.nz, s.halo) == (5, 4, 3, 2)
+    assert s.stride_j % 64 == 0 and s.stride_j >= 9
+    assert s.stride_k == s.stride_j * 8
+    assert s.origin == 2 + 2 * s.stride_j
+    assert s.field_elems == 3 * s.stride_k and s.wfield_elems == 4 * s.stride_k
+    assert lib.wx_workspace_bytes(p, wx.WX_F32) < lib.wx_workspace_bytes(p, wx.WX_F64)
+    assert lib.wx_workspace_bytes(p, 7) == 0
+    lib.wx_destroy(p)
+    for bad in ((3, 4, 3), (4, 3, 3), (4, 4, 2)):
+        assert not lib.wx_create(*bad, 2.0, 100.0, _dz(3))
+        assert b"outside" in lib.wx_last_error()
+    assert not lib.wx_create(8, 8, 3, -1.0, 100.0, _dz(3))
+    dz = _dz(3)
+    dz[1] = 0.0
+    assert not lib.wx_create(8, 8, 3, 1.0, 100.0, dz)
+    assert b"dz[1]" in lib.wx_last_error()
+
+
+def test_params_defaults_match_oracle(lib):
+    from oracle.params import DEFAULT
+    p = lib.wx_create(8, 8, 4, 2.0, 100.0, _dz(4))
+    v = ctypes.c_double()
+    expect = {"gamma4": DEFAULT.gamma4, "k_min": DEFAULT.k_min, "mix_len": DEFAULT.mix_len,
+              "kappa_q": DEFAULT.kappa_q, "cp": DEFAULT.cp, "t_dd": DEFAULT.t_dd,
+              "theta_offset": 0.0, "mass_every": 1.0}
+    for name, val in expect.items():
+        assert lib.wx_get_param(p, wx.PARAMS[name], ctypes.byref(v)) == wx.WX_OK
+        assert v.value == val, name
+    assert lib.wx_set_param(p, wx.PARAMS["cp"], 0.0) == wx.WX_E_INVAL
+    assert lib.wx_set_param(p, wx.PARAMS["k_min"], -1.0) == wx.WX_E_INVAL
+    assert lib.wx_set_param(p, wx.PARAMS["mass_every"], 1.5) == wx.WX_E_INVAL
+    assert lib.wx_set_param(p, 99, 1.0) == wx.WX_E_INVAL
+    assert lib.wx_set_param(p, wx.PARAMS["theta_offset"], -300.0) == wx.WX_OK
+    lib.wx_destroy(p)
+
+
+def test_step_rejects_incomplete_state_before_any_launch(lib):
+    p = lib.wx_create(8, 8, 4, 2.0, 100.0, _dz(4))
+    assert lib.wx_step(p, 1, None) == wx.WX_E_STATE
+    assert b"rho" in lib.wx_last_error()
+    s = p.contents
+    for name in ("rho", "theta", "q", "u", "v", "w", "workspace", "mass_out", "flags_out",
+                 "theta_s", "q_s", "f0", "ch"):
+        setattr(s, name, 4096)          # never dereferenced: validation fails first
+    s.rho = 4100                        # misaligned
+    assert lib.wx_step(p, 1, None) == wx.WX_E_INVAL
+    assert b"aligned" in lib.wx_last_error()
+    s.rho = 4096
+    s.phys_mode = 9
+    assert lib.wx_step(p, 1, None) == wx.WX_E_UNSUPPORTED
+    s.phys_mode = wx.WX_PHYS_PLAIN
+    s.dtype = 5
+    assert lib.wx_step(p, 1, None) == wx.WX_E_INVAL
+    s.dtype = wx.WX_F32
+    assert lib.wx_step(p, -1, None) == wx.WX_E_INVAL
+    assert lib.wx_physics(p, None, wx.WX_PHYS_PLAIN) == wx.WX_E_INVAL
+    assert lib.wx_physics(p, None, 7) == wx.WX_E_UNSUPPORTED
+    assert lib.wx_copy_probe(None, None, 16, None) == wx.WX_E_INVAL
+    lib.wx_destroy(p)

@@ -1,0 +1,281 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 state, normalized max error max|gpu - oracle| / max|oracle|
+<= 1e-12 after 10 steps; FP32 state <= 1e-5 per field after one step from
+identical FP32-representable inputs, with theta measured as theta - 300.
+Bitwise checks: constant fields, uniform states, translation, run-to-run.
+"""
+import hashlib
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import dycore, physics, step
+from oracle.mass import mass_sums
+from oracle.params import DEFAULT
+from paper_1802_05839_amd import inputs, wx
+from tests._util import nmax, uniform_inputs
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run_gpu(inp, nsteps, dtype="f64", phys=wx.WX_PHYS_PLAIN, params=None, theta_offset=None):
+    st = wx.state_from_inputs(inp, dtype=dtype, phys_mode=phys, theta_offset=theta_offset)
+    for k, v in (params or {}).items():
+        st.set_param(k, v)
+    st.step(nsteps)
+    out = st.download()
+    out["flags"] = st.flags()
+    out["mass"] = st.mass()
+    out["mass_raw"] = st.mass_raw()
+    st.close()
+    return out
+
+
+def _oracle(inp, nsteps, physics_on=True, p=DEFAULT):
+    return step.run(inp, nsteps, p=p, physics_on=physics_on)
+
+
+def _compare(gpu, ref, tol, theta_ref=0.0):
+    errs = {"rho": nmax(gpu["rho"], ref.rho),
+            "theta": nmax(gpu["theta"] - theta_ref, ref.theta - theta_ref),
+            "q": nmax(gpu["q"], ref.q)}
+    for k, e in errs.items():
+        assert e <= tol, (k, errs)
+    return errs
+
+
+def test_tiny_fp64_ten_steps_matches_oracle():
+    _say("case: 64x64x16 FP64 10 steps")
+    inp = inputs.generate_config("tiny")
+    gpu = _run_gpu(inp, 10, "f64")
+    ref = _oracle(inp, 10)
+    errs = _compare(gpu, ref, FP64_TOL)
+    _say(f"errors {errs}")
+    assert gpu["flags"]["nonfinite"] == 0 and gpu["flags"]["rho_le0"] == 0
+    # mass sums: the GPU's compensated sums of its own state equal the exactly
+    # rounded sums of that state, and agree with the oracle's state
+    m_own = mass_sums(gpu["rho"], gpu["theta"], gpu["q"], inp.dx, inp.dx, inp.dz)
+    np.testing.assert_allclose(gpu["mass"], m_own, rtol=1e-15)
+    np.testing.assert_allclose(gpu["mass"], step.masses(ref, inp), rtol=1e-12)
+
+
+def test_tiny_fp64_dycore_only_matches_oracle():
+    _say("case: 64x64x16 FP64 dycore only 10 steps")
+    inp = inputs.generate_config("tiny")
+    gpu = _run_gpu(inp, 10, "f64", phys=wx.WX_PHYS_OFF)
+    ref = _oracle(inp, 10, physics_on=False)
+    _compare(gpu, ref, FP64_TOL)
+
+
+def test_tiny_fp32_one_step_matches_oracle():
+    _say("case: 64x64x16 FP32 1 step")
+    inp = inputs.generate_config("tiny")
+    # identical FP32-representable inputs on both sides (theta stored as theta - 300)
+    inp32 = inp.astype(np.float32)
+    inp32.theta = (inp.theta - 300.0).astype(np.float32).astype(np.float64) + 300.0
+    inp32.theta_s = (inp.theta_s - 300.0).astype(np.float32).astype(np.float64) + 300.0
+    gpu = _run_gpu(inp32, 1, "f32", theta_offset=300.0)
+    ref = _oracle(inp32, 1)
+    errs = _compare(gpu, ref, FP32_TOL, theta_ref=300.0)
+    _say(f"fp32 errors {errs}")
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(4, 4, 3), (67, 37, 5), (130, 9, 7), (65, 5, 4)])
+def test_ragged_sizes_fp64(nx, ny, nz):
+    _say(f"case: ragged {nx}x{ny}x{nz} FP64 3 steps")
+    inp = inputs.generate(nx, ny, nz, seed=21)
+    gpu = _run_gpu(inp, 3, "f64")
+    ref = _oracle(inp, 3)
+    _compare(gpu, ref, FP64_TOL)
+
+
+def test_ragged_fp32():
+    _say("case: ragged 97x45x11 FP32 1 step")
+    inp = inputs.generate(97, 45, 11, seed=22)
+    inp32 = inp.astype(np.float32)
+    inp32.theta = (inp.theta - 300.0).astype(np.float32).astype(np.float64) + 300.0
+    inp32.theta_s = (inp.theta_s - 300.0).astype(np.float32).astype(np.float64) + 300.0
+    gpu = _run_gpu(inp32, 1, "f32", theta_offset=300.0)
+    ref = _oracle(inp32, 1)
+    _compare(gpu, ref, FP32_TOL, theta_ref=300.0)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_constant_field_bitwise(dtype):
+    _say(f"case: constant field {dtype}")
+    inp = inputs.generate(40, 24, 9, seed=23)
+    c1, c2 = 287.25, 0.0075
+    inp.theta[:] = c1
+    inp.q[:] = c2
+    inp.theta_s[:] = c1
+    inp.q_s[:] = c2
+    inp.f0[:] = 0.0
+    st = wx.state_from_inputs(inp, dtype=dtype, theta_offset=0.0)
+    st.step(3)
+    th = st.download_raw("theta")[:, 2:-2, 2:2 + inp.nx]
+    q = st.download_raw("q")[:, 2:-2, 2:2 + inp.nx]
+    st.close()
+    npd = np.float32 if dtype == "f32" else np.float64
+    assert np.all(th == npd(c1)) and np.all(q == npd(c2))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_uniform_state_bitwise(dtype):
+    _say(f"case: uniform state {dtype}")
+    inp = uniform_inputs(nx=70, ny=11, nz=6, u0=7.5, v0=-3.25, rho0=1.0625, theta0=301.5, q0=0.004)
+    st = wx.state_from_inputs(inp, dtype=dtype, theta_offset=0.0)
+    st.step(2)
+    npd = np.float32 if dtype == "f32" else np.float64
+    for name, val in (("rho", 1.0625), ("theta", 301.5), ("q", 0.004)):
+        a = st.download_raw(name)[:, 2:2 + inp.ny, 2:2 + inp.nx]
+        assert np.all(a == npd(val)), name
+    st.close()
+
+
+def test_translation_bitwise():
+    _say("case: translation invariance FP32")
+    inp = inputs.generate(72, 40, 8, seed=24)
+    p, qq = 13, 7
+    sh = inp.copy()
+    for name, a in sh.fields().items():
+        setattr(sh, name, np.roll(np.roll(a, qq, axis=-2), p, axis=-1))
+    o1 = _run_gpu(inp, 2, "f32")
+    o2 = _run_gpu(sh, 2, "f32")
+    for name in ("rho", "theta", "q"):
+        np.testing.assert_array_equal(np.roll(np.roll(o1[name], qq, axis=-2), p, axis=-1), o2[name])
+
+
+def test_run_to_run_bitwise():
+    _say("case: reproducibility FP32 5 steps x2")
+    inp = inputs.generate(150, 70, 12, seed=25)
+    digests = []
+    for _ in range(2):
+        st = wx.state_from_inputs(inp, dtype="f32")
+        st.step(5)
+        h = hashlib.sha256()
+        for name in ("rho", "theta", "q"):
+            h.update(st.download_raw(name).tobytes())
+        h.update(st.mass_raw().tobytes())
+        digests.append(h.hexdigest())
+        st.close()
+    assert digests[0] == digests[1]
+
+
+def test_halo_ring_is_periodic_after_step():
+    _say("case: halo ring FP64")
+    inp = inputs.generate(20, 12, 5, seed=26)
+    st = wx.state_from_inputs(inp, dtype="f64")
+    st.step(2)
+    for name in ("rho", "theta", "q"):
+        a = st.download_raw(name)[:, :, :inp.nx + 4]
+        inner = a[:, 2:-2, 2:-2]
+        full = np.pad(inner, ((0, 0), (2, 2), (2, 2)), mode="wrap")
+        np.testing.assert_array_equal(a, full)
+    st.close()
+
+
+def test_tendencies_match_oracle():
+    _say("case: wx_physics tendencies FP64 and FP32")
+    inp = inputs.generate(50, 30, 16, seed=27)
+    ref = physics.column_physics(inp.rho, inp.theta, inp.q, inp.u, inp.v, inp.theta_s, inp.q_s,
+                                 inp.f0, inp.ch, inp.dz, inp.dt)
+    st = wx.state_from_inputs(inp, dtype="f64")
+    tt, tq = st.tendencies()
+    st.close()
+    assert nmax(tt, ref.t_theta) <= FP64_TOL and nmax(tq, ref.t_q) <= FP64_TOL
+    inp32 = inp.astype(np.float32)
+    inp32.theta = (inp.theta - 300.0).astype(np.float32).astype(np.float64) + 300.0
+    inp32.theta_s = (inp.theta_s - 300.0).astype(np.float32).astype(np.float64) + 300.0
+    ref32 = physics.column_physics(inp32.rho, inp32.theta, inp32.q, inp32.u, inp32.v, inp32.theta_s,
+                                   inp32.q_s, inp32.f0, inp32.ch, inp32.dz, inp32.dt)
+    st = wx.state_from_inputs(inp32, dtype="f32", theta_offset=300.0)
+    tt, tq = st.tendencies()
+    st.close()
+    e = (nmax(tt, ref32.t_theta), nmax(tq, ref32.t_q))
+    _say(f"fp32 tendency errors {e}")
+    assert max(e) <= 1e-4
+
+
+@pytest.mark.parametrize("tdd", [0.0, 1e30])
+def test_fp64_elimination_switch(tdd):
+    # T_dd = 0 sends every column through the FP64 forward elimination,
+    # T_dd = 1e30 none; both agree with the oracle and the counter says which.
+    _say(f"case: FP64 elimination switch tdd={tdd}")
+    inp = inputs.generate(70, 20, 12, seed=28)
+    inp.dt = inp.dt * 40.0          # stiff columns: large alpha / m
+    inp32 = inp.astype(np.float32)
+    inp32.theta = (inp.theta - 300.0).astype(np.float32).astype(np.float64) + 300.0
+    inp32.theta_s = (inp.theta_s - 300.0).astype(np.float32).astype(np.float64) + 300.0
+    ref = physics.column_physics(inp32.rho, inp32.theta, inp32.q, inp32.u, inp32.v, inp32.theta_s,
+                                 inp32.q_s, inp32.f0, inp32.ch, inp32.dz, inp32.dt)
+    st = wx.state_from_inputs(inp32, dtype="f32", theta_offset=300.0)
+    st.set_param("t_dd", tdd)
+    st.t["flags_out"].zero_()
+    tt, tq = st.tendencies()
+    flags = st.flags()
+    st.close()
+    ncol = inp.nx * inp.ny
+    assert flags["fp64_columns"] == (ncol if tdd == 0.0 else 0)
+    e = (nmax(tt, ref.t_theta), nmax(tq, ref.t_q))
+    _say(f"tdd={tdd} tendency errors {e} ratio max {ref.ratio.max():.3g}")
+    assert max(e) <= 1e-4
+
+
+def test_fp64_column_count_matches_dominance_ratio():
+    _say("case: FP64 column count at default T_dd on stiff columns")
+    inp = inputs.generate(64, 32, 16, seed=29)
+    inp.dt = inp.dt * 25.0
+    ref = physics.column_physics(inp.rho, inp.theta, inp.q, inp.u, inp.v, inp.theta_s, inp.q_s,
+                                 inp.f0, inp.ch, inp.dz, inp.dt)
+    lo = int(np.sum(ref.ratio > DEFAULT.t_dd * (1 + 1e-6)))
+    hi = int(np.sum(ref.ratio > DEFAULT.t_dd * (1 - 1e-6)))
+    assert 0 < lo < inp.nx * inp.ny
+    st = wx.state_from_inputs(inp, dtype="f64")
+    st.t["flags_out"].zero_()
+    st.tendencies()
+    n = st.flags()["fp64_columns"]
+    st.close()
+    assert lo <= n <= hi
+
+
+def test_mass_conservation_fp64_and_fp32_drift():
+    _say("case: mass conservation FP64 10 steps, FP32 drift")
+    inp = inputs.generate_config("tiny")
+    inp.ch[:] = 0.0
+    inp.f0[:] = 0.0
+    m0 = step.masses(dycore.State(inp.rho, inp.theta, inp.q), inp)
+    gpu = _run_gpu(inp, 10, "f64")
+    rel = np.abs(gpu["mass"] - m0) / m0
+    assert np.all(rel <= 1e-12), rel
+    gpu32 = _run_gpu(inp, 10, "f32")
+    rel32 = np.abs(gpu32["mass"] - m0) / m0
+    _say(f"FP32 relative mass drift after 10 steps: {rel32}")
+    assert np.all(rel32 <= 1e-5)
+
+
+def test_nonfinite_input_is_flagged():
+    _say("case: NaN flag")
+    inp = inputs.generate(32, 16, 6, seed=30)
+    inp.q[2, 5, 7] = np.nan
+    gpu = _run_gpu(inp, 1, "f32")
+    assert gpu["flags"]["nonfinite"] > 0
+
+
+def test_wx_mass_entry_point():
+    _say("case: wx_mass")
+    inp = inputs.generate(33, 17, 7, seed=31)
+    st = wx.state_from_inputs(inp, dtype="f64")
+    m = st.mass(compute=True)
+    st.close()
+    np.testing.assert_allclose(m, mass_sums(inp.rho, inp.theta, inp.q, inp.dx, inp.dx, inp.dz),
+                               rtol=1e-15)
