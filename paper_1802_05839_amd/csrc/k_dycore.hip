@@ -54,8 +54,8 @@ __device__ __forceinline__ T face3(T a, T b, T c) {
 }
 
 template <typename T>
-__global__ void k_halo(T *f0, T *f1, T *f2, T *f3, T *f4, int nx, int ny, long long sj,
-                       long long sk, long long origin) {
+__global__ void k_halo(T *f0, T *f1, T *f2, T *f3, T *f4, int nx, int ny, unsigned sj,
+                       unsigned sk, unsigned origin) {
   const int ring = 4 * (nx + 4) + 4 * ny;
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= ring) return;
@@ -72,8 +72,8 @@ __global__ void k_halo(T *f0, T *f1, T *f2, T *f3, T *f4, int nx, int ny, long l
     i = c < 2 ? c - 2 : nx + c - 2;
   }
   const int si = (i + nx) % nx, sjj = (j + ny) % ny;
-  const long long pl = (long long)blockIdx.y * sk + origin;
-  f[pl + i + j * sj] = f[pl + si + sjj * sj];
+  const unsigned pl = blockIdx.y * sk + origin;
+  stg(f, pl + unsigned(i + j * int(sj)), ldg(f, pl + unsigned(si + sjj * int(sj))));
 }
 
 template <typename T, int STAGE>
@@ -87,27 +87,27 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<T> a) {
   const int i0 = (L % a.nbx) * BX, j0 = (L / a.nbx) * BY;
   const int i = i0 + tx, j = j0 + ty;
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-  const long long sj = a.g.sj, sk = a.g.sk;
+  const unsigned sj = a.g.sj, sk = a.g.sk;
   const bool active = (i < nx) && (j < ny);
 
   // This thread's share of the (BX+4) x (BY+4) plane tile.
-  long long toff[NLOAD];
+  unsigned toff[NLOAD];
   bool tok[NLOAD];
 #pragma unroll
   for (int n = 0; n < NLOAD; ++n) {
     const int e = tid + n * NT;
     const int gi = i0 - 2 + e % TW, gj = j0 - 2 + e / TW;
     tok[n] = (e < TN) && (gi < nx + 2) && (gj < ny + 2);
-    toff[n] = a.g.origin + gi + (long long)gj * sj;
+    toff[n] = unsigned(int(a.g.origin) + gi + gj * int(sj));
   }
   T pr[NLOAD], pt[NLOAD], pq[NLOAD];
   auto fetch = [&](int p) {
-    const long long base = (long long)p * sk;
+    const unsigned base = unsigned(p) * sk;
 #pragma unroll
     for (int n = 0; n < NLOAD; ++n) {
-      pr[n] = tok[n] ? a.in_r[base + toff[n]] : T(0);
-      pt[n] = tok[n] ? a.in_t[base + toff[n]] : T(0);
-      pq[n] = tok[n] ? a.in_q[base + toff[n]] : T(0);
+      pr[n] = tok[n] ? ldg(a.in_r, base + toff[n]) : T(0);
+      pt[n] = tok[n] ? ldg(a.in_t, base + toff[n]) : T(0);
+      pq[n] = tok[n] ? ldg(a.in_q, base + toff[n]) : T(0);
     }
   };
   auto stash = [&](int buf) {
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<T> a) {
   // flux and face values at the face below the current level
   T fzb = 0, tfb = 0, qfb = 0;
 
-  const long long col = a.g.origin + i + (long long)j * sj;
+  const unsigned col = a.g.origin + unsigned(i) + unsigned(j) * sj;
   T wb = 0;
   const T h = a.h, rdx = a.rdx, k4 = a.k4;
   const T r2 = rdx * rdx;
@@ -157,9 +157,9 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<T> a) {
       const T *R = s_r[b] + c0;
       const T *Th = s_t[b] + c0;
       const T *Q = s_q[b] + c0;
-      const long long gc = col + (long long)k * sk;
-      const T uE = a.u[gc], uW = a.u[gc - 1], vN = a.v[gc], vS = a.v[gc - sj];
-      const T wt = (k + 1 < nz) ? a.w[gc + sk] : T(0);
+      const unsigned gc = col + unsigned(k) * sk;
+      const T uE = ldg(a.u, gc), uW = ldg(a.u, gc - 1), vN = ldg(a.v, gc), vS = ldg(a.v, gc - sj);
+      const T wt = (k + 1 < nz) ? ldg(a.w, gc + sk) : T(0);
       const T rdz = a.rdz[k];
 
       // --- density: face values and mass fluxes
@@ -197,12 +197,12 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<T> a) {
         bt = t0;
         bq = q0;
       } else {
-        br = a.bs_r[gc];
-        bt = a.bs_t[gc];
-        bq = a.bs_q[gc];
+        br = ldg(a.bs_r, gc);
+        bt = ldg(a.bs_t, gc);
+        bq = ldg(a.bs_q, gc);
       }
       const T rnew = br - h * div;
-      const T rinv = T(1) / rnew;
+      const T rinv = fast_rcp(rnew);
 
       // density at the four horizontal faces (biharmonic weighting)
       const T rhE = (r0 + rxp1) * T(0.5), rhW = (rxm1 + r0) * T(0.5);
@@ -236,24 +236,24 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<T> a) {
       const T qnew = tracer(Q, q0, qm1, qp1, qp2, qfT, qfb, bq);
 
       // store the cell and its periodic images in the halo ring
-      a.out_r[gc] = rnew;
-      a.out_t[gc] = tnew;
-      a.out_q[gc] = qnew;
-      const long long di = i < 2 ? nx : (i >= nx - 2 ? -nx : 0);
-      const long long dj = j < 2 ? (long long)ny * sj : (j >= ny - 2 ? -(long long)ny * sj : 0);
+      stg(a.out_r, gc, rnew);
+      stg(a.out_t, gc, tnew);
+      stg(a.out_q, gc, qnew);
+      const int di = i < 2 ? nx : (i >= nx - 2 ? -nx : 0);
+      const int dj = j < 2 ? ny * int(sj) : (j >= ny - 2 ? -ny * int(sj) : 0);
       if (di != 0) {
-        a.out_r[gc + di] = rnew;
-        a.out_t[gc + di] = tnew;
-        a.out_q[gc + di] = qnew;
+        stg(a.out_r, gc + di, rnew);
+        stg(a.out_t, gc + di, tnew);
+        stg(a.out_q, gc + di, qnew);
       }
       if (dj != 0) {
-        a.out_r[gc + dj] = rnew;
-        a.out_t[gc + dj] = tnew;
-        a.out_q[gc + dj] = qnew;
+        stg(a.out_r, gc + dj, rnew);
+        stg(a.out_t, gc + dj, tnew);
+        stg(a.out_q, gc + dj, qnew);
         if (di != 0) {
-          a.out_r[gc + dj + di] = rnew;
-          a.out_t[gc + dj + di] = tnew;
-          a.out_q[gc + dj + di] = qnew;
+          stg(a.out_r, gc + dj + di, rnew);
+          stg(a.out_t, gc + dj + di, tnew);
+          stg(a.out_q, gc + dj + di, qnew);
         }
       }
       fzb = fzT;

@@ -71,43 +71,44 @@ template <typename E>
 struct GlobalStore {
   E *p;
   int nz;
-  long long ncol, col;
-  __device__ __forceinline__ E &at(int v, int k) const { return p[((long long)v * nz + k) * ncol + col]; }
+  unsigned ncol, col;
+  __device__ __forceinline__ E &at(int v, int k) const { return ref(p, unsigned(v * nz + k) * ncol + col); }
 };
 
 template <typename T>
 struct Column {
   const PhysArgs<T> &a;
-  long long g0;     // element offset of level 0 of this column
+  unsigned g0;      // element offset of level 0 of this column
   int col;          // i + nx j
-  __device__ __forceinline__ long long at(int k) const { return g0 + (long long)k * a.g.sk; }
+  __device__ __forceinline__ unsigned at(int k) const { return g0 + unsigned(k) * a.g.sk; }
 };
 
 // Forward elimination (bottom to top) in precision E.  Returns max_k r_k.
-template <typename T, typename E, typename S>
-__device__ T upward(const Column<T> &c, const S &st) {
+template <typename T, typename E, int NZC, typename S>
+__device__ __forceinline__ T upward(const Column<T> &c, const S &st) {
   const PhysArgs<T> &a = c.a;
-  const int nz = a.g.nz;
-  const long long sj = a.g.sj;
+  const int nz = NZC > 0 ? NZC : a.g.nz;
+  const unsigned sj = a.g.sj;
   const E dt = E(a.dt), kmin = E(a.kmin), l2 = E(a.l2);
-  long long g = c.at(0);
-  E r0 = E(a.rho[g]), t0 = E(a.th[g]), q0 = E(a.q[g]);
-  E ub0 = (E(a.u[g - 1]) + E(a.u[g])) * E(0.5);
-  E vb0 = (E(a.v[g - sj]) + E(a.v[g])) * E(0.5);
+  unsigned g = c.at(0);
+  E r0 = E(ldg(a.rho, g)), t0 = E(ldg(a.th, g)), q0 = E(ldg(a.q, g));
+  E ub0 = (E(ldg(a.u, g - 1)) + E(ldg(a.u, g))) * E(0.5);
+  E vb0 = (E(ldg(a.v, g - sj)) + E(ldg(a.v, g))) * E(0.5);
   const E beta = dt * r0 * E(a.ch[c.col]);
   const E ths = E(a.th_s[c.col]), qs = E(a.q_s[c.col]);
   E alo = 0, tm1 = t0, qm1 = q0;
   E cp = 0, dtp = 0, dqp = 0;
   T rmax = T(0);
+#pragma unroll
   for (int k = 0; k < nz; ++k) {
     E ahi = 0, r1 = 0, t1 = t0, q1 = q0, ub1 = 0, vb1 = 0;
     if (k + 1 < nz) {
       g = c.at(k + 1);
-      r1 = E(a.rho[g]);
-      t1 = E(a.th[g]);
-      q1 = E(a.q[g]);
-      ub1 = (E(a.u[g - 1]) + E(a.u[g])) * E(0.5);
-      vb1 = (E(a.v[g - sj]) + E(a.v[g])) * E(0.5);
+      r1 = E(ldg(a.rho, g));
+      t1 = E(ldg(a.th, g));
+      q1 = E(ldg(a.q, g));
+      ub1 = (E(ldg(a.u, g - 1)) + E(ldg(a.u, g))) * E(0.5);
+      vb1 = (E(ldg(a.v, g - sj)) + E(ldg(a.v, g))) * E(0.5);
       const E rdzi = E(a.rdzi[k]);
       const E du = ub1 - ub0, dv = vb1 - vb0;
       const E kz = kmin + l2 * (sqrt(du * du + dv * dv) * rdzi);
@@ -122,9 +123,9 @@ __device__ T upward(const Column<T> &c, const S &st) {
       rt += beta * (ths - t0);
       rq += beta * (qs - q0);
     }
-    const T rk = T((alo + ahi) / m);
+    const T rk = T((alo + ahi) * fast_rcp(m));
     rmax = rk > rmax ? rk : rmax;
-    const E inv = E(1) / (diag + alo * cp);
+    const E inv = fast_rcp(diag + alo * cp);
     cp = -ahi * inv;
     dtp = (rt + alo * dtp) * inv;
     dqp = (rq + alo * dqp) * inv;
@@ -135,6 +136,9 @@ __device__ T upward(const Column<T> &c, const S &st) {
     tm1 = t0; t0 = t1;
     qm1 = q0; q0 = q1;
     r0 = r1; ub0 = ub1; vb0 = vb1;
+    // keep each level's loads next to their use when the loop is unrolled
+    // (otherwise all levels' loads are hoisted and the registers spill)
+    if (NZC > 0) __builtin_amdgcn_sched_barrier(0);
   }
   return rmax;
 }
@@ -144,44 +148,46 @@ struct Counters {
 };
 
 // Back substitution (top to bottom), radiation suffix scan and the update.
-template <typename T, typename E, typename S>
-__device__ void downward(const Column<T> &c, const S &st, Kahan *mass, Counters &cnt) {
+template <typename T, typename E, int NZC, int MODE, typename S>
+__device__ __forceinline__ void downward(const Column<T> &c, const S &st, Kahan *mass, Counters &cnt) {
   const PhysArgs<T> &a = c.a;
-  const int nz = a.g.nz;
+  const int nz = NZC > 0 ? NZC : a.g.nz;
   const T f0 = a.f0[c.col];
   const T kappa = a.kappa, cpa = a.cp, dt = a.dt;
   const int i = c.col % a.g.nx, j = c.col / a.g.nx;
   const int nx = a.g.nx, ny = a.g.ny;
-  const long long di = i < 2 ? nx : (i >= nx - 2 ? -nx : 0);
-  const long long dj = j < 2 ? (long long)ny * a.g.sj : (j >= ny - 2 ? -(long long)ny * a.g.sj : 0);
+  const int di = i < 2 ? nx : (i >= nx - 2 ? -nx : 0);
+  const int dj = j < 2 ? ny * int(a.g.sj) : (j >= ny - 2 ? -ny * int(a.g.sj) : 0);
   E dtn = 0, dqn = 0;
   T tau = T(0), tr_hi = T(1);
+#pragma unroll
   for (int k = nz - 1; k >= 0; --k) {
     const E dth = st.at(1, k) - st.at(0, k) * dtn;
     const E dqq = st.at(2, k) - st.at(0, k) * dqn;
     dtn = dth;
     dqn = dqq;
-    const long long g = c.at(k);
-    const T r = a.rho[g], t = a.th[g], q = a.q[g];
+    const unsigned g = c.at(k);
+    const T r = ldg(a.rho, g), t = ldg(a.th, g), q = ldg(a.q, g);
     const T dzk = a.dz[k];
     tau += kappa * r * (q > T(0) ? q : T(0)) * dzk;
     const T tr_lo = exp(-tau);
-    const T heat = f0 * (tr_hi - tr_lo) / (cpa * (r * dzk));
+    const T heat = f0 * (tr_hi - tr_lo) * fast_rcp(cpa * (r * dzk));
     tr_hi = tr_lo;
-    if (a.mode == 1) {
-      const long long o = ((long long)k * ny + j) * nx + i;
-      a.tend_t[o] = T(dth) / dt + heat;
-      a.tend_q[o] = T(dqq) / dt;
+    if (MODE == 1) {
+      const unsigned o = unsigned(k * ny + j) * unsigned(nx) + unsigned(i);
+      stg(a.tend_t, o, T(dth) / dt + heat);
+      stg(a.tend_q, o, T(dqq) / dt);
+      if (NZC > 0) __builtin_amdgcn_sched_barrier(0);
       continue;
     }
     const T tn = t + T(dth) + dt * heat;
     const T qn = q + T(dqq);
-    a.th[g] = tn;
-    a.q[g] = qn;
-    if (di != 0) { a.th[g + di] = tn; a.q[g + di] = qn; }
+    stg(a.th, g, tn);
+    stg(a.q, g, qn);
+    if (di != 0) { stg(a.th, g + di, tn); stg(a.q, g + di, qn); }
     if (dj != 0) {
-      a.th[g + dj] = tn; a.q[g + dj] = qn;
-      if (di != 0) { a.th[g + dj + di] = tn; a.q[g + dj + di] = qn; }
+      stg(a.th, g + dj, tn); stg(a.q, g + dj, qn);
+      if (di != 0) { stg(a.th, g + dj + di, tn); stg(a.q, g + dj + di, qn); }
     }
     if (!(isfinite(r) && isfinite(tn) && isfinite(qn))) cnt.nonfinite++;
     if (!(r > T(0))) cnt.rho_le0++;
@@ -191,10 +197,226 @@ __device__ void downward(const Column<T> &c, const S &st, Kahan *mass, Counters 
       mass[1].add(mv * (double(tn) + a.theta_off));
       mass[2].add(mv * double(qn));
     }
+    if (NZC > 0) __builtin_amdgcn_sched_barrier(0);
   }
 }
 
-template <typename T>
+
+// Fixed-order block reduction of the per-wave results (waves 0..NW-1).
+template <int NW>
+__device__ __forceinline__ void block_finish(const PhysArgs<float> *ap, double *partials, int *flags,
+                                             bool do_mass, bool count_faults, Kahan *mass,
+                                             const Counters &cnt, int fp64) {
+  __shared__ double sm[NW][6];
+  __shared__ int sc[NW][3];
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  (void)ap;
+  const int nf = wave_sum_i(cnt.nonfinite), nr = wave_sum_i(cnt.rho_le0), nd = wave_sum_i(fp64);
+  if (do_mass)
+    for (int v = 0; v < 3; ++v) wave_merge(mass[v]);
+  if (lane == 0) {
+    for (int v = 0; v < 3; ++v) {
+      sm[wv][2 * v] = mass[v].s;
+      sm[wv][2 * v + 1] = mass[v].c;
+    }
+    sc[wv][0] = nf;
+    sc[wv][1] = nr;
+    sc[wv][2] = nd;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    Kahan acc[3];
+    int t0 = 0, t1 = 0, t2 = 0;
+    for (int w = 0; w < NW; ++w) {
+      for (int v = 0; v < 3; ++v) acc[v].merge(sm[w][2 * v], sm[w][2 * v + 1]);
+      t0 += sc[w][0];
+      t1 += sc[w][1];
+      t2 += sc[w][2];
+    }
+    if (do_mass) {
+      double *p = partials + (long long)blockIdx.x * 6;
+      for (int v = 0; v < 3; ++v) {
+        p[2 * v] = acc[v].s;
+        p[2 * v + 1] = acc[v].c;
+      }
+    }
+    if (count_faults) {
+      if (t0) atomicAdd(&flags[0], t0);
+      if (t1) atomicAdd(&flags[1], t1);
+    }
+    if (t2) atomicAdd(&flags[2], t2);
+  }
+}
+
+// FP32 state with a compile-time level count NZ: the production path.
+//
+// 64 x 4 columns per block, one thread per column.  The forward elimination
+// keeps c' in LDS (one float per level and column) and d'_theta, d'_q in
+// registers (every loop over k is unrolled, so each array element is a fixed
+// VGPR).  Both passes prefetch the inputs of level k +- PF while working on
+// level k (a register ring of PF levels), so a wave never waits on the load it
+// is about to use; a scheduling barrier per level keeps the compiler from
+// hoisting further and running out of registers.  Columns whose dominance
+// ratio exceeds T_dd redo the elimination in FP64 (runtime loop, global
+// scratch).
+template <int NZ, int MODE>
+__global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
+  constexpr int PF = 4;
+  extern __shared__ float s_c[];          // [NZ][256]
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
+  const int nbx = (a.g.nx + 63) / 64;
+  const int i = (blockIdx.x % nbx) * 64 + tx, j = (blockIdx.x / nbx) * 4 + ty;
+  const bool active = (i < a.g.nx) && (j < a.g.ny);
+  Kahan mass[3];
+  Counters cnt;
+  int fp64 = 0;
+  if (active) {
+    const unsigned sj = a.g.sj, sk = a.g.sk;
+    const unsigned g0 = a.g.origin + unsigned(i) + unsigned(j) * sj;
+    const int col = i + a.g.nx * j;
+    const float dt = a.dt, kmin = a.kmin, l2 = a.l2;
+
+    // ---- upward pass: build row k from a one-level look-ahead, eliminate
+    float pr[PF], pt[PF], pq[PF], pu[PF], pe[PF], pv[PF], pn[PF];  // prefetch ring, levels k+1 .. k+PF
+    auto fetch_up = [&](int lev, int slot) {
+      const unsigned g = g0 + unsigned(lev) * sk;
+      pr[slot] = ldg(a.rho, g);
+      pt[slot] = ldg(a.th, g);
+      pq[slot] = ldg(a.q, g);
+      pu[slot] = ldg(a.u, g - 1);
+      pe[slot] = ldg(a.u, g);
+      pv[slot] = ldg(a.v, g - sj);
+      pn[slot] = ldg(a.v, g);
+    };
+    float r0 = ldg(a.rho, g0), t0 = ldg(a.th, g0), q0 = ldg(a.q, g0);
+    float ub0 = (ldg(a.u, g0 - 1) + ldg(a.u, g0)) * 0.5f;
+    float vb0 = (ldg(a.v, g0 - sj) + ldg(a.v, g0)) * 0.5f;
+#pragma unroll
+    for (int l = 1; l <= PF; ++l)
+      if (l < NZ) fetch_up(l, l % PF);
+    const float beta = dt * r0 * ldg(a.ch, unsigned(col));
+    const float ths = ldg(a.th_s, unsigned(col)), qs = ldg(a.q_s, unsigned(col));
+    float dtr[NZ], dqr[NZ];
+    float alo = 0.f, tm1 = t0, qm1 = q0, cpv = 0.f, dtp = 0.f, dqp = 0.f, rmax = 0.f;
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) {
+      float ahi = 0.f, r1 = 0.f, t1 = t0, q1 = q0, ub1 = 0.f, vb1 = 0.f;
+      if (k + 1 < NZ) {
+        const int sl = (k + 1) % PF;
+        r1 = pr[sl];
+        t1 = pt[sl];
+        q1 = pq[sl];
+        ub1 = (pu[sl] + pe[sl]) * 0.5f;
+        vb1 = (pv[sl] + pn[sl]) * 0.5f;
+        if (k + 1 + PF < NZ) fetch_up(k + 1 + PF, sl);
+        const float rdzi = a.rdzi[k];
+        const float du = ub1 - ub0, dv = vb1 - vb0;
+        const float kz = kmin + l2 * (__builtin_amdgcn_sqrtf(du * du + dv * dv) * rdzi);
+        ahi = dt * ((r0 + r1) * 0.5f) * kz * rdzi;
+      }
+      const float m = r0 * a.dz[k];
+      float diag = m + alo + ahi;
+      float rt = ahi * (t1 - t0) - alo * (t0 - tm1);
+      float rq = ahi * (q1 - q0) - alo * (q0 - qm1);
+      if (k == 0) {
+        diag += beta;
+        rt += beta * (ths - t0);
+        rq += beta * (qs - q0);
+      }
+      const float rk = (alo + ahi) * fast_rcp(m);
+      rmax = rk > rmax ? rk : rmax;
+      const float inv = fast_rcp(diag + alo * cpv);
+      cpv = -ahi * inv;
+      dtp = (rt + alo * dtp) * inv;
+      dqp = (rq + alo * dqp) * inv;
+      s_c[k * 256 + tid] = cpv;
+      dtr[k] = dtp;
+      dqr[k] = dqp;
+      alo = ahi;
+      tm1 = t0; t0 = t1;
+      qm1 = q0; q0 = q1;
+      r0 = r1; ub0 = ub1; vb0 = vb1;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+
+    const Column<float> c{a, g0, col};
+    if (rmax > a.tdd) {
+      const unsigned ncol = unsigned(a.g.nx) * unsigned(a.g.ny);
+      const GlobalStore<double> gs{a.scratch, NZ, ncol, unsigned(col)};
+      upward<float, double, 0>(c, gs);
+      downward<float, double, 0, MODE>(c, gs, mass, cnt);
+      fp64 = 1;
+    } else {
+      // ---- downward pass: back substitution, radiation suffix scan, update
+      const int nx = a.g.nx, ny = a.g.ny;
+      const float f0 = ldg(a.f0, unsigned(col));
+      const float kappa = a.kappa, cpa = a.cp;
+      const int di = i < 2 ? nx : (i >= nx - 2 ? -nx : 0);
+      const int dj = j < 2 ? ny * int(sj) : (j >= ny - 2 ? -ny * int(sj) : 0);
+      // an opaque copy of the column offset and a compiler memory barrier: the
+      // downward pass recomputes its addresses and re-reads c' from LDS
+      // instead of keeping the upward pass's per-level values alive
+      unsigned gd = g0;
+      asm volatile("" : "+v"(gd)::"memory");
+      float xr[PF], xt[PF], xq[PF];                 // prefetch ring (levels k-1 .. k-PF)
+      auto fetch_dn = [&](int lev, int slot) {
+        const unsigned g = gd + unsigned(lev) * sk;
+        xr[slot] = ldg(a.rho, g);
+        xt[slot] = ldg(a.th, g);
+        xq[slot] = ldg(a.q, g);
+      };
+#pragma unroll
+      for (int l = 0; l < PF; ++l)
+        if (NZ - 1 - l >= 0) fetch_dn(NZ - 1 - l, (NZ - 1 - l) % PF);
+      float dtn = 0.f, dqn = 0.f, tau = 0.f, tr_hi = 1.f;
+#pragma unroll
+      for (int k = NZ - 1; k >= 0; --k) {
+        const int sl = k % PF;
+        const float r = xr[sl], t = xt[sl], q = xq[sl];
+        if (k - PF >= 0) fetch_dn(k - PF, sl);
+        const float ck = s_c[k * 256 + tid];
+        const float dth = dtr[k] - ck * dtn;
+        const float dqq = dqr[k] - ck * dqn;
+        dtn = dth;
+        dqn = dqq;
+        const float dzk = a.dz[k];
+        tau += kappa * r * (q > 0.f ? q : 0.f) * dzk;
+        const float tr_lo = expf(-tau);
+        const float heat = f0 * (tr_hi - tr_lo) * fast_rcp(cpa * (r * dzk));
+        tr_hi = tr_lo;
+        const unsigned g = gd + unsigned(k) * sk;
+        if (MODE == 1) {
+          const unsigned o = unsigned(k * ny + j) * unsigned(nx) + unsigned(i);
+          stg(a.tend_t, o, dth / dt + heat);
+          stg(a.tend_q, o, dqq / dt);
+        } else {
+          const float tn = t + dth + dt * heat;
+          const float qn = q + dqq;
+          stg(a.th, g, tn);
+          stg(a.q, g, qn);
+          if (di != 0) { stg(a.th, g + di, tn); stg(a.q, g + di, qn); }
+          if (dj != 0) {
+            stg(a.th, g + dj, tn); stg(a.q, g + dj, qn);
+            if (di != 0) { stg(a.th, g + dj + di, tn); stg(a.q, g + dj + di, qn); }
+          }
+          if (!(isfinite(r) && isfinite(tn) && isfinite(qn))) cnt.nonfinite++;
+          if (!(r > 0.f)) cnt.rho_le0++;
+          if (a.do_mass) {
+            const double mv = double(r) * a.vol[k];
+            mass[0].add(mv);
+            mass[1].add(mv * (double(tn) + a.theta_off));
+            mass[2].add(mv * double(qn));
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+  block_finish<4>(&a, a.partials, a.flags, MODE == 0 && a.do_mass, MODE == 0, mass, cnt, fp64);
+}
+
+template <typename T, int MODE>
 __global__ __launch_bounds__(PHYS_BX) void k_physics(PhysArgs<T> a) {
   extern __shared__ unsigned char s_raw[];
   const int nbx = (a.g.nx + PHYS_BX - 1) / PHYS_BX;
@@ -206,36 +428,36 @@ __global__ __launch_bounds__(PHYS_BX) void k_physics(PhysArgs<T> a) {
   Counters cnt;
   int fp64 = 0;
   if (active) {
-    const Column<T> c{a, a.g.origin + i + (long long)j * a.g.sj, i + a.g.nx * j};
-    const long long ncol = (long long)a.g.nx * a.g.ny;
+    const Column<T> c{a, a.g.origin + unsigned(i) + unsigned(j) * a.g.sj, i + a.g.nx * j};
+    const unsigned ncol = unsigned(a.g.nx) * unsigned(a.g.ny);
     bool wide;
     if (sizeof(T) == 4) {
       if (a.use_lds) {
         const LdsStore<float> st{reinterpret_cast<float *>(s_raw), a.g.nz, lane};
-        wide = upward<T, float>(c, st) > a.tdd;
-        if (!wide) downward<T, float>(c, st, mass, cnt);
+        wide = upward<T, float, 0>(c, st) > a.tdd;
+        if (!wide) downward<T, float, 0, MODE>(c, st, mass, cnt);
       } else {
-        const GlobalStore<float> st{reinterpret_cast<float *>(a.scratch), a.g.nz, ncol, c.col};
-        wide = upward<T, float>(c, st) > a.tdd;
-        if (!wide) downward<T, float>(c, st, mass, cnt);
+        const GlobalStore<float> st{reinterpret_cast<float *>(a.scratch), a.g.nz, ncol, unsigned(c.col)};
+        wide = upward<T, float, 0>(c, st) > a.tdd;
+        if (!wide) downward<T, float, 0, MODE>(c, st, mass, cnt);
       }
     } else {
-      const GlobalStore<double> st{a.scratch, a.g.nz, ncol, c.col};
-      wide = upward<T, double>(c, st) > a.tdd;
-      downward<T, double>(c, st, mass, cnt);
+      const GlobalStore<double> st{a.scratch, a.g.nz, ncol, unsigned(c.col)};
+      wide = upward<T, double, 0>(c, st) > a.tdd;
+      downward<T, double, 0, MODE>(c, st, mass, cnt);
       fp64 = wide ? 1 : 0;
       wide = false;
     }
     if (wide) {
-      const GlobalStore<double> st{a.scratch, a.g.nz, ncol, c.col};
-      upward<T, double>(c, st);
-      downward<T, double>(c, st, mass, cnt);
+      const GlobalStore<double> st{a.scratch, a.g.nz, ncol, unsigned(c.col)};
+      upward<T, double, 0>(c, st);
+      downward<T, double, 0, MODE>(c, st, mass, cnt);
       fp64 = 1;
     }
   }
   // block (= one wave) reductions in a fixed order
   const int nf = wave_sum_i(cnt.nonfinite), nr = wave_sum_i(cnt.rho_le0), nd = wave_sum_i(fp64);
-  if (a.mode == 0 && a.do_mass) {
+  if (MODE == 0 && a.do_mass) {
     for (int v = 0; v < 3; ++v) wave_merge(mass[v]);
     if (lane == 0) {
       double *p = a.partials + (long long)blockIdx.x * 6;
@@ -245,7 +467,7 @@ __global__ __launch_bounds__(PHYS_BX) void k_physics(PhysArgs<T> a) {
       }
     }
   }
-  if (lane == 0 && a.mode == 0) {
+  if (lane == 0 && MODE == 0) {
     if (nf) atomicAdd(&a.flags[0], nf);
     if (nr) atomicAdd(&a.flags[1], nr);
   }
@@ -261,10 +483,10 @@ __global__ __launch_bounds__(PHYS_BX) void k_mass(MassArgs<T> a) {
   Kahan mass[3];
   Counters cnt;
   if (i < a.g.nx) {
-    const long long g0 = a.g.origin + i + (long long)j * a.g.sj;
+    const unsigned g0 = a.g.origin + unsigned(i) + unsigned(j) * a.g.sj;
     for (int k = 0; k < a.g.nz; ++k) {
-      const long long g = g0 + (long long)k * a.g.sk;
-      const T r = a.rho[g], t = a.th[g], q = a.q[g];
+      const unsigned g = g0 + unsigned(k) * a.g.sk;
+      const T r = ldg(a.rho, g), t = ldg(a.th, g), q = ldg(a.q, g);
       if (!(isfinite(r) && isfinite(t) && isfinite(q))) cnt.nonfinite++;
       if (!(r > T(0))) cnt.rho_le0++;
       const double mv = double(r) * a.vol[k];
@@ -328,9 +550,26 @@ __global__ void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
 
 template <typename T>
 hipError_t launch_physics(const PhysArgs<T> &a, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    const int nb = phys_reg_blocks(a.g.nx, a.g.ny);
+    const dim3 blk(64, 4);
+    if (a.g.nz == 58) {
+      const size_t lds = 58 * 256 * sizeof(float);
+      if (a.mode == 0) hipLaunchKernelGGL((k_physics_f32<58, 0>), dim3(nb), blk, lds, s, a);
+      else hipLaunchKernelGGL((k_physics_f32<58, 1>), dim3(nb), blk, lds, s, a);
+      return hipGetLastError();
+    }
+    if (a.g.nz == 16) {
+      const size_t lds = 16 * 256 * sizeof(float);
+      if (a.mode == 0) hipLaunchKernelGGL((k_physics_f32<16, 0>), dim3(nb), blk, lds, s, a);
+      else hipLaunchKernelGGL((k_physics_f32<16, 1>), dim3(nb), blk, lds, s, a);
+      return hipGetLastError();
+    }
+  }
   const int nb = phys_blocks(a.g.nx, a.g.ny);
   const size_t lds = (sizeof(T) == 4 && a.use_lds) ? size_t(3) * a.g.nz * PHYS_BX * sizeof(float) : 0;
-  hipLaunchKernelGGL(k_physics<T>, dim3(nb), dim3(PHYS_BX), lds, s, a);
+  if (a.mode == 0) hipLaunchKernelGGL((k_physics<T, 0>), dim3(nb), dim3(PHYS_BX), lds, s, a);
+  else hipLaunchKernelGGL((k_physics<T, 1>), dim3(nb), dim3(PHYS_BX), lds, s, a);
   return hipGetLastError();
 }
 

@@ -1,4 +1,5 @@
 // C ABI (include/wx.h): state, validation, workspace layout and launch plan.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -65,7 +66,8 @@ Layout layout(const wx_state *s, size_t es) {
   L.scratch = off;
   off += align256(3 * size_t(s->nz) * size_t(s->nx) * size_t(s->ny) * 8);
   L.partials = off;
-  off += align256(size_t(wx::phys_blocks(s->nx, s->ny)) * 6 * 8);
+  const int nparts = std::max(wx::phys_blocks(s->nx, s->ny), wx::phys_reg_blocks(s->nx, s->ny));
+  off += align256(size_t(nparts) * 6 * 8);
   L.total = off;
   return L;
 }
@@ -109,7 +111,9 @@ int check_fields(const wx_state *s, bool need_phys) {
   return WX_OK;
 }
 
-wx::Geom geom(const wx_state *s) { return wx::Geom{s->nx, s->ny, s->nz, s->stride_j, s->stride_k, s->origin}; }
+wx::Geom geom(const wx_state *s) {
+  return wx::Geom{s->nx, s->ny, s->nz, unsigned(s->stride_j), unsigned(s->stride_k), unsigned(s->origin)};
+}
 
 // Upload the per-dtype constants into the workspace when they changed.
 template <typename T>
@@ -167,6 +171,7 @@ struct Plan {
   const T *dz, *rdz, *rdzi;
   const double *vol;
   double *scratch, *partials;
+  int nparts = 0;   // mass partials written by the last physics / mass launch
 
   Plan(wx_state *s_, hipStream_t st_) : s(s_), st(st_) {
     L = layout(s, sizeof(T));
@@ -249,6 +254,7 @@ struct Plan {
   int physics(int do_mass, Timer &tm) {
     WX_TRY(tm.begin(4));
     WX_HIP(wx::launch_physics<T>(phys_args(0, do_mass, nullptr, nullptr), st));
+    nparts = wx::phys_partials(sizeof(T), s->nx, s->ny, s->nz);
     return tm.end();
   }
 
@@ -262,12 +268,13 @@ struct Plan {
     a.theta_off = impl_of(s)->param[WX_PARAM_THETA_OFFSET];
     WX_TRY(tm.begin(4));
     WX_HIP(wx::launch_mass<T>(a, st));
+    nparts = wx::phys_blocks(s->nx, s->ny);
     return tm.end();
   }
 
   int mass_final(Timer &tm) {
     WX_TRY(tm.begin(5));
-    WX_HIP(wx::launch_mass_final(partials, wx::phys_blocks(s->nx, s->ny), s->mass_out, st));
+    WX_HIP(wx::launch_mass_final(partials, nparts, s->mass_out, st));
     return tm.end();
   }
 
@@ -336,8 +343,9 @@ wx_state *wx_create(int nx, int ny, int nz, double dt, double dx, const double *
     }
   const long long sj = ((long long)nx + 2 * WX_HALO + 63) / 64 * 64;
   const long long sk = sj * (ny + 2 * WX_HALO);
-  if (sk * (long long)(nz + 1) > (1LL << 40)) {
-    fail(WX_E_INVAL, "grid too large");
+  // kernels address every buffer with 32-bit byte offsets (FP64 worst case)
+  if (sk * (long long)(nz + 1) * 8 >= (1LL << 32) || 24LL * nz * nx * ny >= (1LL << 32)) {
+    fail(WX_E_UNSUPPORTED, "grid too large for 32-bit byte offsets");
     return nullptr;
   }
   wx_state *s = new (std::nothrow) wx_state();

@@ -6,11 +6,34 @@
 
 namespace wx {
 
-// Geometry shared by every kernel.
+// Geometry shared by every kernel.  Element offsets fit in 32 bits (checked
+// when the state is created), so kernels index with 32-bit offsets from a
+// uniform base pointer.
 struct Geom {
   int nx, ny, nz;
-  long long sj, sk, origin;  // element strides and offset of interior (0,0,0)
+  unsigned sj, sk, origin;  // element strides and offset of interior (0,0,0)
 };
+
+// Element access through a 32-bit byte offset from a uniform base pointer, so
+// that loads and stores use the scalar-base + 32-bit vector-offset address
+// form (every buffer is smaller than 4 GiB; checked when the state is created).
+template <typename T>
+__device__ __forceinline__ T ldg(const T *base, unsigned idx) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + idx * unsigned(sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void stg(T *base, unsigned idx, T v) {
+  *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + idx * unsigned(sizeof(T))) = v;
+}
+template <typename T>
+__device__ __forceinline__ T &ref(T *base, unsigned idx) {
+  return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + idx * unsigned(sizeof(T)));
+}
+
+// Reciprocal in the arithmetic precision: the hardware estimate (1 ulp) in
+// FP32, an exact division in FP64.
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 
 template <typename T>
 struct StageArgs {
@@ -71,5 +94,11 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 inline int stage_tiles_x(int nx) { return (nx + 63) / 64; }
 inline int stage_tiles_y(int ny) { return (ny + 3) / 4; }
 inline int phys_blocks(int nx, int ny) { return ((nx + PHYS_BX - 1) / PHYS_BX) * ny; }
+inline int phys_reg_blocks(int nx, int ny) { return ((nx + 63) / 64) * ((ny + 3) / 4); }
+// physics kernel variant for a state: register-resident columns for FP32 and these level counts
+inline bool phys_uses_reg(int elem_size, int nz) { return elem_size == 4 && (nz == 58 || nz == 16); }
+inline int phys_partials(int elem_size, int nx, int ny, int nz) {
+  return phys_uses_reg(elem_size, nz) ? phys_reg_blocks(nx, ny) : phys_blocks(nx, ny);
+}
 
 }  // namespace wx

@@ -207,11 +207,12 @@ def test_tendencies_match_oracle():
 
 
 @pytest.mark.parametrize("tdd", [0.0, 1e30])
-def test_fp64_elimination_switch(tdd):
+@pytest.mark.parametrize("nz", [12, 16, 58])
+def test_fp64_elimination_switch(tdd, nz):
     # T_dd = 0 sends every column through the FP64 forward elimination,
     # T_dd = 1e30 none; both agree with the oracle and the counter says which.
-    _say(f"case: FP64 elimination switch tdd={tdd}")
-    inp = inputs.generate(70, 20, 12, seed=28)
+    _say(f"case: FP64 elimination switch tdd={tdd} nz={nz}")
+    inp = inputs.generate(70, 20, nz, seed=28)
     inp.dt = inp.dt * 40.0          # stiff columns: large alpha / m
     inp32 = inp.astype(np.float32)
     inp32.theta = (inp.theta - 300.0).astype(np.float32).astype(np.float64) + 300.0
@@ -279,3 +280,77 @@ def test_wx_mass_entry_point():
     st.close()
     np.testing.assert_allclose(m, mass_sums(inp.rho, inp.theta, inp.q, inp.dx, inp.dx, inp.dz),
                                rtol=1e-15)
+
+
+def _f32_inputs(inp):
+    """FP32-representable copy of a problem (theta rounded as theta - 300)."""
+    out = inp.astype(np.float32)
+    out.theta = (inp.theta - 300.0).astype(np.float32).astype(np.float64) + 300.0
+    out.theta_s = (inp.theta_s - 300.0).astype(np.float32).astype(np.float64) + 300.0
+    return out
+
+
+def _crop_check(inp, gpu, nsteps, windows, tol):
+    """Oracle on periodic crops enlarged by the light cone, compared inside.
+
+    One step reads at most 2 cells around a cell per RK stage (6 per step);
+    the physics is column-local, so a crop enlarged by 6 n cells on each side
+    reproduces the full-grid result in its inner window.
+    """
+    m = 6 * nsteps
+    worst = {}
+    for (i0, j0, cx, cy) in windows:
+        sub = inputs.crop(inp, i0 - m, j0 - m, cx + 2 * m, cy + 2 * m)
+        ref = step.run(sub, nsteps)
+        ii = np.arange(i0, i0 + cx) % inp.nx
+        jj = np.arange(j0, j0 + cy) % inp.ny
+        for name in ("rho", "theta", "q"):
+            g = gpu[name][:, jj][:, :, ii]
+            r = getattr(ref, name)[:, m:m + cy, m:m + cx]
+            off = 300.0 if name == "theta" else 0.0
+            e = nmax(g - off, r - off)
+            worst[name] = max(worst.get(name, 0.0), e)
+    for k, e in worst.items():
+        assert e <= tol, worst
+    return worst
+
+
+def test_share_grid_fp32_crops():
+    # 400 x 320 x 58: one GPU's share of the 1581 x 1301 grid
+    _say("case: 400x320x58 FP32 1 step, crops")
+    inp = _f32_inputs(inputs.generate_config("share"))
+    gpu = _run_gpu(inp, 1, "f32", theta_offset=300.0)
+    w = [(0, 0, 40, 40), (380, 300, 40, 40), (197, 123, 48, 32)]
+    worst = _crop_check(inp, gpu, 1, w, FP32_TOL)
+    _say(f"share grid fp32 errors {worst}")
+
+
+def test_share_grid_fp64_three_steps_crops():
+    _say("case: 400x320x58 FP64 3 steps, crops")
+    inp = inputs.generate_config("share")
+    gpu = _run_gpu(inp, 3, "f64")
+    worst = _crop_check(inp, gpu, 3, [(390, 5, 24, 24), (150, 160, 24, 24)], FP64_TOL)
+    _say(f"share grid fp64 errors {worst}")
+
+
+def test_full_grid_fp32_crops_and_mass():
+    # the benchmark's workload: 1581 x 1301 x 58 in FP32, one step
+    _say("case: 1581x1301x58 FP32 1 step, crops")
+    inp = inputs.generate_config("full", dtype=np.float32)
+    inp64 = inp.astype(np.float64)
+    inp64.theta = (inp.theta.astype(np.float64) - 300.0).astype(np.float32).astype(np.float64) + 300.0
+    inp64.theta_s = (inp.theta_s.astype(np.float64) - 300.0).astype(np.float32).astype(np.float64) + 300.0
+    st = wx.state_from_inputs(inp64, dtype="f32", theta_offset=300.0)
+    m0 = st.mass(compute=True)
+    st.step(1)
+    gpu = st.download()
+    flags = st.flags()
+    m1 = st.mass()
+    st.close()
+    del inp
+    assert flags["nonfinite"] == 0 and flags["rho_le0"] == 0
+    # density is conserved exactly by the dycore and untouched by the physics
+    assert abs(m1[0] - m0[0]) / m0[0] <= 1e-6
+    w = [(0, 0, 32, 32), (1565, 1285, 32, 32), (790, 650, 32, 32), (1500, 20, 32, 32)]
+    worst = _crop_check(inp64, gpu, 1, w, FP32_TOL)
+    _say(f"full grid fp32 errors {worst}")
