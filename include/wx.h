@@ -63,7 +63,10 @@ typedef enum wx_dtype { WX_F32 = 0, WX_F64 = 1 } wx_dtype;
 
 typedef enum wx_phys_mode {
   WX_PHYS_OFF = 0,        /* dycore only                                        */
-  WX_PHYS_PLAIN = 1       /* dycore, then implicit diffusion + radiation        */
+  WX_PHYS_PLAIN = 1,      /* dycore, then implicit diffusion + radiation        */
+  WX_PHYS_SURROGATE = 2,  /* dycore, then the learned surrogate on every column */
+  WX_PHYS_JUDGED = 3      /* dycore, surrogate, plain physics on sampled columns
+                             as judge, whole-step fallback to the plain physics  */
 } wx_phys_mode;
 
 /* Tunable constants (readings of the paper; defaults in brackets). */
@@ -81,7 +84,13 @@ typedef enum wx_param {
   WX_PARAM_MASS_EVERY = 7,   /* wx_step computes the mass sums on every step
                                 whose 1-based index is a multiple of this, and
                                 always on the last step; 0 = never [1]          */
-  WX_PARAM_COUNT = 8
+  WX_PARAM_JUDGE_SEED = 8,   /* judge sample seed, integer < 2^32 [0]           */
+  WX_PARAM_JUDGE_REL = 9,    /* fallback when a pooled RMSE > rel * sigma [0.05] */
+  WX_PARAM_JUDGE_RATE = 10,  /* one column in `rate` is sampled, integer >= 1;
+                                fixed once the surrogate workspace is sized [100] */
+  WX_PARAM_STEP = 11,        /* index t of the next step (sample hash), integer
+                                >= 0; wx_step advances it by nsteps [0]          */
+  WX_PARAM_COUNT = 12
 } wx_param;
 
 /* Flags written by wx_step / wx_mass into flags_out[WX_NFLAGS] (cleared at the
@@ -89,7 +98,7 @@ typedef enum wx_param {
 #define WX_FLAG_NONFINITE 0   /* cells with a non-finite rho, theta or q        */
 #define WX_FLAG_RHO_LE0 1     /* cells with rho <= 0                             */
 #define WX_FLAG_FP64_COLS 2   /* column solves that took the FP64 elimination    */
-#define WX_FLAG_RESERVED 3
+#define WX_FLAG_FALLBACK 3    /* judged steps that fell back to the plain physics */
 #define WX_NFLAGS 4
 
 typedef struct wx_state {
@@ -115,6 +124,11 @@ typedef struct wx_state {
   double *mass_out;        /* 6 doubles: (sum, compensation) of rho V,
                               rho theta V, rho q V with V = dx dy dz_k            */
   int32_t *flags_out;      /* WX_NFLAGS ints                                      */
+  /* surrogate modes only (WX_PHYS_SURROGATE / WX_PHYS_JUDGED; FP32 state, nz 58): */
+  void *mlp;               /* trained parameter blob (wx_mlp_bytes)               */
+  void *surrogate_work;    /* >= wx_surrogate_work_bytes(...) device bytes        */
+  double *judge_out;       /* 4 doubles, last judged step: RMSE theta [K/s], RMSE
+                              q [1/s], fallback (0/1), sampled columns            */
   void *impl;              /* private                                             */
 } wx_state;
 
@@ -139,6 +153,11 @@ const char *wx_last_error(void);
  * block partials of the mass sums and a few constants. */
 size_t wx_workspace_bytes(const wx_state *s, int dtype);
 
+/* Device workspace of the surrogate modes: feature, activation and output
+ * buffers for chunks of up to 262144 columns, and the judge's sample list
+ * sized for the current WX_PARAM_JUDGE_RATE. */
+size_t wx_surrogate_work_bytes(const wx_state *s);
+
 /* Set / get a wx_param.  Values must be finite; GAMMA4, KMIN, MIXLEN, KAPPA_Q
  * >= 0, CP > 0, TDD >= 0, MASS_EVERY >= 0 (integral). */
 int wx_set_param(wx_state *s, int param, double value);
@@ -150,8 +169,9 @@ int wx_halo(wx_state *s, void *stream);
 
 /* Advance the state by nsteps >= 0 steps on `stream` (also stored as
  * s->stream).  Per call: halo fill, then per step three RK stages (the long
- * step of section "The ASUCA Weather Prediction Model") and, if phys_mode is
- * WX_PHYS_PLAIN, the column physics.  Fields are updated in place; the halo
+ * step of section "The ASUCA Weather Prediction Model") and the physics of
+ * phys_mode: none, the plain column physics, the surrogate on every column,
+ * or the judged surrogate (see the surrogate section below).  Fields are updated in place; the halo
  * ring is kept current.  Mass sums of the final state go to mass_out (see
  * WX_PARAM_MASS_EVERY); flags_out is cleared and then accumulated. */
 int wx_step(wx_state *s, int nsteps, void *stream);
@@ -176,6 +196,91 @@ int wx_profile_step(wx_state *s, int nsteps, void *stream, double *ms_out, int n
 /* Plain device copy kernel of `bytes` (multiple of 16) from src to dst on
  * `stream`: the reference for bandwidth and for scaling HBM counters. */
 int wx_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
+
+/* ======================================================================
+ * Learned surrogate of the column physics (BF16 matrix-core MLP).
+ *
+ * A 294-512-512-116 ReLU network maps a column's physics inputs to its
+ * theta and q tendencies.  GEMM operands are BF16 (round to nearest even),
+ * accumulation FP32; weights are kept FP32 with BF16 copies.  Layouts:
+ *   features  [n][WX_MLP_KIN] : theta, q, rho, u, v over k = 0..57 (u, v
+ *             cell-centred), then theta_s, q_s, F0, C_h; zero padding;
+ *             column c = i + nx j;
+ *   targets   [n][WX_MLP_NOUTP]: 58 theta tendencies [K/s], 58 q tendencies
+ *             [1/s], zero padding.
+ * All buffers are device memory owned by the caller.  The parameter blob is
+ * one buffer of wx_mlp_bytes() bytes whose sections start at
+ * wx_mlp_offset(section); the caller may read or write any section (FP32
+ * weights written by the caller take effect after wx_mlp_refresh).
+ * ====================================================================== */
+#define WX_MLP_NZ 58
+#define WX_MLP_NIN 294
+#define WX_MLP_KIN 320
+#define WX_MLP_NHID 512
+#define WX_MLP_NOUT 116
+#define WX_MLP_NOUTP 128
+
+typedef enum wx_mlp_section {
+  /* FP32 parameters: W1 [512][320], b1 [512], W2 [512][512], b2 [512],
+     W3 [128][512], b3 [128] (padding entries stay zero) */
+  WX_MLP_W1 = 0, WX_MLP_B1 = 1, WX_MLP_W2 = 2, WX_MLP_B2 = 3, WX_MLP_W3 = 4, WX_MLP_B3 = 5,
+  WX_MLP_GRAD = 6,     /* + 0..5: gradients of the last wx_mlp_forward_backward, same shapes */
+  WX_MLP_ADAM_M = 12,  /* + 0..5: Adam first moments */
+  WX_MLP_ADAM_V = 18,  /* + 0..5: Adam second moments */
+  WX_MLP_W1_BF16 = 24, WX_MLP_W2_BF16 = 25, WX_MLP_W3_BF16 = 26,  /* BF16 copies, same shapes */
+  WX_MLP_W2T_BF16 = 27,  /* W2 transposed [512][512] */
+  WX_MLP_W3T_BF16 = 28,  /* W3 transposed [512][128] */
+  WX_MLP_X_MEAN = 29, WX_MLP_X_INVSTD = 30,  /* FP32 [320]: feature mean and 1/std (0 on padding) */
+  WX_MLP_Y_MEAN = 31, WX_MLP_Y_STD = 32,     /* FP32 [128]: target mean and std (1 on padding) */
+  WX_MLP_SIGMA = 33,    /* FP32 [2]: pooled std of the theta and q tendencies */
+  WX_MLP_SIGMA64 = 34,  /* FP64 [2]: the same in FP64 */
+  WX_MLP_NSECTIONS = 35
+} wx_mlp_section;
+
+size_t wx_mlp_bytes(void);
+/* Byte offset of a section in the blob; -1 for an unknown section. */
+int64_t wx_mlp_offset(int section);
+/* He-uniform weights (+-sqrt(6/fan_in), element e of tensor t drawn from
+ * SplitMix64((seed << 32) | (t << 28) | e)), zero biases, gradients and
+ * moments, identity normalisation, BF16 copies. */
+int wx_mlp_init(void *blob, uint64_t seed, void *stream);
+/* Rebuild the BF16 copies from the FP32 weights. */
+int wx_mlp_refresh(void *blob, void *stream);
+
+/* Normalisation: FP64 mean and population std per feature and target over
+ * n raw rows (std < 1e-12 is replaced by 1), and the pooled std of the theta
+ * and q tendencies; stored in the blob.  scratch: wx_mlp_norm_scratch_bytes(n). */
+size_t wx_mlp_norm_scratch_bytes(size_t n);
+int wx_mlp_fit_norm(void *blob, const float *x_raw, const float *y_raw, size_t n, void *scratch, void *stream);
+/* x_out [n][320] BF16 = (x - mean) / std; y_out [n][128] FP32 (y may be NULL). */
+int wx_mlp_normalize(const void *blob, const float *x_raw, const float *y_raw, size_t n, void *x_out,
+                     float *y_out, void *stream);
+
+/* Training on normalised data x [N][320] BF16 and y [N][128] FP32: the batch
+ * is rows[0..batch) (device int32).  forward_backward writes the gradients of
+ * mean((y_hat - y)^2) over the batch and the 116 outputs into the GRAD
+ * sections and the sum of squared errors into loss_sum[0] (device).  adam
+ * applies one Adam step (t >= 1, beta 0.9 / 0.999, eps 1e-8) and refreshes
+ * the BF16 copies.  work: wx_mlp_work_bytes(batch).  batch is 1..65536. */
+size_t wx_mlp_work_bytes(int batch);
+int wx_mlp_forward_backward(void *blob, void *work, const void *x, const float *y, const int32_t *rows,
+                            int batch, float *loss_sum, void *stream);
+int wx_mlp_adam(void *blob, float lr, int t, void *stream);
+int wx_mlp_train_step(void *blob, void *work, const void *x, const float *y, const int32_t *rows, int batch,
+                      float lr, int t, float *loss_sum, void *stream);
+
+/* Inference: y_out [n][128] FP32 normalised outputs for x [n][320] BF16.
+ * work: wx_mlp_infer_work_bytes(n). */
+size_t wx_mlp_infer_work_bytes(int n);
+int wx_mlp_infer(const void *blob, void *work, const void *x, int n, float *y_out, void *stream);
+
+/* Feature rows of the current state on s->stream (nz must be 58): raw FP32
+ * (normalized = 0, blob unused) or normalised BF16 with the blob's statistics.
+ * out holds nx*ny rows of WX_MLP_KIN values. */
+int wx_features(wx_state *s, int normalized, void *out, const void *blob);
+/* Training data of the current state on s->stream (FP32 state, nz = 58): raw
+ * feature rows and the plain-physics tendency rows (targets), nx*ny each. */
+int wx_dataset(wx_state *s, float *x_raw, float *y_raw);
 
 #ifdef __cplusplus
 }

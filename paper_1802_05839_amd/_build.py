@@ -17,7 +17,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libwx.so")
 
-SOURCES = ["wx_host.hip", "k_dycore.hip", "k_physics.hip"]
+SOURCES = ["wx_host.hip", "wx_mlp_host.hip", "k_dycore.hip", "k_physics.hip", "k_mlp.hip",
+           "k_surrogate.hip", "k_judge.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",
@@ -26,6 +27,7 @@ HIP_FLAGS = [
     "-fPIC",
     "-Wall",
     "-Wno-unused-result",
+    "-Wno-pass-failed",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

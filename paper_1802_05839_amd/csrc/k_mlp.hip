@@ -1,0 +1,333 @@
+// The learned surrogate of the column physics: BF16 MFMA GEMMs with FP32
+// accumulation, loss, Adam, initialisation, feature/label assembly and
+// normalisation.
+//
+// Method (readings; the paper has no learned component): a 294-512-512-116
+// ReLU network maps a column's physics inputs to its theta and q tendencies;
+// GEMM operands (inputs, activations, weights, upstream gradients) are BF16
+// rounded to nearest even, accumulation is FP32, bias / ReLU / loss / bias
+// gradients / Adam are FP32; weights are stored FP32 (master) with BF16
+// copies refreshed after each update.
+//
+// GEMM: C[m][n] = sum_k A(m,k) B(k,n) on 64 x 64 output tiles, K in steps of
+// 32, four waves each owning a 32 x 32 quarter as 2 x 2 tiles of
+// v_mfma_f32_16x16x32_bf16.  Operands are staged through LDS in [row][k]
+// order (k contiguous) so each lane feeds the matrix core with one 16-byte
+// LDS read per tile; global operands may be k-contiguous (row-major [rows][K])
+// or row-contiguous ([K][rows]); the latter are transposed on the way into LDS.
+// Every output element is produced by one lane with a fixed k order, and a
+// split over K writes partial tiles that a second kernel sums in a fixed order,
+// so results are bitwise reproducible.
+#include "wx_internal.h"
+#include "wx_mlp_internal.h"
+
+namespace wx {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t f2bf(float x) {
+  uint32_t b = __float_as_uint(x);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return uint16_t(b >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+constexpr int GBM = 64, GBN = 64, GBK = 32, GLD = GBK + 8;  // LDS row stride (bf16 elements)
+
+// Load one 64 x 32 operand tile (rows r0.., k k0..) into LDS as [row][k].
+// KCONTIG: memory is [rows][ld] with k contiguous; else [K][ld] with rows
+// contiguous.  rows_idx optionally indirects the row index (batch gather).
+template <bool KCONTIG>
+__device__ __forceinline__ void load_tile(uint16_t *lds, const uint16_t *g, int ld, int r0, int k0,
+                                          int nrows, int nk, const int *rows_idx) {
+  const int t = threadIdx.x;
+  if (KCONTIG) {
+    const int r = t >> 2, kk = (t & 3) * 8;             // 64 rows x 4 chunks of 8
+    const int gr = r0 + r, gk = k0 + kk;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (gr < nrows && gk < nk) {
+      const int row = rows_idx ? rows_idx[gr] : gr;
+      v = *reinterpret_cast<const uint4 *>(g + (size_t)row * ld + gk);
+    }
+    *reinterpret_cast<uint4 *>(lds + r * GLD + kk) = v;
+  } else {
+    const int kk = t >> 3, r = (t & 7) * 8;             // 32 k x 8 chunks of 8 rows
+    const int gr = r0 + r, gk = k0 + kk;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (gk < nk && gr < nrows) v = *reinterpret_cast<const uint4 *>(g + (size_t)gk * ld + gr);
+    const uint16_t *e = reinterpret_cast<const uint16_t *>(&v);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) lds[(r + q) * GLD + kk] = e[q];
+  }
+}
+
+// Epilogue kinds
+enum { EP_F32 = 0, EP_BIAS_F32 = 1, EP_BIAS_RELU_BF16 = 2, EP_PARTIAL_F32 = 4 };
+
+struct GemmArgs {
+  const uint16_t *A, *B;
+  int lda, ldb;
+  int M, N, K;                 // logical sizes (K = reduction length of this launch's split)
+  int k_split;                 // K elements per split (grid.z splits)
+  const int *rows_a;           // optional row gather for A (KCONTIG only)
+  const float *bias;           // [N]
+  void *C;                     // output
+  int ldc;
+  size_t split_stride;         // EP_PARTIAL_F32: elements between split slices
+};
+
+template <bool AK, bool BK_, int EP>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t sA[2][GBM * GLD];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[2][GBN * GLD];
+  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+  const int kb = blockIdx.z * a.k_split;
+  const int ke = min(a.K, kb + a.k_split);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int nsteps = (ke - kb + GBK - 1) / GBK;
+  if (nsteps > 0) {
+    load_tile<AK>(sA[0], a.A, a.lda, m0, kb, a.M, ke, a.rows_a);
+    load_tile<BK_>(sB[0], a.B, a.ldb, n0, kb, a.N, ke, nullptr);
+  }
+  __syncthreads();
+  for (int s = 0; s < nsteps; ++s) {
+    const int cur = s & 1;
+    if (s + 1 < nsteps) {
+      load_tile<AK>(sA[cur ^ 1], a.A, a.lda, m0, kb + (s + 1) * GBK, a.M, ke, a.rows_a);
+      load_tile<BK_>(sB[cur ^ 1], a.B, a.ldb, n0, kb + (s + 1) * GBK, a.N, ke, nullptr);
+    }
+    const int kl = (lane >> 4) * 8;
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(sA[cur] + (wm + x * 16 + (lane & 15)) * GLD + kl);
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const bf16x8 fb = *reinterpret_cast<const bf16x8 *>(sB[cur] + (wn + y * 16 + (lane & 15)) * GLD + kl);
+        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[x][y], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // lane holds C[4 * (lane / 16) + r][lane % 16] of each 16 x 16 tile
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + x * 16 + 4 * (lane >> 4) + r;
+        const int n = n0 + wn + y * 16 + (lane & 15);
+        if (m >= a.M || n >= a.N) continue;
+        float v = acc[x][y][r];
+        if (EP == EP_F32) {
+          static_cast<float *>(a.C)[(size_t)m * a.ldc + n] = v;
+        } else if (EP == EP_BIAS_F32) {
+          static_cast<float *>(a.C)[(size_t)m * a.ldc + n] = v + a.bias[n];
+        } else if (EP == EP_BIAS_RELU_BF16) {
+          v += a.bias[n];
+          static_cast<uint16_t *>(a.C)[(size_t)m * a.ldc + n] = f2bf(v > 0.f ? v : 0.f);
+        } else {
+          static_cast<float *>(a.C)[blockIdx.z * a.split_stride + (size_t)m * a.ldc + n] = v;
+        }
+      }
+}
+
+// Sum nsplit partial slices in order: out[i] = sum_s part[s][i].
+__global__ void k_sum_splits(const float *part, int nsplit, size_t stride, float *out, size_t n) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int p = 0; p < nsplit; ++p) s += part[p * stride + i];
+  out[i] = s;
+}
+
+// Loss and output gradient: d = 2 (y - t) / (B * nout) on the first nout
+// outputs (0 on padding), as FP32 and BF16; per-row partial loss sums.
+__global__ void k_loss(const float *y, const float *t, const int *rows, int batch, int nout, int ldy,
+                       float *d32, uint16_t *d16, float *row_loss) {
+  const int m = blockIdx.x;
+  const int n = threadIdx.x;                        // 128 threads = padded outputs
+  const int row = rows ? rows[m] : m;
+  float e = 0.f, g = 0.f;
+  if (n < nout) {
+    e = y[(size_t)m * ldy + n] - t[(size_t)row * ldy + n];
+    g = 2.f * e / float(batch * nout);
+  }
+  d32[(size_t)m * ldy + n] = g;
+  d16[(size_t)m * ldy + n] = f2bf(g);
+  __shared__ float sh[128];
+  sh[n] = e * e;
+  __syncthreads();
+  for (int w = 64; w >= 1; w >>= 1) {
+    if (n < w) sh[n] += sh[n + w];
+    __syncthreads();
+  }
+  if (n == 0) row_loss[m] = sh[0];
+}
+
+// Column sums over rows in a fixed order, two levels: chunk partials
+// part[c][col] = sum of rows [c*chunk, (c+1)*chunk), then k_sum_splits.
+__global__ void k_colsum_part(const float *a, int rows, int cols, int lda, int chunk, float *part) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= cols) return;
+  const int r0 = blockIdx.y * chunk, r1 = min(rows, r0 + chunk);
+  float s = 0.f;
+  for (int r = r0; r < r1; ++r) s += a[(size_t)r * lda + col];
+  part[(size_t)blockIdx.y * cols + col] = s;
+}
+
+// Hidden-layer gradient: g = (upstream @ W) * (h > 0) in place (FP32) and its
+// BF16 GEMM operand.
+__global__ void k_mask_round(float *a, const uint16_t *mask, size_t n, uint16_t *out) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float g = bf2f(mask[i]) > 0.f ? a[i] : 0.f;
+  a[i] = g;
+  out[i] = f2bf(g);
+}
+
+// Adam on FP32 master weights; refresh the BF16 copy (and its transpose).
+__global__ void k_adam(float *w, const float *g, float *m, float *v, size_t n, float lr, float bc1,
+                       float bc2, uint16_t *wb, uint16_t *wbt, int rows, int cols) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = 0.9f * m[i] + 0.1f * gi;
+  const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
+  w[i] = wi;
+  if (wb) {
+    const uint16_t h = f2bf(wi);
+    wb[i] = h;
+    if (wbt) {
+      const int r = int(i / cols), c = int(i % cols);
+      wbt[(size_t)c * rows + r] = h;
+    }
+  }
+}
+
+// BF16 copies of FP32 weights (after initialisation or an upload).
+__global__ void k_to_bf16(const float *w, size_t n, uint16_t *wb, uint16_t *wbt, int rows, int cols) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint16_t h = f2bf(w[i]);
+  wb[i] = h;
+  if (wbt) {
+    const int r = int(i / cols), c = int(i % cols);
+    wbt[(size_t)c * rows + r] = h;
+  }
+}
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// He-uniform init of a (fan_out x fan_in) block inside a padded (rows x ld)
+// FP32 matrix; element e = r * fan_in + c draws SplitMix64 of
+// (seed << 32) | (tensor << 28) | e.
+__global__ void k_he_init(float *w, int ld, int fan_out, int fan_in, uint64_t seed, int tensor, float bound) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= fan_out * fan_in) return;
+  const int r = e / fan_in, c = e % fan_in;
+  const uint64_t z = splitmix64((seed << 32) | (uint64_t(tensor) << 28) | uint64_t(e));
+  const float u = float(uint32_t(z >> 40)) * (1.0f / 16777216.0f);
+  w[(size_t)r * ld + c] = (2.0f * u - 1.0f) * bound;
+}
+
+}  // namespace
+
+hipError_t launch_gemm(const GemmSpec &g, hipStream_t s) {
+  GemmArgs a;
+  a.A = g.A; a.B = g.B; a.lda = g.lda; a.ldb = g.ldb;
+  a.M = g.M; a.N = g.N; a.K = g.K;
+  a.k_split = g.splits > 1 ? (g.K + g.splits - 1) / g.splits : g.K;
+  a.k_split = (a.k_split + GBK - 1) / GBK * GBK;
+  a.rows_a = g.rows_a; a.bias = g.bias;
+  a.C = g.C; a.ldc = g.ldc; a.split_stride = g.split_stride;
+  const int splits = g.splits > 1 ? (g.K + a.k_split - 1) / a.k_split : 1;
+  dim3 grid((g.N + GBN - 1) / GBN, (g.M + GBM - 1) / GBM, splits);
+#define WX_G(AK, BK, EP) hipLaunchKernelGGL((k_gemm<AK, BK, EP>), grid, dim3(256), 0, s, a)
+  const int key = (g.a_kcontig ? 1 : 0) | (g.b_kcontig ? 2 : 0);
+  switch (g.epilogue) {
+    case GEMM_BIAS_RELU_BF16:
+      if (key != 3) return hipErrorInvalidValue;
+      WX_G(true, true, EP_BIAS_RELU_BF16);
+      break;
+    case GEMM_BIAS_F32:
+      if (key != 3) return hipErrorInvalidValue;
+      WX_G(true, true, EP_BIAS_F32);
+      break;
+    case GEMM_F32:
+      if (key != 3) return hipErrorInvalidValue;
+      WX_G(true, true, EP_F32);
+      break;
+    case GEMM_PARTIAL_F32:
+      if (key != 0) return hipErrorInvalidValue;
+      WX_G(false, false, EP_PARTIAL_F32);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef WX_G
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_splits(const float *part, int nsplit, size_t stride, float *out, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_splits, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, part, nsplit, stride, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss(const float *y, const float *t, const int *rows, int batch, int nout, int ldy,
+                       float *d32, uint16_t *d16, float *row_loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_loss, dim3(batch), dim3(128), 0, s, y, t, rows, batch, nout, ldy, d32, d16, row_loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float *a, int rows, int cols, int lda, float *part, float *out, hipStream_t s) {
+  const int chunk = 64, nchunk = (rows + chunk - 1) / chunk;
+  hipLaunchKernelGGL(k_colsum_part, dim3((cols + 127) / 128, nchunk), dim3(128), 0, s, a, rows, cols, lda, chunk, part);
+  hipLaunchKernelGGL(k_sum_splits, dim3((cols + 255) / 256), dim3(256), 0, s, part, nchunk, size_t(cols), out,
+                     size_t(cols));
+  return hipGetLastError();
+}
+
+hipError_t launch_mask_round(float *a, const uint16_t *mask, size_t n, uint16_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_mask_round, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, a, mask, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float *w, const float *g, float *m, float *v, size_t n, float lr, float bc1, float bc2,
+                       uint16_t *wb, uint16_t *wbt, int rows, int cols, hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, w, g, m, v, n, lr, bc1, bc2, wb,
+                     wbt, rows, cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float *w, size_t n, uint16_t *wb, uint16_t *wbt, int rows, int cols, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, w, n, wb, wbt, rows, cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_he_init(float *w, int ld, int fan_out, int fan_in, uint64_t seed, int tensor, float bound,
+                          hipStream_t s) {
+  const int n = fan_out * fan_in;
+  hipLaunchKernelGGL(k_he_init, dim3((n + 255) / 256), dim3(256), 0, s, w, ld, fan_out, fan_in, seed, tensor, bound);
+  return hipGetLastError();
+}
+
+}  // namespace wx

@@ -80,6 +80,7 @@ struct Column {
   const PhysArgs<T> &a;
   unsigned g0;      // element offset of level 0 of this column
   int col;          // i + nx j
+  int row;          // output row of the row-major tendency layout
   __device__ __forceinline__ unsigned at(int k) const { return g0 + unsigned(k) * a.g.sk; }
 };
 
@@ -174,9 +175,17 @@ __device__ __forceinline__ void downward(const Column<T> &c, const S &st, Kahan 
     const T heat = f0 * (tr_hi - tr_lo) * fast_rcp(cpa * (r * dzk));
     tr_hi = tr_lo;
     if (MODE == 1) {
-      const unsigned o = unsigned(k * ny + j) * unsigned(nx) + unsigned(i);
-      stg(a.tend_t, o, T(dth) / dt + heat);
-      stg(a.tend_q, o, T(dqq) / dt);
+      if (a.tend_rows) {
+        const unsigned o = unsigned(c.row) * TEND_ROW + unsigned(k);
+        stg(a.tend_t, o, T(dth) / dt + heat);
+        stg(a.tend_t, o + unsigned(nz), T(dqq) / dt);
+        if (k == 0)
+          for (int p = 2 * nz; p < TEND_ROW; ++p) stg(a.tend_t, unsigned(c.row) * TEND_ROW + unsigned(p), T(0));
+      } else {
+        const unsigned o = unsigned(k * ny + j) * unsigned(nx) + unsigned(i);
+        stg(a.tend_t, o, T(dth) / dt + heat);
+        stg(a.tend_q, o, T(dqq) / dt);
+      }
       if (NZC > 0) __builtin_amdgcn_sched_barrier(0);
       continue;
     }
@@ -264,6 +273,7 @@ template <int NZ, int MODE>
 __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
   constexpr int PF = 4;
   extern __shared__ float s_c[];          // [NZ][256]
+  if (a.run_if && *a.run_if == 0) return;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
   const int nbx = (a.g.nx + 63) / 64;
   const int i = (blockIdx.x % nbx) * 64 + tx, j = (blockIdx.x / nbx) * 4 + ty;
@@ -340,7 +350,7 @@ __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
       __builtin_amdgcn_sched_barrier(0);
     }
 
-    const Column<float> c{a, g0, col};
+    const Column<float> c{a, g0, col, col};
     if (rmax > a.tdd) {
       const unsigned ncol = unsigned(a.g.nx) * unsigned(a.g.ny);
       const GlobalStore<double> gs{a.scratch, NZ, ncol, unsigned(col)};
@@ -387,9 +397,17 @@ __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
         tr_hi = tr_lo;
         const unsigned g = gd + unsigned(k) * sk;
         if (MODE == 1) {
-          const unsigned o = unsigned(k * ny + j) * unsigned(nx) + unsigned(i);
-          stg(a.tend_t, o, dth / dt + heat);
-          stg(a.tend_q, o, dqq / dt);
+          if (a.tend_rows) {
+            const unsigned o = unsigned(col) * TEND_ROW + unsigned(k);
+            stg(a.tend_t, o, dth / dt + heat);
+            stg(a.tend_t, o + unsigned(NZ), dqq / dt);
+            if (k == 0)
+              for (int p = 2 * NZ; p < TEND_ROW; ++p) stg(a.tend_t, unsigned(col) * TEND_ROW + unsigned(p), 0.f);
+          } else {
+            const unsigned o = unsigned(k * ny + j) * unsigned(nx) + unsigned(i);
+            stg(a.tend_t, o, dth / dt + heat);
+            stg(a.tend_q, o, dqq / dt);
+          }
         } else {
           const float tn = t + dth + dt * heat;
           const float qn = q + dqq;
@@ -419,16 +437,28 @@ __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
 template <typename T, int MODE>
 __global__ __launch_bounds__(PHYS_BX) void k_physics(PhysArgs<T> a) {
   extern __shared__ unsigned char s_raw[];
-  const int nbx = (a.g.nx + PHYS_BX - 1) / PHYS_BX;
-  const int bi = blockIdx.x % nbx, j = blockIdx.x / nbx;
+  if (a.run_if && *a.run_if == 0) return;
   const int lane = threadIdx.x;
-  const int i = bi * PHYS_BX + lane;
-  const bool active = i < a.g.nx;
+  int i, j, row;
+  bool active;
+  if (a.col_list) {                       // listed columns (tendency rows by slot)
+    row = blockIdx.x * PHYS_BX + lane;
+    active = row < min(*a.n_list, a.list_cap);
+    const int cc = active ? a.col_list[row] : 0;
+    i = cc % a.g.nx;
+    j = cc / a.g.nx;
+  } else {
+    const int nbx = (a.g.nx + PHYS_BX - 1) / PHYS_BX;
+    j = blockIdx.x / nbx;
+    i = (blockIdx.x % nbx) * PHYS_BX + lane;
+    active = i < a.g.nx;
+    row = i + a.g.nx * j;
+  }
   Kahan mass[3];
   Counters cnt;
   int fp64 = 0;
   if (active) {
-    const Column<T> c{a, a.g.origin + unsigned(i) + unsigned(j) * a.g.sj, i + a.g.nx * j};
+    const Column<T> c{a, a.g.origin + unsigned(i) + unsigned(j) * a.g.sj, i + a.g.nx * j, row};
     const unsigned ncol = unsigned(a.g.nx) * unsigned(a.g.ny);
     bool wide;
     if (sizeof(T) == 4) {
@@ -550,6 +580,13 @@ __global__ void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
 
 template <typename T>
 hipError_t launch_physics(const PhysArgs<T> &a, hipStream_t s) {
+  if (a.col_list) {
+    if (a.mode != 1 || a.list_cap <= 0) return hipErrorInvalidValue;
+    const int nb = (a.list_cap + PHYS_BX - 1) / PHYS_BX;
+    const size_t lds = (sizeof(T) == 4 && a.use_lds) ? size_t(3) * a.g.nz * PHYS_BX * sizeof(float) : 0;
+    hipLaunchKernelGGL((k_physics<T, 1>), dim3(nb), dim3(PHYS_BX), lds, s, a);
+    return hipGetLastError();
+  }
   if constexpr (sizeof(T) == 4) {
     const int nb = phys_reg_blocks(a.g.nx, a.g.ny);
     const dim3 blk(64, 4);

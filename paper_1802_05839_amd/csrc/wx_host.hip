@@ -10,6 +10,7 @@
 
 #include "wx.h"
 #include "wx_internal.h"
+#include "wx_mlp_internal.h"
 
 namespace {
 
@@ -33,7 +34,8 @@ int fail(int code, const char *fmt, ...) {
   } while (0)
 
 // Default constants (the readings; see wx_param in wx.h).
-const double kDefaults[WX_PARAM_COUNT] = {1.0 / 256.0, 0.1, 50.0, 0.02, 1004.0, 64.0, 0.0, 1.0};
+const double kDefaults[WX_PARAM_COUNT] = {1.0 / 256.0, 0.1, 50.0, 0.02, 1004.0, 64.0, 0.0, 1.0,
+                                          0.0,         0.05, 100.0, 0.0};
 
 struct Impl {
   std::vector<double> dz;
@@ -129,6 +131,45 @@ int ensure_consts(wx_state *s, hipStream_t st) {
   im->dirty[d] = false;
   im->dirty[1 - d] = true;
   return WX_OK;
+}
+
+// Surrogate workspace: chunk buffers for up to kChunk columns, the judge's
+// sample list (capacity for the current sampling rate), plain tendencies of
+// the sampled columns and a few counters.
+constexpr int kChunk = 262144;
+struct SurrogateLayout {
+  size_t x, h, y, list, bcount, boff, nlist, fallback, tplain, total;
+  int chunk, cap, nblk;
+};
+
+SurrogateLayout surrogate_layout(const wx_state *s) {
+  SurrogateLayout L{};
+  const long long ncol = (long long)s->nx * s->ny;
+  const double rate = impl_of(s)->param[WX_PARAM_JUDGE_RATE];
+  const double mean = double(ncol) / rate;
+  long long cap = (long long)(mean + 10.0 * std::sqrt(mean) + 64.0);
+  if (cap > ncol) cap = ncol;
+  L.cap = int(cap);
+  L.chunk = int(std::min<long long>(ncol, kChunk));
+  const int rows = std::max(L.chunk, L.cap);
+  L.nblk = int((ncol + 255) / 256);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = off;
+    off += align256(bytes);
+    return r;
+  };
+  L.x = take(size_t(rows) * wx::MLP_KIN * 2);
+  L.h = take(wx_mlp_infer_work_bytes(rows));
+  L.y = take(size_t(rows) * wx::MLP_NOUTP * 4);
+  L.list = take(size_t(L.cap) * 4);
+  L.bcount = take(size_t(L.nblk) * 4);
+  L.boff = take(size_t(L.nblk) * 4);
+  L.nlist = take(4);
+  L.fallback = take(4);
+  L.tplain = take(size_t(L.cap) * wx::TEND_ROW * 4);
+  L.total = off;
+  return L;
 }
 
 // Launch-class timing hook used by wx_profile_step.
@@ -248,6 +289,11 @@ struct Plan {
     a.mode = mode;
     a.do_mass = do_mass;
     a.use_lds = (sizeof(T) == 4 && s->nz <= wx::PHYS_LDS_NZ_MAX) ? 1 : 0;
+    a.tend_rows = 0;
+    a.col_list = nullptr;
+    a.n_list = nullptr;
+    a.list_cap = 0;
+    a.run_if = nullptr;
     return a;
   }
 
@@ -278,21 +324,117 @@ struct Plan {
     return tm.end();
   }
 
+  wx::FeatArgs<T> feat_args(uint16_t *out) {
+    wx::FeatArgs<T> a;
+    a.rho = base[0]; a.th = base[1]; a.q = base[2];
+    a.u = static_cast<const T *>(s->u);
+    a.v = static_cast<const T *>(s->v);
+    a.th_s = static_cast<const T *>(s->theta_s);
+    a.q_s = static_cast<const T *>(s->q_s);
+    a.f0 = static_cast<const T *>(s->f0);
+    a.ch = static_cast<const T *>(s->ch);
+    a.g = geom(s);
+    a.theta_off = impl_of(s)->param[WX_PARAM_THETA_OFFSET];
+    a.mode = 1;
+    a.out_f32 = nullptr;
+    a.out_bf16 = out;
+    const unsigned char *b = static_cast<const unsigned char *>(s->mlp);
+    a.mean = reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_X_MEAN));
+    a.inv_std = reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_X_INVSTD));
+    a.c0 = 0;
+    a.nrows = 0;
+    a.list = nullptr;
+    a.n_list = nullptr;
+    return a;
+  }
+
+  // Surrogate physics of step t on the post-dycore state (optionally judged).
+  int surrogate(bool judged, uint64_t t, Timer &tm) {
+    const Impl *im = impl_of(s);
+    const SurrogateLayout L = surrogate_layout(s);
+    unsigned char *w = static_cast<unsigned char *>(s->surrogate_work);
+    uint16_t *xb = reinterpret_cast<uint16_t *>(w + L.x);
+    float *y = reinterpret_cast<float *>(w + L.y);
+    int *list = reinterpret_cast<int *>(w + L.list);
+    int *n_list = reinterpret_cast<int *>(w + L.nlist);
+    int *fallback = reinterpret_cast<int *>(w + L.fallback);
+    float *tplain = reinterpret_cast<float *>(w + L.tplain);
+    const unsigned char *b = static_cast<const unsigned char *>(s->mlp);
+    const float *ymean = reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_Y_MEAN));
+    const float *ystd = reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_Y_STD));
+    const double *sigma = reinterpret_cast<const double *>(b + wx_mlp_offset(WX_MLP_SIGMA64));
+    const uint64_t seed = uint64_t(im->param[WX_PARAM_JUDGE_SEED]);
+    const unsigned rate = unsigned(im->param[WX_PARAM_JUDGE_RATE]);
+    const int ncol = s->nx * s->ny;
+    WX_TRY(tm.begin(6));
+    if (judged) {
+      WX_HIP(wx::launch_sample(ncol, seed, t, rate, reinterpret_cast<int *>(w + L.bcount),
+                               reinterpret_cast<int *>(w + L.boff), n_list, L.cap, list, st));
+      wx::PhysArgs<T> pa = phys_args(1, 0, reinterpret_cast<T *>(tplain), nullptr);
+      pa.tend_rows = 1;
+      pa.col_list = list;
+      pa.n_list = n_list;
+      pa.list_cap = L.cap;
+      WX_HIP(wx::launch_physics<T>(pa, st));
+      wx::FeatArgs<T> fa = feat_args(xb);
+      fa.nrows = L.cap;
+      fa.list = list;
+      fa.n_list = n_list;
+      WX_HIP(wx::launch_features<T>(fa, st));
+      if (int rc = wx_mlp_infer(s->mlp, w + L.h, xb, L.cap, y, st)) return rc;
+      WX_HIP(wx::launch_judge(y, tplain, n_list, L.cap, ymean, ystd, sigma, im->param[WX_PARAM_JUDGE_REL], s->nz,
+                              fallback, s->judge_out, s->flags_out, st));
+    }
+    wx::ApplyArgs<T> aa;
+    aa.th = base[1];
+    aa.q = base[2];
+    aa.g = geom(s);
+    aa.dt = T(s->dt);
+    aa.ymean = ymean;
+    aa.ystd = ystd;
+    aa.fallback = judged ? fallback : nullptr;
+    aa.judged = judged ? 1 : 0;
+    aa.seed = seed;
+    aa.t = t;
+    aa.rate = rate;
+    for (int c0 = 0; c0 < ncol; c0 += L.chunk) {
+      const int n = std::min(L.chunk, ncol - c0);
+      wx::FeatArgs<T> fa = feat_args(xb);
+      fa.c0 = c0;
+      fa.nrows = n;
+      WX_HIP(wx::launch_features<T>(fa, st));
+      if (int rc = wx_mlp_infer(s->mlp, w + L.h, xb, n, y, st)) return rc;
+      WX_HIP(wx::launch_apply_surrogate<T>(aa, y, c0, n, st));
+    }
+    if (judged) {
+      WX_HIP(wx::launch_apply_sampled<T>(aa, tplain, list, n_list, L.cap, st));
+      wx::PhysArgs<T> pa = phys_args(0, 0, nullptr, nullptr);
+      pa.run_if = fallback;
+      WX_HIP(wx::launch_physics<T>(pa, st));
+    }
+    return tm.end();
+  }
+
   int run(int nsteps, Timer &tm) {
     WX_TRY(ensure_consts<T>(s, st));
     WX_HIP(wx::launch_fill_i32(s->flags_out, WX_NFLAGS, 0, st));
     WX_TRY(halo(tm));
-    const int every = int(impl_of(s)->param[WX_PARAM_MASS_EVERY]);
+    Impl *im = impl_of(s);
+    const int every = int(im->param[WX_PARAM_MASS_EVERY]);
     const T dt = T(s->dt);
+    const bool surr = s->phys_mode == WX_PHYS_SURROGATE || s->phys_mode == WX_PHYS_JUDGED;
     for (int n = 1; n <= nsteps; ++n) {
       WX_TRY(stage(1, base, s1, dt / T(3), tm));
       WX_TRY(stage(2, s1, s2, dt / T(2), tm));
       WX_TRY(stage(3, s2, base, dt, tm));
       const int do_mass = every > 0 && (n % every == 0 || n == nsteps);
+      const uint64_t t = uint64_t(im->param[WX_PARAM_STEP]);
+      im->param[WX_PARAM_STEP] = double(t + 1);
       if (s->phys_mode == WX_PHYS_PLAIN) {
         WX_TRY(physics(do_mass, tm));
-      } else if (do_mass) {
-        WX_TRY(mass(tm));
+      } else {
+        if (surr) WX_TRY(surrogate(s->phys_mode == WX_PHYS_JUDGED, t, tm));
+        if (do_mass) WX_TRY(mass(tm));
       }
       if (do_mass) WX_TRY(mass_final(tm));
     }
@@ -302,9 +444,16 @@ struct Plan {
 
 int validate_for_step(wx_state *s) {
   if (!s || !s->impl) return fail(WX_E_INVAL, "state is NULL");
-  WX_TRY(check_fields(s, s->phys_mode == WX_PHYS_PLAIN));
-  if (s->phys_mode != WX_PHYS_OFF && s->phys_mode != WX_PHYS_PLAIN)
+  if (s->phys_mode < WX_PHYS_OFF || s->phys_mode > WX_PHYS_JUDGED)
     return fail(WX_E_UNSUPPORTED, "phys_mode %d is not supported", s->phys_mode);
+  WX_TRY(check_fields(s, s->phys_mode != WX_PHYS_OFF));
+  if (s->phys_mode == WX_PHYS_SURROGATE || s->phys_mode == WX_PHYS_JUDGED) {
+    if (s->dtype != WX_F32) return fail(WX_E_UNSUPPORTED, "the surrogate modes need an FP32 state");
+    if (s->nz != wx::MLP_NZ) return fail(WX_E_UNSUPPORTED, "the surrogate needs nz == %d", wx::MLP_NZ);
+    if (!s->mlp || !s->surrogate_work || !aligned16(s->mlp) || !aligned16(s->surrogate_work))
+      return fail(WX_E_STATE, "surrogate modes need mlp and surrogate_work (16-byte aligned)");
+    if (s->phys_mode == WX_PHYS_JUDGED && !s->judge_out) return fail(WX_E_STATE, "judged mode needs judge_out");
+  }
   return WX_OK;
 }
 
@@ -318,6 +467,13 @@ int run_steps(wx_state *s, int nsteps, hipStream_t st, Timer &tm) {
 }
 
 }  // namespace
+
+namespace wx {
+int set_error(int code, const char *msg) {
+  g_err = msg;
+  return code;
+}
+}  // namespace wx
 
 extern "C" {
 
@@ -387,14 +543,22 @@ size_t wx_workspace_bytes(const wx_state *s, int dtype) {
   return layout(s, dtype == WX_F32 ? 4 : 8).total;
 }
 
+size_t wx_surrogate_work_bytes(const wx_state *s) {
+  if (!s || !s->impl) return 0;
+  return surrogate_layout(s).total;
+}
+
 int wx_set_param(wx_state *s, int param, double value) {
   if (!s || !s->impl) return fail(WX_E_INVAL, "state is NULL");
   if (param < 0 || param >= WX_PARAM_COUNT) return fail(WX_E_INVAL, "unknown param %d", param);
   if (!std::isfinite(value)) return fail(WX_E_INVAL, "param value must be finite");
   if (param == WX_PARAM_CP && !(value > 0)) return fail(WX_E_INVAL, "cp must be > 0");
   if (param != WX_PARAM_THETA_OFFSET && value < 0) return fail(WX_E_INVAL, "param %d must be >= 0", param);
-  if (param == WX_PARAM_MASS_EVERY && value != std::floor(value))
-    return fail(WX_E_INVAL, "mass_every must be an integer");
+  if ((param == WX_PARAM_MASS_EVERY || param == WX_PARAM_JUDGE_SEED || param == WX_PARAM_JUDGE_RATE ||
+       param == WX_PARAM_STEP) && value != std::floor(value))
+    return fail(WX_E_INVAL, "param %d must be an integer", param);
+  if (param == WX_PARAM_JUDGE_SEED && value >= 4294967296.0) return fail(WX_E_INVAL, "judge seed must be < 2^32");
+  if (param == WX_PARAM_JUDGE_RATE && value < 1) return fail(WX_E_INVAL, "judge rate must be >= 1");
   impl_of(s)->param[param] = value;
   return WX_OK;
 }
@@ -468,6 +632,53 @@ int wx_mass(wx_state *s) {
   return p.mass_final(tm);
 }
 
+int wx_features(wx_state *s, int normalized, void *out, const void *blob) {
+  if (!s || !s->impl) return fail(WX_E_INVAL, "state is NULL");
+  if (!out || !aligned16(out)) return fail(WX_E_INVAL, "out is NULL or misaligned");
+  if (normalized && !blob) return fail(WX_E_INVAL, "normalised features need the parameter blob");
+  if (s->nz != wx::MLP_NZ) return fail(WX_E_UNSUPPORTED, "features need nz == %d", wx::MLP_NZ);
+  WX_TRY(check_fields(s, true));
+  hipStream_t st = static_cast<hipStream_t>(s->stream);
+  const unsigned char *b = static_cast<const unsigned char *>(blob);
+  const float *mean = blob ? reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_X_MEAN)) : nullptr;
+  const float *istd = blob ? reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_X_INVSTD)) : nullptr;
+  auto run = [&](auto tag) -> int {
+    using T = decltype(tag);
+    wx::FeatArgs<T> a;
+    a.rho = (const T *)s->rho; a.th = (const T *)s->theta; a.q = (const T *)s->q;
+    a.u = (const T *)s->u; a.v = (const T *)s->v;
+    a.th_s = (const T *)s->theta_s; a.q_s = (const T *)s->q_s; a.f0 = (const T *)s->f0; a.ch = (const T *)s->ch;
+    a.g = geom(s);
+    a.theta_off = impl_of(s)->param[WX_PARAM_THETA_OFFSET];
+    a.mode = normalized ? 1 : 0;
+    a.out_f32 = normalized ? nullptr : static_cast<float *>(out);
+    a.out_bf16 = normalized ? static_cast<uint16_t *>(out) : nullptr;
+    a.mean = mean;
+    a.inv_std = istd;
+    a.c0 = 0;
+    a.nrows = s->nx * s->ny;
+    a.list = nullptr;
+    a.n_list = nullptr;
+    WX_HIP(wx::launch_features<T>(a, st));
+    return WX_OK;
+  };
+  return s->dtype == WX_F32 ? run(float()) : run(double());
+}
+
+int wx_dataset(wx_state *s, float *x_raw, float *y_raw) {
+  if (!s || !s->impl) return fail(WX_E_INVAL, "state is NULL");
+  if (!x_raw || !y_raw || !aligned16(x_raw) || !aligned16(y_raw)) return fail(WX_E_INVAL, "bad output buffers");
+  if (s->dtype != WX_F32) return fail(WX_E_UNSUPPORTED, "wx_dataset needs an FP32 state");
+  WX_TRY(wx_features(s, 0, x_raw, nullptr));
+  hipStream_t st = static_cast<hipStream_t>(s->stream);
+  Plan<float> p(s, st);
+  WX_TRY(ensure_consts<float>(s, st));
+  wx::PhysArgs<float> a = p.phys_args(1, 0, y_raw, nullptr);
+  a.tend_rows = 1;
+  WX_HIP(wx::launch_physics<float>(a, st));
+  return WX_OK;
+}
+
 int wx_profile_step(wx_state *s, int nsteps, void *stream, double *ms_out, int n_out) {
   WX_TRY(validate_for_step(s));
   if (nsteps < 1) return fail(WX_E_INVAL, "nsteps must be >= 1");
@@ -483,7 +694,7 @@ int wx_profile_step(wx_state *s, int nsteps, void *stream, double *ms_out, int n
   int rc = run_steps(s, nsteps, st, tm);
   hipError_t se = hipStreamSynchronize(st);
   double sum[8] = {0};
-  int cnt[8] = {0};
+  int cnt[8] = {0};   // classes: 0 halo, 1-3 stages, 4 physics/mass, 5 mass final, 6 surrogate
   if (rc == WX_OK && se == hipSuccess) {
     for (size_t n = 0; n + 1 < ev.size(); ++n) {
       if (cls[n] < 0 || cls[n + 1] != -1) continue;

@@ -64,6 +64,11 @@ struct PhysArgs {
   int mode;                        // 0: update state, 1: write tendencies
   int do_mass;                     // mode 0: accumulate mass partials
   int use_lds;                     // FP32 elimination stored in LDS
+  int tend_rows;                   // mode 1: rows [col][128] (theta 0..nz-1, q nz..2nz-1, zero pad)
+  const int *col_list;             // mode 1: columns list[s], s < min(*n_list, list_cap); row s
+  const int *n_list;
+  int list_cap;
+  const int *run_if;               // when set, the launch does nothing unless *run_if != 0
 };
 
 template <typename T>
@@ -89,6 +94,7 @@ template <typename T>
 hipError_t launch_mass(const MassArgs<T> &a, hipStream_t s);
 hipError_t launch_mass_final(const double *partials, int nparts, double *out, hipStream_t s);
 hipError_t launch_fill_i32(int *p, int n, int value, hipStream_t s);
+constexpr int TEND_ROW = 128;      // row width of the row-major tendency layout
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 
 inline int stage_tiles_x(int nx) { return (nx + 63) / 64; }

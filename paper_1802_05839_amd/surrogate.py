@@ -1,0 +1,117 @@
+"""Training and evaluation driver of the physics surrogate (host orchestration).
+
+Every numerical step runs in libwx: the dataset rows come from
+``wx_dataset`` (features and plain-physics tendencies of a state), the
+statistics from ``wx_mlp_fit_norm``, the training steps from
+``wx_mlp_train_step`` (BF16 MFMA forward/backward + Adam).  This module only
+decides which states to sample, the seeded batch order and the bookkeeping.
+
+Recipe: states are the plain-method runs on 400 x 320 x 58 grids (one GPU's
+share of the 1581 x 1301 x 58 grid) with seeds 100..103, sampled after 0, 25,
+50 and 75 steps: 16 snapshots x 128,000 columns = 2,048,000 rows.  The
+held-out set is seed 104 after 50 steps.  20 epochs of batch 4096, Adam
+lr 1e-3, shuffle seeded per epoch.
+"""
+from __future__ import annotations
+
+import time
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+from . import inputs, wx
+
+TRAIN_SEEDS = (100, 101, 102, 103)
+SNAPSHOTS = (0, 25, 50, 75)
+HELD_OUT = (104, 50)
+
+
+def build_dataset(seeds: Sequence[int] = TRAIN_SEEDS, snapshots: Sequence[int] = SNAPSHOTS,
+                  nx: int = 400, ny: int = 320, log=None):
+    """Raw (features, targets) device tensors over all seeds and snapshots."""
+    import torch
+    xs, ys = [], []
+    for seed in seeds:
+        inp = inputs.generate(nx, ny, 58, seed=seed, dtype=np.float32)
+        st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
+        done = 0
+        for snap in snapshots:
+            st.step(snap - done)
+            done = snap
+            x, y = st.dataset()
+            xs.append(x)
+            ys.append(y)
+        torch.cuda.synchronize()
+        st.close()
+        if log:
+            log(f"dataset seed {seed}: {len(snapshots)} snapshots")
+    return torch.cat(xs), torch.cat(ys)
+
+
+def train(mlp: "wx.Mlp", x, y, epochs: int = 20, batch: int = 4096, lr: float = 1e-3,
+          shuffle_seed: int = 0, log=None) -> List[float]:
+    """Adam over seeded shuffles; returns the mean training loss of each epoch."""
+    import torch
+    n = int(x.shape[0])
+    nb = n // batch
+    hist = []
+    t = 0
+    dev = x.device
+    for ep in range(epochs):
+        perm = np.random.Generator(np.random.PCG64(np.random.SeedSequence([shuffle_seed, ep]))).permutation(n)
+        rows = torch.from_numpy(perm[: nb * batch].astype(np.int32)).to(dev)
+        total = 0.0
+        for b in range(nb):
+            t += 1
+            mlp.train_step(x, y, rows[b * batch:(b + 1) * batch], lr, t)
+            if b == nb - 1 or b % 50 == 0:
+                total += mlp.last_loss_sum() / (batch * wx.MLP_NOUT) if b == nb - 1 else 0.0
+        hist.append(total)
+        if log:
+            log(f"epoch {ep + 1}: last-batch loss {total:.4f}")
+    return hist
+
+
+def tendency_rmse(mlp: "wx.Mlp", x_raw, y_raw) -> Dict[str, float]:
+    """Held-out RMSE of the surrogate's tendencies against the plain physics.
+
+    Also the zero-tendency baseline and the training-set std of each variable.
+    """
+    import torch
+    xn, _ = mlp.normalize(x_raw)
+    yn = mlp.infer(xn)
+    ym = mlp._sec("y_mean", torch.float32, (wx.MLP_NOUTP,))
+    ys = mlp._sec("y_std", torch.float32, (wx.MLP_NOUTP,))
+    pred = (yn * ys + ym)[:, :wx.MLP_NOUT].double()
+    ref = y_raw[:, :wx.MLP_NOUT].double()
+    nz = wx.MLP_NZ
+    sig = mlp.sigma().cpu().numpy()
+    out = {}
+    for v, sl in (("theta", slice(0, nz)), ("q", slice(nz, 2 * nz))):
+        out[f"rmse_{v}"] = float(torch.sqrt(torch.mean((pred[:, sl] - ref[:, sl]) ** 2)).item())
+        out[f"rmse_zero_{v}"] = float(torch.sqrt(torch.mean(ref[:, sl] ** 2)).item())
+    out["sigma_theta"], out["sigma_q"] = float(sig[0]), float(sig[1])
+    return out
+
+
+def held_out(nx: int = 400, ny: int = 320, seed: int = HELD_OUT[0], steps: int = HELD_OUT[1]):
+    inp = inputs.generate(nx, ny, 58, seed=seed, dtype=np.float32)
+    st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
+    st.step(steps)
+    x, y = st.dataset()
+    st.close()
+    return x, y
+
+
+def fit(mlp: "wx.Mlp", x_raw, y_raw, epochs: int = 20, batch: int = 4096, lr: float = 1e-3,
+        init_seed: int = 1, log=None):
+    """Initialise, normalise and train; returns (loss history, seconds of training)."""
+    import torch
+    mlp.init(init_seed)
+    mlp.fit_norm(x_raw, y_raw)
+    xn, yn = mlp.normalize(x_raw, y_raw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = train(mlp, xn, yn, epochs=epochs, batch=batch, lr=lr, log=log)
+    torch.cuda.synchronize()
+    return hist, time.perf_counter() - t0

@@ -19,15 +19,30 @@ LIB_PATH = os.path.join(_PKG, "libwx.so")
 
 WX_OK, WX_E_INVAL, WX_E_HIP, WX_E_STATE, WX_E_UNSUPPORTED = 0, -1, -2, -3, -4
 WX_F32, WX_F64 = 0, 1
-WX_PHYS_OFF, WX_PHYS_PLAIN = 0, 1
+WX_PHYS_OFF, WX_PHYS_PLAIN, WX_PHYS_SURROGATE, WX_PHYS_JUDGED = 0, 1, 2, 3
 PARAMS = {"gamma4": 0, "k_min": 1, "mix_len": 2, "kappa_q": 3, "cp": 4, "t_dd": 5,
-          "theta_offset": 6, "mass_every": 7}
-FLAG_NAMES = ("nonfinite", "rho_le0", "fp64_columns", "reserved")
+          "theta_offset": 6, "mass_every": 7, "judge_seed": 8, "judge_rel": 9, "judge_rate": 10,
+          "step": 11}
+FLAG_NAMES = ("nonfinite", "rho_le0", "fp64_columns", "fallback_steps")
 HALO = 2
 
 EXPORTS = ("wx_create", "wx_destroy", "wx_last_error", "wx_workspace_bytes", "wx_set_param",
            "wx_get_param", "wx_halo", "wx_step", "wx_physics", "wx_mass", "wx_profile_step",
-           "wx_copy_probe")
+           "wx_copy_probe", "wx_features", "wx_dataset", "wx_mlp_bytes", "wx_mlp_offset",
+           "wx_mlp_init", "wx_mlp_refresh", "wx_mlp_norm_scratch_bytes", "wx_mlp_fit_norm",
+           "wx_mlp_normalize", "wx_mlp_work_bytes", "wx_mlp_forward_backward", "wx_mlp_adam",
+           "wx_mlp_train_step", "wx_mlp_infer_work_bytes", "wx_mlp_infer",
+           "wx_surrogate_work_bytes")
+
+# surrogate network shapes and blob sections (include/wx.h)
+MLP_NZ, MLP_NIN, MLP_KIN, MLP_NHID, MLP_NOUT, MLP_NOUTP = 58, 294, 320, 512, 116, 128
+MLP_SECTIONS = {"W1": 0, "b1": 1, "W2": 2, "b2": 3, "W3": 4, "b3": 5, "grad": 6, "adam_m": 12,
+                "adam_v": 18, "W1_bf16": 24, "W2_bf16": 25, "W3_bf16": 26, "W2T_bf16": 27,
+                "W3T_bf16": 28, "x_mean": 29, "x_invstd": 30, "y_mean": 31, "y_std": 32,
+                "sigma": 33, "sigma64": 34}
+MLP_PARAM_NAMES = ("W1", "b1", "W2", "b2", "W3", "b3")
+MLP_PARAM_SHAPES = {"W1": (MLP_NHID, MLP_KIN), "b1": (MLP_NHID,), "W2": (MLP_NHID, MLP_NHID),
+                    "b2": (MLP_NHID,), "W3": (MLP_NOUTP, MLP_NHID), "b3": (MLP_NOUTP,)}
 
 
 class WxError(RuntimeError):
@@ -49,6 +64,7 @@ class _State(ctypes.Structure):
         ("ch", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p),
         ("mass_out", ctypes.c_void_p), ("flags_out", ctypes.c_void_p),
+        ("mlp", ctypes.c_void_p), ("surrogate_work", ctypes.c_void_p), ("judge_out", ctypes.c_void_p),
         ("impl", ctypes.c_void_p),
     ]
 
@@ -87,8 +103,32 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.wx_profile_step.argtypes = [sp, ctypes.c_int, ctypes.c_void_p,
                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     lib.wx_copy_probe.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    lib.wx_features.argtypes = [sp, ctypes.c_int, vp, vp]
+    lib.wx_dataset.argtypes = [sp, vp, vp]
+    lib.wx_mlp_bytes.argtypes = []
+    lib.wx_mlp_offset.argtypes = [ctypes.c_int]
+    lib.wx_mlp_init.argtypes = [vp, ctypes.c_uint64, vp]
+    lib.wx_mlp_refresh.argtypes = [vp, vp]
+    lib.wx_mlp_norm_scratch_bytes.argtypes = [sz]
+    lib.wx_mlp_fit_norm.argtypes = [vp, vp, vp, sz, vp, vp]
+    lib.wx_mlp_normalize.argtypes = [vp, vp, vp, sz, vp, vp, vp]
+    lib.wx_mlp_work_bytes.argtypes = [ctypes.c_int]
+    lib.wx_mlp_forward_backward.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp, vp]
+    lib.wx_mlp_adam.argtypes = [vp, ctypes.c_float, ctypes.c_int, vp]
+    lib.wx_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, ctypes.c_int,
+                                      vp, vp]
+    lib.wx_mlp_infer_work_bytes.argtypes = [ctypes.c_int]
+    lib.wx_mlp_infer.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp]
+    lib.wx_surrogate_work_bytes.argtypes = [sp]
+    size_returning = {"wx_workspace_bytes", "wx_mlp_bytes", "wx_mlp_norm_scratch_bytes",
+                      "wx_mlp_work_bytes", "wx_mlp_infer_work_bytes", "wx_surrogate_work_bytes"}
     for name in EXPORTS[4:]:
-        if name != "wx_workspace_bytes":
+        if name in size_returning:
+            getattr(lib, name).restype = ctypes.c_size_t
+        elif name == "wx_mlp_offset":
+            getattr(lib, name).restype = ctypes.c_int64
+        else:
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -225,6 +265,25 @@ class State:
     def set_phys_mode(self, mode: int) -> None:
         self._p.contents.phys_mode = int(mode)
 
+    def attach_mlp(self, mlp: "Mlp") -> None:
+        """Use a trained surrogate: sets the blob and allocates the surrogate workspace."""
+        torch = _torch()
+        s = self._p.contents
+        self.mlp = mlp
+        s.mlp = mlp.blob.data_ptr()
+        self.t["surrogate_work"] = torch.zeros(int(self.lib.wx_surrogate_work_bytes(self._p)),
+                                               dtype=torch.uint8, device=self.device)
+        self.t["judge_out"] = torch.zeros(4, dtype=torch.float64, device=self.device)
+        s.surrogate_work = self.t["surrogate_work"].data_ptr()
+        s.judge_out = self.t["judge_out"].data_ptr()
+
+    def judge(self):
+        """(RMSE theta, RMSE q, fallback, sampled columns) of the last judged step."""
+        torch = _torch()
+        torch.cuda.synchronize(self.device)
+        j = self.t["judge_out"].cpu().numpy()
+        return float(j[0]), float(j[1]), bool(j[2]), int(j[3])
+
     def tendencies(self, stream=None):
         """Plain-physics tendencies (dtheta/dt, dq/dt) of the current state, (nz, ny, nx) float64."""
         torch = _torch()
@@ -267,6 +326,31 @@ class State:
                "wx_profile_step")
         return np.array(out[:])
 
+    def features(self, mlp=None, stream=None):
+        """Feature rows of the current state: raw FP32 (mlp None) or normalised BF16."""
+        torch = _torch()
+        self._p.contents.stream = _stream_ptr(stream)
+        n = self.nx * self.ny
+        if mlp is None:
+            out = torch.zeros(n, MLP_KIN, dtype=torch.float32, device=self.device)
+            _check(self.lib.wx_features(self._p, 0, out.data_ptr(), None), "wx_features")
+        else:
+            out = torch.zeros(n, MLP_KIN, dtype=torch.int16, device=self.device)
+            _check(self.lib.wx_features(self._p, 1, out.data_ptr(), mlp.blob.data_ptr()), "wx_features")
+        return out
+
+    def dataset(self, x_raw=None, y_raw=None, stream=None):
+        """(raw features [ncol, 320], plain-physics targets [ncol, 128]) as device tensors."""
+        torch = _torch()
+        self._p.contents.stream = _stream_ptr(stream)
+        n = self.nx * self.ny
+        if x_raw is None:
+            x_raw = torch.zeros(n, MLP_KIN, dtype=torch.float32, device=self.device)
+        if y_raw is None:
+            y_raw = torch.zeros(n, MLP_NOUTP, dtype=torch.float32, device=self.device)
+        _check(self.lib.wx_dataset(self._p, x_raw.data_ptr(), y_raw.data_ptr()), "wx_dataset")
+        return x_raw, y_raw
+
     def close(self) -> None:
         if getattr(self, "_p", None):
             _torch().cuda.synchronize(self.device)
@@ -296,3 +380,113 @@ def state_from_inputs(inp, dtype: str = "f32", phys_mode: int = WX_PHYS_PLAIN,
                device=device)
     st.upload(inp, theta_offset=theta_offset)
     return st
+
+
+def bf16_bits_to_float(t):
+    """Device int16 tensor of BF16 bit patterns -> float32 tensor (exact)."""
+    torch = _torch()
+    return (t.to(torch.int32) << 16).view(torch.float32)
+
+
+class Mlp:
+    """The surrogate's parameter blob (device memory owned here)."""
+
+    def __init__(self, device: str = "cuda:0"):
+        torch = _torch()
+        self.lib = load_library()
+        self.device = torch.device(device)
+        self.blob = torch.zeros(int(self.lib.wx_mlp_bytes()), dtype=torch.uint8, device=self.device)
+        self._work = None
+        self._work_batch = 0
+        self._infer_work = None
+        self._loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+
+    def _sec(self, name: str, dtype, shape):
+        torch = _torch()
+        off = int(self.lib.wx_mlp_offset(MLP_SECTIONS[name] if isinstance(name, str) else name))
+        n = int(np.prod(shape))
+        esize = torch.empty(0, dtype=dtype).element_size()
+        return self.blob[off:off + n * esize].view(dtype).view(*shape)
+
+    def param(self, name: str, kind: str = "param"):
+        """FP32 view of a parameter ("param"), its gradient ("grad") or Adam moment ("adam_m", "adam_v")."""
+        torch = _torch()
+        base = {"param": 0, "grad": 6, "adam_m": 12, "adam_v": 18}[kind]
+        return self._sec(base + MLP_PARAM_NAMES.index(name), torch.float32, MLP_PARAM_SHAPES[name])
+
+    def sigma(self):
+        torch = _torch()
+        return self._sec("sigma64", torch.float64, (2,))
+
+    def init(self, seed: int, stream=None) -> None:
+        _check(self.lib.wx_mlp_init(self.blob.data_ptr(), int(seed), _stream_ptr(stream)), "wx_mlp_init")
+
+    def set_params(self, params: Dict[str, np.ndarray], stream=None) -> None:
+        """Write FP32 weights (unpadded shapes are zero-padded) and refresh the BF16 copies."""
+        torch = _torch()
+        for name, arr in params.items():
+            full = np.zeros(MLP_PARAM_SHAPES[name], dtype=np.float32)
+            full[tuple(slice(0, n) for n in arr.shape)] = arr
+            self.param(name).copy_(torch.from_numpy(full))
+        _check(self.lib.wx_mlp_refresh(self.blob.data_ptr(), _stream_ptr(stream)), "wx_mlp_refresh")
+
+    def fit_norm(self, x_raw, y_raw, stream=None) -> None:
+        torch = _torch()
+        n = x_raw.shape[0]
+        scratch = torch.zeros(int(self.lib.wx_mlp_norm_scratch_bytes(n)), dtype=torch.uint8,
+                              device=self.device)
+        _check(self.lib.wx_mlp_fit_norm(self.blob.data_ptr(), x_raw.data_ptr(), y_raw.data_ptr(), n,
+                                        scratch.data_ptr(), _stream_ptr(stream)), "wx_mlp_fit_norm")
+        torch.cuda.synchronize(self.device)
+
+    def normalize(self, x_raw, y_raw=None, stream=None):
+        torch = _torch()
+        n = x_raw.shape[0]
+        xo = torch.zeros(n, MLP_KIN, dtype=torch.int16, device=self.device)
+        yo = torch.zeros(n, MLP_NOUTP, dtype=torch.float32, device=self.device) if y_raw is not None else None
+        _check(self.lib.wx_mlp_normalize(self.blob.data_ptr(), x_raw.data_ptr(),
+                                         None if y_raw is None else y_raw.data_ptr(), n, xo.data_ptr(),
+                                         None if yo is None else yo.data_ptr(), _stream_ptr(stream)),
+               "wx_mlp_normalize")
+        return xo, yo
+
+    def _ensure_work(self, batch: int):
+        torch = _torch()
+        if self._work is None or self._work_batch < batch:
+            self._work = torch.zeros(int(self.lib.wx_mlp_work_bytes(batch)), dtype=torch.uint8,
+                                     device=self.device)
+            self._work_batch = batch
+
+    def forward_backward(self, x, y, rows, stream=None) -> None:
+        batch = int(rows.shape[0])
+        self._ensure_work(batch)
+        _check(self.lib.wx_mlp_forward_backward(self.blob.data_ptr(), self._work.data_ptr(), x.data_ptr(),
+                                                y.data_ptr(), rows.data_ptr(), batch, self._loss.data_ptr(),
+                                                _stream_ptr(stream)), "wx_mlp_forward_backward")
+
+    def adam(self, lr: float, t: int, stream=None) -> None:
+        _check(self.lib.wx_mlp_adam(self.blob.data_ptr(), float(lr), int(t), _stream_ptr(stream)), "wx_mlp_adam")
+
+    def train_step(self, x, y, rows, lr: float, t: int, stream=None) -> None:
+        batch = int(rows.shape[0])
+        self._ensure_work(batch)
+        _check(self.lib.wx_mlp_train_step(self.blob.data_ptr(), self._work.data_ptr(), x.data_ptr(),
+                                          y.data_ptr(), rows.data_ptr(), batch, float(lr), int(t),
+                                          self._loss.data_ptr(), _stream_ptr(stream)), "wx_mlp_train_step")
+
+    def last_loss_sum(self) -> float:
+        torch = _torch()
+        torch.cuda.synchronize(self.device)
+        return float(self._loss.item())
+
+    def infer(self, x, stream=None):
+        """Normalised outputs [n, 128] FP32 for normalised BF16 inputs x [n, 320]."""
+        torch = _torch()
+        n = int(x.shape[0])
+        need = int(self.lib.wx_mlp_infer_work_bytes(n))
+        if self._infer_work is None or self._infer_work.numel() < need:
+            self._infer_work = torch.zeros(need, dtype=torch.uint8, device=self.device)
+        y = torch.zeros(n, MLP_NOUTP, dtype=torch.float32, device=self.device)
+        _check(self.lib.wx_mlp_infer(self.blob.data_ptr(), self._infer_work.data_ptr(), x.data_ptr(), n,
+                                     y.data_ptr(), _stream_ptr(stream)), "wx_mlp_infer")
+        return y
