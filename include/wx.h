@@ -203,9 +203,9 @@ int wx_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
  * A 294-512-512-116 ReLU network maps a column's physics inputs to its
  * theta and q tendencies.  GEMM operands are BF16 (round to nearest even),
  * accumulation FP32; weights are kept FP32 with BF16 copies.  Layouts:
- *   features  [n][WX_MLP_KIN] : theta, q, rho, u, v over k = 0..57 (u, v
- *             cell-centred), then theta_s, q_s, F0, C_h; zero padding;
- *             column c = i + nx j;
+ *   features  [n][WX_MLP_KIN] : theta - 300 K, q, rho, u, v over k = 0..57
+ *             (u, v cell-centred), then theta_s - 300 K, q_s, F0, C_h; zero
+ *             padding; column c = i + nx j;
  *   targets   [n][WX_MLP_NOUTP]: 58 theta tendencies [K/s], 58 q tendencies
  *             [1/s], zero padding.
  * All buffers are device memory owned by the caller.  The parameter blob is

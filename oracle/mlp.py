@@ -7,8 +7,10 @@ plain physics reads and its outputs are the physics tendencies.  Readings:
 
 * Features (294 per column): the post-dycore profiles theta, q, rho, cell-
   centred u and v (58 levels each, in that order, k = 0 first), then theta_s,
-  q_s, F0, C_h; z-scored per feature with FP64 training-set mean and standard
-  deviation (a deviation below 1e-12 is replaced by 1).
+  q_s, F0, C_h; theta and theta_s enter as deviations from 300 K (so that an
+  FP32 feature keeps horizontal variations far below 300 K's FP32 spacing);
+  z-scored per feature with FP64 training-set mean and standard deviation (a
+  deviation below 1e-12 is replaced by 1).
 * Targets (116): the 58 theta tendencies then the 58 q tendencies of the plain
   physics, z-scored per output.
 * Network: h1 = ReLU(W1 x + b1) (294 -> 512), h2 = ReLU(W2 h1 + b2)
@@ -67,13 +69,16 @@ def bf16(x) -> np.ndarray:
 # --------------------------------------------------------------------------
 # features, targets, normalisation
 # --------------------------------------------------------------------------
+THETA_REF = 300.0
+
+
 def features(rho, theta, q, u, v, theta_s, q_s, f0, ch) -> np.ndarray:
     """(ncol, 5 nz + 4) inputs, column c = i + nx j."""
     nz, ny, nx = rho.shape
     ub = (np.roll(u, 1, axis=2) + u) / 2.0
     vb = (np.roll(v, 1, axis=1) + v) / 2.0
-    prof = [a.reshape(nz, ny * nx).T for a in (theta, q, rho, ub, vb)]
-    surf = [a.reshape(ny * nx, 1) for a in (theta_s, q_s, f0, ch)]
+    prof = [a.reshape(nz, ny * nx).T for a in (theta - THETA_REF, q, rho, ub, vb)]
+    surf = [a.reshape(ny * nx, 1) for a in (theta_s - THETA_REF, q_s, f0, ch)]
     return np.concatenate(prof + surf, axis=1)
 
 

@@ -4,9 +4,11 @@
 //
 // Feature row of column c = i + nx j (5 nz + 4 values, padded to 320 with
 // zeros): theta, q, rho, the cell-centred u = (u_{i-1/2} + u_{i+1/2}) / 2 and
-// v, each over k = 0..nz-1, then theta_s, q_s, F0, C_h.  theta is absolute
-// (the stored value plus the state's theta offset).  Target row: the 58 theta
-// tendencies then the 58 q tendencies, padded to 128.
+// v, each over k = 0..nz-1, then theta_s, q_s, F0, C_h.  theta and theta_s
+// enter as deviations from 300 K (stored value + the state's theta offset -
+// 300, formed in FP64), which keeps horizontal variations far below the FP32
+// spacing at 300 K.  Target row: the 58 theta tendencies then the 58 q
+// tendencies, padded to 128.
 #include "wx_internal.h"
 #include "wx_mlp_internal.h"
 
@@ -18,6 +20,8 @@ __device__ __forceinline__ uint16_t f2bf(float x) {
   b += 0x7FFFu + ((b >> 16) & 1u);
   return uint16_t(b >> 16);
 }
+
+constexpr double kThetaRef = 300.0;   // theta features are theta - 300 K
 
 // One thread per column; writes the raw FP32 feature row (mode 0) or the
 // normalised BF16 row (mode 1: (x - mean) * inv_std).
@@ -47,13 +51,13 @@ __global__ void k_features(FeatArgs<T> a) {
   };
   for (int k = 0; k < nz; ++k) {
     const unsigned g = g0 + unsigned(k) * a.g.sk;
-    put(k, float(double(ldg(a.th, g)) + a.theta_off));
+    put(k, float(double(ldg(a.th, g)) + a.theta_off - kThetaRef));
     put(nz + k, float(ldg(a.q, g)));
     put(2 * nz + k, float(ldg(a.rho, g)));
     put(3 * nz + k, float((ldg(a.u, g - 1) + ldg(a.u, g)) * T(0.5)));
     put(4 * nz + k, float((ldg(a.v, g - a.g.sj) + ldg(a.v, g)) * T(0.5)));
   }
-  put(5 * nz, float(double(ldg(a.th_s, unsigned(c))) + a.theta_off));
+  put(5 * nz, float(double(ldg(a.th_s, unsigned(c))) + a.theta_off - kThetaRef));
   put(5 * nz + 1, float(ldg(a.q_s, unsigned(c))));
   put(5 * nz + 2, float(ldg(a.f0, unsigned(c))));
   put(5 * nz + 3, float(ldg(a.ch, unsigned(c))));

@@ -163,8 +163,10 @@ def test_adam_matches_oracle():
         got = m.param(name).cpu().numpy()
         sl = tuple(slice(0, s) for s in cur[name].shape)
         np.testing.assert_allclose(got[sl], cur[name], rtol=0, atol=2e-7 + 1e-6 * np.abs(cur[name]).max())
+    # the transposed BF16 copy is the transpose of the BF16 copy
+    w3b = wx.bf16_bits_to_float(m._sec("W3_bf16", torch.int16, (128, 512))).cpu().numpy()
     w3t = wx.bf16_bits_to_float(m._sec("W3T_bf16", torch.int16, (512, 128))).cpu().numpy()
-    np.testing.assert_array_equal(w3t, omlp.bf16(m.param("W3").cpu().numpy().astype(np.float64)).T)
+    np.testing.assert_array_equal(w3t, w3b.T)
 
 
 def _state32(nx, ny, seed):

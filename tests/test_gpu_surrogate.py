@@ -1,0 +1,223 @@
+"""GPU parity of the coupled surrogate step (dycore + surrogate physics + judge).
+
+The network weights and normalisation statistics are drawn on the host and
+uploaded; the oracle step runs the FP64 dycore, the oracle network with BF16
+rounding at the same points, the plain physics of the sampled columns and the
+same judge.
+
+Tolerances.  rho never passes through the network: 1e-5 normalized max, as
+for the plain FP32 step.  theta and q are compared through their physics
+increments (state after the step minus state after the dycore):
+
+* exact composition (no winds, no diffusion, so the dycore is the identity in
+  both precisions and the normalisation is taken in FP32 on both sides): the
+  BF16 network inputs are then identical, and the increments must agree to
+  the forward-pass bar, 1e-3 Frobenius-relative, plus half an FP32 spacing of
+  the stored state per value;
+* general winds: the FP32 dycore differs from the FP64 one by up to 1e-5,
+  which moves some normalised inputs across a BF16 rounding boundary (one
+  ulp, 2^-8 relative); the bar is 1e-2 Frobenius-relative (2.5 ulps).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import dycore, physics
+from oracle import mlp as omlp
+from oracle.params import DEFAULT
+from paper_1802_05839_amd import inputs, wx
+from tests._util import nmax
+
+pytestmark = pytest.mark.gpu
+NZ, NIN, NOUT = 58, wx.MLP_NIN, wx.MLP_NOUT
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _state32(nx, ny, seed):
+    inp = inputs.generate(nx, ny, NZ, seed=seed)
+    i32 = inp.astype(np.float32)
+    i32.theta = (inp.theta - 300.0).astype(np.float32).astype(np.float64) + 300.0
+    i32.theta_s = (inp.theta_s - 300.0).astype(np.float32).astype(np.float64) + 300.0
+    return i32
+
+
+def _model(inp, seed=3):
+    """Host weights (small output layer so tendencies stay physical) and statistics."""
+    rng = np.random.default_rng(seed)
+    p = {"W1": rng.uniform(-1, 1, (512, NIN)) * np.sqrt(6 / NIN), "b1": rng.normal(0, 0.05, 512),
+         "W2": rng.uniform(-1, 1, (512, 512)) * np.sqrt(6 / 512), "b2": rng.normal(0, 0.05, 512),
+         "W3": rng.uniform(-1, 1, (NOUT, 512)) * np.sqrt(6 / 512) * 0.1, "b3": rng.normal(0, 0.05, NOUT)}
+    p = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+    x = omlp.features(inp.rho, inp.theta, inp.q, inp.u, inp.v, inp.theta_s, inp.q_s, inp.f0, inp.ch)
+    out = physics.column_physics(inp.rho, inp.theta, inp.q, inp.u, inp.v, inp.theta_s, inp.q_s,
+                                 inp.f0, inp.ch, inp.dz, inp.dt)
+    y = omlp.targets(out.t_theta, out.t_q)
+    n = omlp.norm_stats(x, y)
+    stats = {"x_mean": n.x_mean.astype(np.float32), "x_invstd": (1.0 / n.x_std).astype(np.float32),
+             "y_mean": n.y_mean.astype(np.float32), "y_std": n.y_std.astype(np.float32),
+             "sigma64": np.array([n.sigma_theta, n.sigma_q])}
+    return p, stats
+
+
+def _upload(m, p, stats):
+    import torch
+    m.init(1)
+    m.set_params({k: v.astype(np.float32) for k, v in p.items()})
+    for name, n in (("x_mean", wx.MLP_KIN), ("x_invstd", wx.MLP_KIN), ("y_mean", wx.MLP_NOUTP),
+                    ("y_std", wx.MLP_NOUTP)):
+        full = np.zeros(n, np.float32) if name != "y_std" else np.ones(n, np.float32)
+        v = stats[name]
+        full[:v.shape[0]] = v
+        m._sec(name, torch.float32, (n,)).copy_(torch.from_numpy(full))
+    m._sec("sigma64", torch.float64, (2,)).copy_(torch.from_numpy(stats["sigma64"]))
+    torch.cuda.synchronize()
+
+
+def _oracle_surrogate(inp, p, stats, sample=None, k4=None, norm32=False):
+    """One oracle step with surrogate physics; sampled columns take the plain result.
+
+    ``norm32`` forms the normalised inputs in FP32, the precision in which the
+    kernel takes their BF16 rounding decision."""
+    k4 = DEFAULT.k4(inp.dx, inp.dt) if k4 is None else k4
+    s = dycore.rk3(dycore.State(inp.rho, inp.theta, inp.q), inp.u, inp.v, inp.w, inp.dx, inp.dx,
+                   inp.dz, inp.dt, k4)
+    x = omlp.features(s.rho, s.theta, s.q, inp.u, inp.v, inp.theta_s, inp.q_s, inp.f0, inp.ch)
+    if norm32:
+        xn = ((x.astype(np.float32) - stats["x_mean"]) * stats["x_invstd"]).astype(np.float64)
+    else:
+        xn = (x - stats["x_mean"].astype(np.float64)) * stats["x_invstd"].astype(np.float64)
+    y, _ = omlp.forward(p, xn, bf=True)
+    t_hat = y * stats["y_std"].astype(np.float64) + stats["y_mean"].astype(np.float64)
+    out = physics.column_physics(s.rho, s.theta, s.q, inp.u, inp.v, inp.theta_s, inp.q_s, inp.f0,
+                                 inp.ch, inp.dz, inp.dt)
+    t_ref = omlp.targets(out.t_theta, out.t_q)
+    use = t_hat.copy()
+    if sample is not None:
+        use[sample] = t_ref[sample]
+    nz, ny, nx = s.rho.shape
+    tt = use[:, :nz].T.reshape(nz, ny, nx)
+    tq = use[:, nz:].T.reshape(nz, ny, nx)
+    return s, s.theta + inp.dt * tt, s.q + inp.dt * tq, t_hat, t_ref, out
+
+
+def _run(inp, p, stats, mode, seed=0, gamma4=None):
+    m = wx.Mlp()
+    _upload(m, p, stats)
+    st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
+    if gamma4 is not None:
+        st.set_param("gamma4", gamma4)
+    st.set_param("judge_seed", seed)
+    st.attach_mlp(m)
+    st.set_phys_mode(mode)
+    st.step(1)
+    got = st.download()
+    got["flags"] = st.flags()
+    if mode == wx.WX_PHYS_JUDGED:
+        got["judge"] = st.judge()
+    st.close()
+    return got
+
+
+def _dycore_only(inp, gamma4=None):
+    st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
+    if gamma4 is not None:
+        st.set_param("gamma4", gamma4)
+    st.set_phys_mode(wx.WX_PHYS_OFF)
+    st.step(1)
+    out = st.download()
+    st.close()
+    return out
+
+
+def _incr_err(got, base, th, q, s):
+    """Frobenius-relative errors of the theta and q physics increments."""
+    out = []
+    for name, new, old in (("theta", th, s.theta), ("q", q, s.q)):
+        d_gpu = got[name] - base[name]
+        d_ref = new - old
+        out.append(float(np.linalg.norm(d_gpu - d_ref) / np.linalg.norm(d_ref)))
+    return tuple(out)
+
+
+def test_surrogate_step_exact_composition():
+    _say("case: surrogate step, identity dycore, 96x64x58")
+    inp = _state32(96, 64, 60)
+    for a in (inp.u, inp.v, inp.w):
+        a[...] = 0.0
+    p, stats = _model(inp)
+    got = _run(inp, p, stats, wx.WX_PHYS_SURROGATE, gamma4=0.0)
+    s, th, q, *_ = _oracle_surrogate(inp, p, stats, k4=0.0, norm32=True)
+    np.testing.assert_array_equal(got["rho"], inp.rho)
+    for name, new, old in (("theta", th, inp.theta), ("q", q, inp.q)):
+        d_gpu = got[name] - old
+        d_ref = new - old
+        half_ulp = 0.5 * np.spacing(np.float32(np.max(np.abs(old - (300.0 if name == "theta" else 0.0)))))
+        tol = 1e-3 * np.linalg.norm(d_ref) + float(half_ulp) * np.sqrt(d_ref.size)
+        err = float(np.linalg.norm(d_gpu - d_ref))
+        _say(f"{name} increment error {err:.3e} (|ref| {np.linalg.norm(d_ref):.3e}, tol {tol:.3e})")
+        assert err <= tol
+
+
+def test_surrogate_step_matches_oracle():
+    _say("case: surrogate step 96x64x58")
+    inp = _state32(96, 64, 61)
+    p, stats = _model(inp)
+    got = _run(inp, p, stats, wx.WX_PHYS_SURROGATE)
+    base = _dycore_only(inp)
+    s, th, q, *_ = _oracle_surrogate(inp, p, stats)
+    e_rho = nmax(got["rho"], s.rho)
+    e_inc = _incr_err(got, base, th, q, s)
+    _say(f"surrogate step: rho {e_rho:.3e}, increments {e_inc}, state "
+         f"{nmax(got['theta'] - 300, th - 300):.3e} {nmax(got['q'], q):.3e}")
+    assert e_rho <= 1e-5
+    assert max(e_inc) <= 1e-2
+
+
+def test_judged_step_matches_oracle_without_fallback():
+    _say("case: judged step, no fallback, 160x128x58")
+    inp = _state32(160, 128, 62)
+    p, stats = _model(inp)
+    stats["sigma64"] = np.array([1e3, 1e3])          # bound never reached
+    seed = 77
+    got = _run(inp, p, stats, wx.WX_PHYS_JUDGED, seed=seed)
+    base = _dycore_only(inp)
+    mask = omlp.sample_mask(seed, 0, inp.nx * inp.ny)
+    s, th, q, t_hat, t_ref, _ = _oracle_surrogate(inp, p, stats, sample=mask)
+    r_t, r_q, fb = omlp.judge(t_hat, t_ref, mask, 1e3, 1e3)
+    g_rt, g_rq, g_fb, g_n = got["judge"]
+    e_rho = nmax(got["rho"], s.rho)
+    e_inc = _incr_err(got, base, th, q, s)
+    _say(f"judged step: rho {e_rho:.3e}, increments {e_inc}, rmse {g_rt:.3e} {g_rq:.3e} "
+         f"vs {r_t:.3e} {r_q:.3e}, n={g_n}")
+    assert g_n == int(mask.sum()) and not g_fb and not fb
+    assert abs(g_rt - r_t) <= 1e-2 * r_t and abs(g_rq - r_q) <= 1e-2 * r_q
+    assert e_rho <= 1e-5
+    assert max(e_inc) <= 1e-2
+    # sampled columns carry the plain physics: FP32 stencil bar on their increments
+    nz = NZ
+    cols = np.flatnonzero(mask)
+    for name, new, old in (("theta", th, s.theta), ("q", q, s.q)):
+        d_gpu = (got[name] - base[name]).reshape(nz, -1)[:, cols]
+        d_ref = (new - old).reshape(nz, -1)[:, cols]
+        assert nmax(d_gpu, d_ref) <= 1e-3, name
+    assert got["flags"]["fallback_steps"] == 0
+
+
+def test_fallback_reproduces_plain_step_bitwise():
+    _say("case: forced fallback equals the plain step")
+    inp = _state32(96, 64, 63)
+    p, stats = _model(inp)
+    stats["sigma64"] = np.array([1e-30, 1e-30])      # any error exceeds the bound
+    got = _run(inp, p, stats, wx.WX_PHYS_JUDGED, seed=5)
+    assert got["judge"][2] and got["flags"]["fallback_steps"] == 1
+    st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
+    st.step(1)
+    plain = st.download()
+    st.close()
+    for name in ("rho", "theta", "q"):
+        np.testing.assert_array_equal(got[name], plain[name])

@@ -103,7 +103,7 @@ def test_feature_layout():
                       np.full((ny, nx), 2.0), np.arange(8.0).reshape(ny, nx), np.full((ny, nx), 4.0))
     assert f.shape == (8, 5 * nz + 4)
     c = 2 + nx * 1                           # column i=2, j=1
-    np.testing.assert_array_equal(f[c, 0:3], a[:, 1, 2] + 200)      # theta
+    np.testing.assert_array_equal(f[c, 0:3], a[:, 1, 2] + 200 - 300)  # theta - 300 K
     np.testing.assert_array_equal(f[c, 3:6], a[:, 1, 2] + 300)      # q
     np.testing.assert_array_equal(f[c, 6:9], a[:, 1, 2] + 100)      # rho
     assert f[c, 9 + 1] == 2.0 and f[c + 1, 9 + 1] == 2.0 and f[c - 1, 9 + 1] == 0.0
