@@ -53,6 +53,21 @@ __device__ __forceinline__ T face3(T a, T b, T c) {
   return b + (T(2) * (c - b) + (b - a)) * T(1.0 / 6.0);
 }
 
+// Both faces of a cell along one axis from the five cells m2, m1, c, p1, p2
+// and the wind sign at each face, sharing the four differences:
+//   upper face (c | p1): c + (2 d1 + d0)/6 if the wind is >= 0, else
+//                        p1 - (2 d1 + d2)/6;
+//   lower face (m1 | c): m1 + (2 d0 + dm)/6, else c - (2 d0 + d1)/6.
+// Branch-free; each value is bitwise that of face3 on the same three cells,
+// so the two cells sharing a face compute the same value.
+template <typename T>
+__device__ __forceinline__ void faces3(T m2, T m1, T c, T p1, T p2, bool up_hi, bool up_lo, T &f_hi, T &f_lo) {
+  const T dm = m1 - m2, d0 = c - m1, d1 = p1 - c, d2 = p2 - p1;
+  const T s6 = T(1.0 / 6.0);
+  f_hi = fma(fma(T(2), d1, up_hi ? d0 : d2), up_hi ? s6 : -s6, up_hi ? c : p1);
+  f_lo = fma(fma(T(2), d0, up_lo ? dm : d1), up_lo ? s6 : -s6, up_lo ? m1 : c);
+}
+
 template <typename T>
 __global__ void k_halo(T *f0, T *f1, T *f2, T *f3, T *f4, int nx, int ny, unsigned sj,
                        unsigned sk, unsigned origin) {
@@ -165,10 +180,10 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<T> a) {
       // --- density: face values and mass fluxes
       const T rxm2 = R[-2], rxm1 = R[-1], rxp1 = R[1], rxp2 = R[2];
       const T rym2 = R[-2 * TW], rym1 = R[-TW], ryp1 = R[TW], ryp2 = R[2 * TW];
-      const T rfE = uE >= T(0) ? face3(rxm1, r0, rxp1) : face3(rxp2, rxp1, r0);
-      const T rfW = uW >= T(0) ? face3(rxm2, rxm1, r0) : face3(rxp1, r0, rxm1);
-      const T rfN = vN >= T(0) ? face3(rym1, r0, ryp1) : face3(ryp2, ryp1, r0);
-      const T rfS = vS >= T(0) ? face3(rym2, rym1, r0) : face3(ryp1, r0, rym1);
+      const bool upE = uE >= T(0), upW = uW >= T(0), upN = vN >= T(0), upS = vS >= T(0);
+      T rfE, rfW, rfN, rfS;
+      faces3(rxm2, rxm1, r0, rxp1, rxp2, upE, upW, rfE, rfW);
+      faces3(rym2, rym1, r0, ryp1, ryp2, upN, upS, rfN, rfS);
       T rfT = 0, tfT = 0, qfT = 0;
       const bool top = (k + 1 >= nz);
       const bool centred = (k == 0) || (k + 2 == nz);
@@ -187,9 +202,12 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<T> a) {
           qfT = face3(qp2, qp1, q0);
         }
       }
-      const T fxE = uE * rfE, fxW = uW * rfW, fyN = vN * rfN, fyS = vS * rfS;
+      // mass fluxes, pre-scaled by 1/dx or 1/dz (shared by the three fields;
+      // the neighbour that shares a face computes the same value bitwise)
+      const T FE = uE * rfE * rdx, FW = uW * rfW * rdx, FN = vN * rfN * rdx, FS = vS * rfS * rdx;
       const T fzT = top ? T(0) : wt * rfT;
-      const T div = (fxE - fxW) * rdx + (fyN - fyS) * rdx + (fzT - fzb) * rdz;
+      const T FT = fzT * rdz, FB = fzb * rdz;
+      const T div = ((FE - FW) + (FN - FS)) + (FT - FB);
 
       T br, bt, bq;
       if (STAGE == 1) {
@@ -202,38 +220,46 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<T> a) {
         bq = ldg(a.bs_q, gc);
       }
       const T rnew = br - h * div;
-      const T rinv = fast_rcp(rnew);
+      const T hr = h * fast_rcp(rnew);
 
-      // density at the four horizontal faces (biharmonic weighting)
-      const T rhE = (r0 + rxp1) * T(0.5), rhW = (rxm1 + r0) * T(0.5);
-      const T rhN = (r0 + ryp1) * T(0.5), rhS = (rym1 + r0) * T(0.5);
+      // twice the density at the four horizontal faces, and their sum
+      const T rhE = r0 + rxp1, rhW = rxm1 + r0, rhN = r0 + ryp1, rhS = rym1 + r0;
+      const T rhSum = (rhE + rhW) + (rhN + rhS);
 
-      auto tracer = [&](const T *P, T pc, T pm1, T pp1, T pp2, T fzfT, T fzfB, T base) -> T {
-        (void)pp2;
+      // phi_new = base + h (A + B) / rho_new with
+      //   A = -sum_faces +-F (phi_face - base) / spacing            (increment form)
+      //   B = -div(K4 rho_face grad Lap phi)
+      //     = -(K4 / (2 dx^4)) [sum_nb 2 rho_face L_nb - (sum 2 rho_face) L_c]
+      // where L = (sum of the four neighbours) - 4 phi is dx^2 times the
+      // Laplacian; constant phi gives A = B = 0 exactly.
+      const T cB = k4 * T(0.5) * r2 * r2;
+      auto tracer = [&](const T *P, T pc, T fzfT, T fzfB, T base) -> T {
         const T xm2 = P[-2], xm1 = P[-1], xp1 = P[1], xp2 = P[2];
         const T ym2 = P[-2 * TW], ym1 = P[-TW], yp1 = P[TW], yp2 = P[2 * TW];
         const T dpp = P[TW + 1], dpm = P[-TW + 1], dmp = P[TW - 1], dmm = P[-TW - 1];
-        const T fE = uE >= T(0) ? face3(xm1, pc, xp1) : face3(xp2, xp1, pc);
-        const T fW = uW >= T(0) ? face3(xm2, xm1, pc) : face3(xp1, pc, xm1);
-        const T fN = vN >= T(0) ? face3(ym1, pc, yp1) : face3(yp2, yp1, pc);
-        const T fS = vS >= T(0) ? face3(ym2, ym1, pc) : face3(yp1, pc, ym1);
-        const T ax = (fxE * (fE - base) - fxW * (fW - base)) * rdx;
-        const T ay = (fyN * (fN - base) - fyS * (fS - base)) * rdx;
-        const T az = (fzT * (fzfT - base) - fzb * (fzfB - base)) * rdz;
-        const T A = -(ax + ay + az);
-        const T lc = ((xp1 - T(2) * pc + xm1) + (yp1 - T(2) * pc + ym1)) * r2;
-        const T le = ((xp2 - T(2) * xp1 + pc) + (dpp - T(2) * xp1 + dpm)) * r2;
-        const T lw = ((pc - T(2) * xm1 + xm2) + (dmp - T(2) * xm1 + dmm)) * r2;
-        const T ln = ((dpp - T(2) * yp1 + dmp) + (yp2 - T(2) * yp1 + pc)) * r2;
-        const T ls = ((dpm - T(2) * ym1 + dmm) + (pc - T(2) * ym1 + ym2)) * r2;
-        const T gE = k4 * rhE * (le - lc) * rdx, gW = k4 * rhW * (lc - lw) * rdx;
-        const T gN = k4 * rhN * (ln - lc) * rdx, gS = k4 * rhS * (lc - ls) * rdx;
-        const T B = -((gE - gW) * rdx + (gN - gS) * rdx);
-        (void)pm1; (void)pp1;
-        return base + h * (A + B) * rinv;
+        T fE, fW, fN, fS;
+        faces3(xm2, xm1, pc, xp1, xp2, upE, upW, fE, fW);
+        faces3(ym2, ym1, pc, yp1, yp2, upN, upS, fN, fS);
+        T adv = FE * (fE - base);
+        adv -= FW * (fW - base);
+        adv += FN * (fN - base);
+        adv -= FS * (fS - base);
+        adv += FT * (fzfT - base);
+        adv -= FB * (fzfB - base);
+        const T lc = ((xp1 + xm1) + (yp1 + ym1)) - T(4) * pc;
+        const T le = ((xp2 + pc) + (dpp + dpm)) - T(4) * xp1;
+        const T lw = ((pc + xm2) + (dmp + dmm)) - T(4) * xm1;
+        const T ln = ((dpp + dmp) + (yp2 + pc)) - T(4) * yp1;
+        const T ls = ((dpm + dmm) + (pc + ym2)) - T(4) * ym1;
+        T bs = rhE * le;
+        bs += rhW * lw;
+        bs += rhN * ln;
+        bs += rhS * ls;
+        bs -= rhSum * lc;
+        return base - hr * (adv + cB * bs);
       };
-      const T tnew = tracer(Th, t0, tm1, tp1, tp2, tfT, tfb, bt);
-      const T qnew = tracer(Q, q0, qm1, qp1, qp2, qfT, qfb, bq);
+      const T tnew = tracer(Th, t0, tfT, tfb, bt);
+      const T qnew = tracer(Q, q0, qfT, qfb, bq);
 
       // store the cell and its periodic images in the halo ring
       stg(a.out_r, gc, rnew);
