@@ -5,14 +5,25 @@ physics (section "Architecture-Dependant Parallelization Granularity" treats
 that physics as one column-local operator), so its inputs are exactly what the
 plain physics reads and its outputs are the physics tendencies.  Readings:
 
-* Features (294 per column): the post-dycore profiles theta, q, rho, cell-
-  centred u and v (58 levels each, in that order, k = 0 first), then theta_s,
-  q_s, F0, C_h; theta and theta_s enter as deviations from 300 K (so that an
-  FP32 feature keeps horizontal variations far below 300 K's FP32 spacing);
-  z-scored per feature with FP64 training-set mean and standard deviation (a
-  deviation below 1e-12 is replaced by 1).
+* Features (294 per column): five profiles of 58 values (k = 0 first) built
+  from the post-dycore theta' = theta - 300 K, q and the cell-centred winds
+  (u, v) of the column, then theta_s - 300 K, q_s, F0, C_h:
+    1. theta'_0, then the differences theta'_k - theta'_{k-1};
+    2. q_0, then q_k - q_{k-1};
+    3. the wind speed |(u, v)_0|, then the shear S_k = |(u, v)_k - (u, v)_{k-1}|;
+    4. 0, then S_k (theta'_k - theta'_{k-1});
+    5. 0, then S_k (q_k - q_{k-1}).
+  The implicit diffusion acts on the vertical differences with a coefficient
+  set by the shear (the mixing length closure), and the radiation on q, so
+  these are the quantities the column operator depends on; differences keep
+  their full relative precision when rounded to BF16, where nearly equal
+  neighbouring levels would not.  Each feature is z-scored with the FP64
+  training-set mean and standard deviation (a deviation below 1e-12 is
+  replaced by 1).
 * Targets (116): the 58 theta tendencies then the 58 q tendencies of the plain
-  physics, z-scored per output.
+  physics, centred per output and scaled by the pooled standard deviation of
+  their variable (sigma_theta or sigma_q), so that the training loss weighs
+  every level as the judge's pooled RMSE does.
 * Network: h1 = ReLU(W1 x + b1) (294 -> 512), h2 = ReLU(W2 h1 + b2)
   (512 -> 512), y = W3 h2 + b3 (512 -> 116).  GEMM operands are rounded to
   BF16 (round to nearest, ties to even): x, h1, h2, the weights and the
@@ -72,14 +83,30 @@ def bf16(x) -> np.ndarray:
 THETA_REF = 300.0
 
 
-def features(rho, theta, q, u, v, theta_s, q_s, f0, ch) -> np.ndarray:
-    """(ncol, 5 nz + 4) inputs, column c = i + nx j."""
-    nz, ny, nx = rho.shape
-    ub = (np.roll(u, 1, axis=2) + u) / 2.0
-    vb = (np.roll(v, 1, axis=1) + v) / 2.0
-    prof = [a.reshape(nz, ny * nx).T for a in (theta - THETA_REF, q, rho, ub, vb)]
-    surf = [a.reshape(ny * nx, 1) for a in (theta_s - THETA_REF, q_s, f0, ch)]
-    return np.concatenate(prof + surf, axis=1)
+def features(rho, theta, q, u, v, theta_s, q_s, f0, ch, dtype=np.float64) -> np.ndarray:
+    """(ncol, 5 nz + 4) inputs, column c = i + nx j.
+
+    ``dtype`` is the arithmetic precision of the differences, speeds and
+    products (theta - 300 K is formed in float64 first); rho is not an input."""
+    del rho
+    nz, ny, nx = theta.shape
+    ub = ((np.roll(u, 1, axis=2).astype(dtype) + u.astype(dtype)) * dtype(0.5)).reshape(nz, -1).T
+    vb = ((np.roll(v, 1, axis=1).astype(dtype) + v.astype(dtype)) * dtype(0.5)).reshape(nz, -1).T
+    th = (theta - THETA_REF).astype(dtype).reshape(nz, -1).T
+    qq = q.astype(dtype).reshape(nz, -1).T
+    dth = th[:, 1:] - th[:, :-1]
+    dq = qq[:, 1:] - qq[:, :-1]
+    du = ub[:, 1:] - ub[:, :-1]
+    dv = vb[:, 1:] - vb[:, :-1]
+    shear = np.sqrt(du * du + dv * dv)
+    speed0 = np.sqrt(ub[:, :1] * ub[:, :1] + vb[:, :1] * vb[:, :1])
+    zero = np.zeros_like(speed0)
+    prof = [np.concatenate([th[:, :1], dth], 1), np.concatenate([qq[:, :1], dq], 1),
+            np.concatenate([speed0, shear], 1), np.concatenate([zero, shear * dth], 1),
+            np.concatenate([zero, shear * dq], 1)]
+    surf = [np.asarray(a, dtype=np.float64).reshape(ny * nx, 1).astype(dtype)
+            for a in (theta_s - THETA_REF, q_s, f0, ch)]
+    return np.concatenate(prof + surf, axis=1).astype(np.float64)
 
 
 def targets(t_theta, t_q) -> np.ndarray:
@@ -98,11 +125,13 @@ class Norm(NamedTuple):
 
 
 def norm_stats(x: np.ndarray, y: np.ndarray) -> Norm:
+    """Feature mean / std per column; target mean per output and the pooled std
+    of its variable (outputs 0..nz-1 theta, nz..2nz-1 q)."""
     xs = x.std(axis=0)
-    ys = y.std(axis=0)
     nz = y.shape[1] // 2
-    return Norm(x.mean(axis=0), np.where(xs < 1e-12, 1.0, xs), y.mean(axis=0),
-                np.where(ys < 1e-12, 1.0, ys), float(y[:, :nz].std()), float(y[:, nz:].std()))
+    s_t, s_q = float(y[:, :nz].std()), float(y[:, nz:].std())
+    ys = np.concatenate([np.full(nz, s_t if s_t >= 1e-12 else 1.0), np.full(nz, s_q if s_q >= 1e-12 else 1.0)])
+    return Norm(x.mean(axis=0), np.where(xs < 1e-12, 1.0, xs), y.mean(axis=0), ys, s_t, s_q)
 
 
 # --------------------------------------------------------------------------

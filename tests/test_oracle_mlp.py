@@ -94,20 +94,70 @@ def test_bf16_forward_close_to_exact_forward():
     assert np.linalg.norm(y1 - y0) / np.linalg.norm(y0) < 2e-2
 
 
-def test_feature_layout():
-    nz, ny, nx = 3, 2, 4
-    a = np.arange(nz * ny * nx, dtype=float).reshape(nz, ny, nx)
-    u = np.zeros((nz, ny, nx))
-    u[1, 1, 2] = 4.0                         # east face of cell (i=2, j=1): centre mean 2 at i=2 and i=3
-    f = mlp.features(a + 100, a + 200, a + 300, u, np.zeros_like(u), np.full((ny, nx), 1.0),
-                      np.full((ny, nx), 2.0), np.arange(8.0).reshape(ny, nx), np.full((ny, nx), 4.0))
-    assert f.shape == (8, 5 * nz + 4)
-    c = 2 + nx * 1                           # column i=2, j=1
-    np.testing.assert_array_equal(f[c, 0:3], a[:, 1, 2] + 200 - 300)  # theta - 300 K
-    np.testing.assert_array_equal(f[c, 3:6], a[:, 1, 2] + 300)      # q
-    np.testing.assert_array_equal(f[c, 6:9], a[:, 1, 2] + 100)      # rho
-    assert f[c, 9 + 1] == 2.0 and f[c + 1, 9 + 1] == 2.0 and f[c - 1, 9 + 1] == 0.0
-    np.testing.assert_array_equal(f[:, 5 * nz + 2], np.arange(8.0))  # F0, column order i + nx j
+def _feature_state(seed, nz=6, ny=3, nx=5):
+    rng = np.random.default_rng(seed)
+    sh = (nz, ny, nx)
+    return (np.full(sh, 1.1), 300 + rng.normal(0, 2, sh), rng.uniform(0, 0.02, sh),
+            rng.normal(0, 10, sh), rng.normal(0, 10, sh), 300 + rng.normal(0, 1, (ny, nx)),
+            rng.uniform(0, 0.02, (ny, nx)), np.arange(float(ny * nx)).reshape(ny, nx),
+            np.full((ny, nx), 4.0))
+
+
+def test_feature_profiles_reconstruct_theta_and_q():
+    """Cumulative sums of profiles 1 and 2 give theta - 300 K and q back."""
+    rho, th, q, u, v, ts, qs, f0, ch = _feature_state(1)
+    nz = th.shape[0]
+    f = mlp.features(rho, th, q, u, v, ts, qs, f0, ch)
+    assert f.shape == (th[0].size, 5 * nz + 4)
+    np.testing.assert_allclose(np.cumsum(f[:, :nz], axis=1), (th - 300).reshape(nz, -1).T, atol=1e-12)
+    np.testing.assert_allclose(np.cumsum(f[:, nz:2 * nz], axis=1), q.reshape(nz, -1).T, atol=1e-15)
+    np.testing.assert_array_equal(f[:, 5 * nz + 2], f0.ravel())          # column order i + nx j
+    np.testing.assert_allclose(f[:, 5 * nz], (ts - 300).ravel(), atol=1e-12)
+    np.testing.assert_array_equal(f[:, 5 * nz + 3], 4.0)
+
+
+def test_feature_shear_closed_form_and_invariances():
+    """Linear wind profiles: speed at k = 0 and a constant shear |(a, b)|;
+    a uniform wind added to every level changes only the k = 0 speed; a
+    uniform theta shift changes only the first feature; profiles 4 and 5 are
+    the shear times the theta and q differences."""
+    rho, th, q, _, _, ts, qs, f0, ch = _feature_state(2)
+    nz, ny, nx = th.shape
+    k = np.arange(nz, dtype=float)[:, None, None] * np.ones((1, ny, nx))
+    a, b, c, d = 3.0, -4.0, 6.0, 8.0
+    u, v = a * k + c, b * k + d                 # uniform in i, j: face and centre values agree
+    f = mlp.features(rho, th, q, u, v, ts, qs, f0, ch)
+    sp = f[:, 2 * nz:3 * nz]
+    np.testing.assert_allclose(sp[:, 0], 10.0, rtol=1e-15)          # |(6, 8)|
+    np.testing.assert_allclose(sp[:, 1:], 5.0, rtol=1e-15)          # |(3, -4)|
+    g = mlp.features(rho, th + 7.5, q, u + 20.0, v - 3.0, ts, qs, f0, ch)
+    same = np.ones(f.shape[1], bool)
+    same[[0, 2 * nz]] = False                   # theta'_0 and the k = 0 speed
+    np.testing.assert_allclose(g[:, same], f[:, same], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(g[:, 2 * nz], np.hypot(c + 20.0, d - 3.0), rtol=1e-15)
+    np.testing.assert_allclose(g[:, 0], f[:, 0] + 7.5, rtol=1e-15)
+    np.testing.assert_allclose(f[:, 3 * nz + 1:4 * nz], sp[:, 1:] * f[:, 1:nz], rtol=1e-14)
+    np.testing.assert_allclose(f[:, 4 * nz + 1:5 * nz], sp[:, 1:] * f[:, nz + 1:2 * nz], rtol=1e-14)
+    assert np.all(f[:, 3 * nz] == 0) and np.all(f[:, 4 * nz] == 0)
+
+
+def test_feature_face_staggering():
+    """An east-face u perturbation of cell (i, j) at level k moves the
+    cell-centred wind of cells i and i + 1 only, so only their speed/shear
+    features at levels k and k + 1 change."""
+    rho, th, q, u, v, ts, qs, f0, ch = _feature_state(3)
+    nz, ny, nx = th.shape
+    kk, jj, ii = 2, 1, nx - 1                   # the east face of the last cell wraps to i = 0
+    u2 = u.copy()
+    u2[kk, jj, ii] += 5.0
+    f = mlp.features(rho, th, q, u, v, ts, qs, f0, ch)
+    g = mlp.features(rho, th, q, u2, v, ts, qs, f0, ch)
+    changed = np.argwhere(np.abs(g - f) > 0)
+    cols = {ii + nx * jj, 0 + nx * jj}
+    assert {int(c) for c in changed[:, 0]} == cols
+    levels = {int(x) % nz for x in changed[:, 1]}
+    assert levels == {kk, kk + 1}
+    assert all(2 * nz <= x < 5 * nz for x in changed[:, 1])
 
 
 def test_norm_stats_constant_feature():
@@ -117,6 +167,17 @@ def test_norm_stats_constant_feature():
     assert n.x_std[0] == 1.0 and n.x_mean[0] == 3.0
     assert n.sigma_theta == pytest.approx(np.arange(10.0).std())
     assert n.sigma_q == pytest.approx(2 * np.arange(10.0).std())
+
+
+def test_norm_stats_pooled_target_scale():
+    """Targets share the pooled std of their variable: the std of the whole
+    theta block (all rows and levels), not the per-output std."""
+    rng = np.random.default_rng(4)
+    y = np.concatenate([rng.normal(0, 1, (500, 3)) * [1, 2, 3], rng.normal(5, 1e-3, (500, 3))], 1)
+    n = mlp.norm_stats(rng.normal(size=(500, 2)), y)
+    np.testing.assert_allclose(n.y_std[:3], np.std(y[:, :3].ravel()), rtol=1e-12)
+    np.testing.assert_allclose(n.y_std[3:], np.std(y[:, 3:].ravel()), rtol=1e-12)
+    np.testing.assert_allclose(n.y_mean, y.mean(0), rtol=1e-12)
 
 
 def test_sample_mask_and_judge():
