@@ -8,7 +8,11 @@ scan) + the compensated FP64 mass sums, all in the HIP library.
 
 Prints one JSON line:  metric Mcell-steps/s (interior cells x steps / s),
 the roofline of the dominant kernel (the RK3 stage kernel) and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+oracle timed on a bounded sample of the same workload.  Unless --no-surrogate,
+the line also carries the learned-physics leg: the MLP surrogate trained on
+2,048,000 columns of 400 x 320 x 58 states, its held-out tendency RMSE, and
+surrogate and judged steps on the same grid timed against plain steps, with
+the MFMA roofline of the inference GEMMs.
 
     python bench.py [--gpus 1] [--steps 200] [--warmup 5] [--config full]
 """
@@ -27,6 +31,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0               # dense BF16 matrix-core peak
+# algorithmic network FLOPs per column: 2 (294*512 + 512*512 + 512*116)
+MLP_FLOPS_PER_COL = 2 * (294 * 512 + 512 * 512 + 512 * 116)
 # algorithmic values moved per interior cell (FP32: 4 B each)
 VALUES_STAGE = {1: 9, 2: 12, 3: 12}     # stage input (3) [+ base (3)] + u, v, w + output (3)
 VALUES_PHYSICS = 7                      # rho, theta, q, u, v in; theta, q out
@@ -80,6 +87,122 @@ def cpu_baseline(budget_s: float = 15.0):
                       f"{t:.1f} s"}
 
 
+def surrogate_leg(args, host_inp, stream):
+    """Training, held-out RMSE and coupled-step timing of the physics surrogate."""
+    import torch
+
+    from paper_1802_05839_amd import surrogate, wx
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    out = {}
+    t0 = time.perf_counter()
+    x, y = surrogate.build_dataset(log=log)
+    torch.cuda.synchronize()
+    out["dataset"] = {"rows": int(x.shape[0]),
+                      "states": "400x320x58 seeds 100-103 after " + "/".join(map(str, surrogate.SNAPSHOTS)) + " steps",
+                      "seconds": round(time.perf_counter() - t0, 2)}
+    log(f"dataset {x.shape[0]} rows in {out['dataset']['seconds']} s")
+    mlp = wx.Mlp()
+    hist, train_s = surrogate.fit(mlp, x, y, epochs=args.train_epochs, batch=4096, lr=1e-3, log=log)
+    nsteps = (int(x.shape[0]) // 4096) * args.train_epochs
+    del x, y
+    torch.cuda.empty_cache()
+    held = {}
+    for n, (xh, yh) in surrogate.held_out().items():
+        rm = surrogate.tendency_rmse(mlp, xh, yh)
+        held[f"step{n}"] = {**{k: float(f"{v:.4e}") for k, v in rm.items()},
+                            "rmse_over_sigma_theta": round(rm["rmse_theta"] / rm["sigma_theta"], 4),
+                            "rmse_over_sigma_q": round(rm["rmse_q"] / rm["sigma_q"], 4)}
+        del xh, yh
+    out["train"] = {"epochs": args.train_epochs, "batch": 4096, "adam_steps": nsteps, "lr": 1e-3,
+                    "seconds": round(train_s, 2),
+                    "samples_per_s": round(nsteps * 4096 / train_s, 1),
+                    "TFLOPs": round(3 * MLP_FLOPS_PER_COL * 4096 * nsteps / train_s / 1e12, 1),
+                    "loss_first_epoch": round(hist[0], 5), "loss_last_epoch": round(hist[-1], 5)}
+    out["held_out"] = {"state": "400x320x58 seed 104", "judge_bound_over_sigma": 0.05, **held}
+    log(f"trained {nsteps} steps in {train_s:.1f} s; held-out {out['held_out']}")
+
+    # coupled runs on the benchmark grid: plain, judged and unjudged surrogate
+    nx, ny, nz = host_inp.nx, host_inp.ny, host_inp.nz
+    ncells = nx * ny * nz
+    ncol = nx * ny
+    steps = args.coupled_steps
+    res = {}
+    states = {}
+    for mode_name, mode in (("plain", wx.WX_PHYS_PLAIN), ("judged", wx.WX_PHYS_JUDGED),
+                            ("surrogate", wx.WX_PHYS_SURROGATE)):
+        st = wx.state_from_inputs(host_inp, dtype="f32", theta_offset=300.0)
+        if mode != wx.WX_PHYS_PLAIN:
+            st.attach_mlp(mlp)
+        st.set_phys_mode(mode)
+        n = steps if mode_name != "surrogate" else max(1, steps // 5)
+        rmse = []
+        if mode_name == "judged":
+            # ten blocks so that the judge's RMSE is sampled along the run;
+            # flags count per wx_step call and are summed over the blocks
+            blocks = 10
+            ms = 0.0
+            flags = {}
+            for b in range(blocks):
+                k = n // blocks + (1 if b < n % blocks else 0)
+                ms += timed(lambda: st.step(k))
+                rmse.append(st.judge())
+                for key, val in st.flags().items():
+                    flags[key] = flags.get(key, 0) + val
+        else:
+            ms = timed(lambda: st.step(n))
+            flags = st.flags()
+        r = {"steps": n, "ms_per_step": round(ms / n, 4), "Mcell_steps_per_s": round(ncells * n / ms / 1e3, 1),
+             "flags": flags}
+        if rmse:
+            r["judge_rmse_theta"] = [float(f"{j[0]:.3e}") for j in rmse]
+            r["judge_rmse_q"] = [float(f"{j[1]:.3e}") for j in rmse]
+            r["judge_sampled_columns"] = int(rmse[-1][3])
+            r["fallback_steps"] = flags["fallback_steps"]
+        # the state after exactly n steps, before the profiling steps below
+        if mode_name in ("plain", "judged"):
+            states[mode_name] = {f: st.interior(f).double() for f in ("theta", "q")}
+        if mode != wx.WX_PHYS_PLAIN:
+            prof = dict(zip(wx.PROFILE_CLASSES, st.profile(min(n, args.profile_steps), stream).tolist()))
+            r["per_launch_ms"] = {k: round(v, 4) for k, v in prof.items() if v > 0}
+        res[mode_name] = r
+        st.close()
+        log(f"{mode_name}: {r['ms_per_step']} ms/step")
+    # the judged run against the plain run after the same number of steps
+    # (theta as stored: the deviation from 300 K)
+    div = {}
+    for f in ("theta", "q"):
+        a = states["judged"][f]
+        b = states["plain"][f]
+        div[f] = float(f"{(torch.linalg.norm(a - b) / torch.linalg.norm(b)).item():.3e}")
+    del states
+    res["judged_vs_plain_rel_l2"] = div
+    out["coupled"] = res
+
+    # MFMA roofline of the fused surrogate kernel (one launch over all columns:
+    # feature rows, three BF16 layers, tendency update)
+    prof = res["surrogate"]["per_launch_ms"]
+    fused_ms = prof.get("surrogate", 0.0)
+    if fused_ms > 0:
+        achieved = MLP_FLOPS_PER_COL * ncol / (fused_ms / 1e3) / 1e12
+        out["roofline_mlp"] = {"bound": "mfma", "achieved": round(achieved, 1), "peak": BF16_PEAK_TFLOPS,
+                               "unit": "TFLOP/s", "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
+                               "kernel": "k_surrogate_fused (features + 3 BF16 layers + update)",
+                               "launch_ms": round(fused_ms, 4), "flops_per_column": MLP_FLOPS_PER_COL}
+    out["speed_vs_plain"] = {k: round(res["plain"]["ms_per_step"] / res[k]["ms_per_step"], 3)
+                             for k in ("judged", "surrogate")}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +211,9 @@ def main() -> int:
     ap.add_argument("--config", default="full", choices=["full", "share", "crop", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--train-epochs", type=int, default=120)
+    ap.add_argument("--coupled-steps", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -107,7 +233,6 @@ def main() -> int:
     inp = inputs.generate(nx, ny, nz, seed=cfg["seed"], dtype=np.float32)
     log(f"generated {nx}x{ny}x{nz} in {time.perf_counter() - t0:.1f} s, dt={inp.dt:.4f}")
     st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
-    del inp
     torch.cuda.synchronize()
     log("uploaded")
     stream = torch.cuda.current_stream()
@@ -132,7 +257,7 @@ def main() -> int:
 
     # per-kernel durations with HIP events on the same stream
     prof = st.profile(args.profile_steps, stream)
-    d_halo, d1, d2, d3, d_phys, d_mass = prof.tolist()
+    d_halo, d1, d2, d3, d_phys, d_mass = prof.tolist()[:6]
     stage_bytes = sum(VALUES_STAGE.values()) * 4 * ncells
     stage_ms = d1 + d2 + d3
     achieved = stage_bytes / (stage_ms / 1e3) / 1e9
@@ -184,6 +309,9 @@ def main() -> int:
         "flags": flags,
         "mass": [float(x) for x in mass],
     }
+    if not args.no_surrogate and nz == 58:
+        out["surrogate"] = surrogate_leg(args, inp, stream)
+    del inp
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline()

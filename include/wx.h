@@ -189,8 +189,12 @@ int wx_mass(wx_state *s);
 /* Timing instrument: run nsteps steps like wx_step with a HIP event around
  * every kernel launch (same stream), synchronize, and write the average
  * duration in ms of each launch class to ms_out[0..n_out): 0 halo fill,
- * 1 stage 1, 2 stage 2, 3 stage 3, 4 physics, 5 mass finalisation.  The
- * events themselves add small gaps between launches. */
+ * 1 stage 1, 2 stage 2, 3 stage 3, 4 physics (mass partials when the plain
+ * physics is off), 5 mass finalisation; with the surrogate: 6 judge prelude
+ * (sampling, plain physics and inference of the sampled columns, verdict),
+ * 7 the fused surrogate over all columns, 8 sampled-column apply plus the
+ * fallback physics launch.  Classes that did not run read 0.  The events
+ * themselves add small gaps between launches. */
 int wx_profile_step(wx_state *s, int nsteps, void *stream, double *ms_out, int n_out);
 
 /* Plain device copy kernel of `bytes` (multiple of 16) from src to dst on
@@ -203,9 +207,12 @@ int wx_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
  * A 294-512-512-116 ReLU network maps a column's physics inputs to its
  * theta and q tendencies.  GEMM operands are BF16 (round to nearest even),
  * accumulation FP32; weights are kept FP32 with BF16 copies.  Layouts:
- *   features  [n][WX_MLP_KIN] : theta - 300 K, q, rho, u, v over k = 0..57
- *             (u, v cell-centred), then theta_s - 300 K, q_s, F0, C_h; zero
- *             padding; column c = i + nx j;
+ *   features  [n][WX_MLP_KIN] : five profiles over k = 0..57 from theta' =
+ *             theta - 300 K, q and the cell-centred winds (u, v): theta'_0
+ *             then theta'_k - theta'_{k-1}; q_0 then q_k - q_{k-1}; |(u,v)_0|
+ *             then the shear S_k = |(u,v)_k - (u,v)_{k-1}|; 0 then S_k times
+ *             the theta' difference; 0 then S_k times the q difference; then
+ *             theta_s - 300 K, q_s, F0, C_h; zero padding; column c = i + nx j;
  *   targets   [n][WX_MLP_NOUTP]: 58 theta tendencies [K/s], 58 q tendencies
  *             [1/s], zero padding.
  * All buffers are device memory owned by the caller.  The parameter blob is
@@ -231,7 +238,7 @@ typedef enum wx_mlp_section {
   WX_MLP_W2T_BF16 = 27,  /* W2 transposed [512][512] */
   WX_MLP_W3T_BF16 = 28,  /* W3 transposed [512][128] */
   WX_MLP_X_MEAN = 29, WX_MLP_X_INVSTD = 30,  /* FP32 [320]: feature mean and 1/std (0 on padding) */
-  WX_MLP_Y_MEAN = 31, WX_MLP_Y_STD = 32,     /* FP32 [128]: target mean and std (1 on padding) */
+  WX_MLP_Y_MEAN = 31, WX_MLP_Y_STD = 32,     /* FP32 [128]: target mean and scale (1 on padding) */
   WX_MLP_SIGMA = 33,    /* FP32 [2]: pooled std of the theta and q tendencies */
   WX_MLP_SIGMA64 = 34,  /* FP64 [2]: the same in FP64 */
   WX_MLP_NSECTIONS = 35
@@ -247,9 +254,11 @@ int wx_mlp_init(void *blob, uint64_t seed, void *stream);
 /* Rebuild the BF16 copies from the FP32 weights. */
 int wx_mlp_refresh(void *blob, void *stream);
 
-/* Normalisation: FP64 mean and population std per feature and target over
- * n raw rows (std < 1e-12 is replaced by 1), and the pooled std of the theta
- * and q tendencies; stored in the blob.  scratch: wx_mlp_norm_scratch_bytes(n). */
+/* Normalisation: FP64 mean and population std per feature over n raw rows
+ * (std < 1e-12 is replaced by 1); per target its mean and the pooled std of
+ * its variable (theta tendencies or q tendencies, over all rows and levels),
+ * which is also stored as sigma; all in the blob.
+ * scratch: wx_mlp_norm_scratch_bytes(n). */
 size_t wx_mlp_norm_scratch_bytes(size_t n);
 int wx_mlp_fit_norm(void *blob, const float *x_raw, const float *y_raw, size_t n, void *scratch, void *stream);
 /* x_out [n][320] BF16 = (x - mean) / std; y_out [n][128] FP32 (y may be NULL). */
@@ -273,6 +282,17 @@ int wx_mlp_train_step(void *blob, void *work, const void *x, const float *y, con
  * work: wx_mlp_infer_work_bytes(n). */
 size_t wx_mlp_infer_work_bytes(int n);
 int wx_mlp_infer(const void *blob, void *work, const void *x, int n, float *y_out, void *stream);
+
+/* Fused surrogate inference on columns of the current FP32 state (nz = 58)
+ * on s->stream: row r < n is column cols[r] (device int32; an index outside
+ * 0..nx*ny-1 gives the row of zero features) or column r when cols is NULL
+ * (then n <= nx*ny).  rows_out [n][WX_MLP_NOUTP] (device FP32) receives the
+ * normalised network outputs; the tendencies are rows_out * y_std + y_mean.
+ * The kernel builds the feature rows from the state and the blob's
+ * statistics and runs the three layers without leaving the chip; the outputs
+ * equal wx_features(normalized = 1) followed by wx_mlp_infer bit for bit.
+ * This is the kernel that the surrogate step modes run over every column. */
+int wx_surrogate_rows(wx_state *s, const void *blob, const int32_t *cols, int n, float *rows_out);
 
 /* Feature rows of the current state on s->stream (nz must be 58): raw FP32
  * (normalized = 0, blob unused) or normalised BF16 with the blob's statistics.

@@ -1,0 +1,264 @@
+// Fused surrogate physics: for a tile of 128 columns, one workgroup builds the
+// normalised feature rows, runs the 294-512-512-116 network on the matrix
+// cores and applies the predicted theta and q tendencies to the state, so the
+// activations never leave LDS (the column-local operator of the section on
+// parallelisation granularity, here replaced by the learned model).
+//
+// Work split (8 waves, 512 threads):
+//   features  thread (column = t % 128, part = t / 128); a wave covers 64
+//             consecutive columns of one field level, so state reads coalesce;
+//             part p forms levels [15 p, 15 p + 15) of the five profiles (part
+//             3 also the surface values and the padding);
+//   layers    wave w owns output columns [64 w, 64 w + 64) of the two hidden
+//             layers (8 x 4 tiles of v_mfma_f32_16x16x32_bf16) and [16 w,
+//             16 w + 16) of the output layer; A operands come from LDS, the
+//             BF16 weights stream from global memory (L2-resident, 0.98 MB),
+//             one k-step ahead;
+//   outputs   thread (column, part) updates 29 levels of theta or q with
+//             coalesced read-modify-writes and the periodic halo images.
+// The k order of every dot product (steps of 32 from k = 0, the same lane
+// fragments) equals that of the stand-alone GEMM kernel, so both give
+// bitwise-equal network outputs.
+//
+// LDS (133,120 B, one workgroup per CU): the input tile [128][328] BF16, the
+// hidden tile [128][520] BF16 and the output tile [128][129] FP32 alias one
+// buffer; barriers separate the phases.  Padded row strides keep the 16-byte
+// fragment reads free of bank conflicts.
+#include "wx_internal.h"
+#include "wx_mlp_internal.h"
+
+namespace wx {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int FT = 128;                  // columns per tile
+constexpr int FTHREADS = 512;
+constexpr int XLD = MLP_KIN + 8;         // 328
+constexpr int HLD = MLP_NHID + 8;        // 520
+constexpr int YLD = MLP_NOUTP + 1;       // 129 (FP32)
+constexpr int LDS_BYTES = FT * HLD * 2;  // 133,120
+static_assert(FT * XLD * 2 <= LDS_BYTES, "input tile must fit the shared buffer");
+static_assert(FT * YLD * 4 <= LDS_BYTES, "output tile must fit the shared buffer");
+constexpr double kThetaRef = 300.0;      // theta features are theta - 300 K
+constexpr int kNZ = MLP_NZ;              // levels (the network is built for 58)
+constexpr int kHalf = (kNZ + 1) / 2;     // levels per thread in the update
+constexpr int kPartLev = 15;             // levels per thread in the feature phase
+static_assert(4 * kPartLev >= kNZ, "four parts must cover the column");
+
+// acc[x][y] += A(rows 16x.., k) * B(cols n0 + 16y.., k) over k = 0..K-1.
+// A: LDS [rows][lda]; B: global [N][ldb], k contiguous.
+template <int MT, int NT>
+__device__ __forceinline__ void tile_gemm(f32x4 (&acc)[MT][NT], const uint16_t *A, int lda, const uint16_t *B,
+                                          int ldb, int n0, int K, int lane) {
+  const int kl = (lane >> 4) * 8, rl = lane & 15;
+  const uint16_t *bp = B + (size_t)(n0 + rl) * ldb + kl;
+  bf16x8 bcur[NT], bnext[NT];
+#pragma unroll
+  for (int y = 0; y < NT; ++y) bcur[y] = *reinterpret_cast<const bf16x8 *>(bp + (size_t)y * 16 * ldb);
+#pragma unroll 1
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const int kn = k0 + 32 < K ? k0 + 32 : k0;   // last step reloads its own slice
+#pragma unroll
+    for (int y = 0; y < NT; ++y) bnext[y] = *reinterpret_cast<const bf16x8 *>(bp + (size_t)y * 16 * ldb + kn);
+#pragma unroll
+    for (int x = 0; x < MT; ++x) {
+      const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(A + (x * 16 + rl) * lda + k0 + kl);
+#pragma unroll
+      for (int y = 0; y < NT; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, bcur[y], acc[x][y], 0, 0, 0);
+    }
+#pragma unroll
+    for (int y = 0; y < NT; ++y) bcur[y] = bnext[y];
+  }
+}
+
+// Hidden-layer epilogue: H[m][n] = bf16(relu(acc + b[n])); lane holds rows
+// 4 (lane / 16) + r of each 16 x 16 tile at column lane % 16.
+template <int MT, int NT>
+__device__ __forceinline__ void store_hidden(const f32x4 (&acc)[MT][NT], const float *b, int n0, uint16_t *H,
+                                             int lane) {
+#pragma unroll
+  for (int y = 0; y < NT; ++y) {
+    const int n = n0 + y * 16 + (lane & 15);
+    const float bn = b[n];
+#pragma unroll
+    for (int x = 0; x < MT; ++x)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float v = acc[x][y][r] + bn;
+        H[(x * 16 + 4 * (lane >> 4) + r) * HLD + n] = f2bf(v > 0.f ? v : 0.f);
+      }
+  }
+}
+
+__global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LDS_BYTES];
+  if (a.fallback && *a.fallback) return;
+  const bool rows_mode = a.rows_out != nullptr;
+  const int nrows = rows_mode ? (a.n_list ? min(*a.n_list, a.cap) : a.cap) : a.ncols;
+  const int r0 = blockIdx.x * FT;
+  if (r0 >= nrows) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nx = a.g.nx;
+  uint16_t *X = reinterpret_cast<uint16_t *>(lds);
+  uint16_t *H = reinterpret_cast<uint16_t *>(lds);
+  float *Y = reinterpret_cast<float *>(lds);
+
+  // ---- feature rows -> X ---------------------------------------------------
+  {
+    const int col = tid & (FT - 1), part = tid >> 7;
+    const int r = r0 + col;
+    int c = -1;
+    if (r < nrows) c = rows_mode ? (a.list ? a.list[r] : r) : a.c0 + r;
+    if (c >= nx * a.g.ny) c = -1;                    // not a column: zero row
+    uint16_t *xr = X + col * XLD;
+    auto put = [&](int f, float x) { xr[f] = f2bf((x - a.xmean[f]) * a.xinvstd[f]); };
+    if (c < 0) {
+      for (int f = part; f < MLP_KIN; f += 4) xr[f] = 0;
+    } else {
+      const int i = c % nx, j = c / nx;
+      const unsigned g0 = a.g.origin + unsigned(i) + unsigned(j) * a.g.sj;
+      const unsigned sk = a.g.sk, sj = a.g.sj;
+      // part p builds levels [15 p, 15 p + 15) of all five profiles: it
+      // first loads its levels (and the one below) into registers, so about
+      // 96 independent loads are in flight, then forms the features
+      const int kb = part * kPartLev, ke = min(kNZ, kb + kPartLev);
+      const int k0 = kb > 0 ? kb - 1 : 0;
+      float th[kPartLev + 1], qq[kPartLev + 1], ul[kPartLev + 1], uh[kPartLev + 1], vl[kPartLev + 1],
+          vh[kPartLev + 1];
+#pragma unroll
+      for (int n = 0; n <= kPartLev; ++n) {
+        const int k = k0 + n;
+        if (k < ke) {
+          const unsigned g = g0 + unsigned(k) * sk;
+          th[n] = ldg(a.th, g);
+          qq[n] = ldg(a.q, g);
+          ul[n] = ldg(a.u, g - 1);
+          uh[n] = ldg(a.u, g);
+          vl[n] = ldg(a.v, g - sj);
+          vh[n] = ldg(a.v, g);
+        }
+      }
+      LevelVals prev{};
+#pragma unroll
+      for (int n = 0; n <= kPartLev; ++n) {
+        const int k = k0 + n;
+        if (k >= ke) break;
+        LevelVals cur;
+        cur.th = float(double(th[n]) + a.theta_off - kThetaRef);
+        cur.q = qq[n];
+        cur.u = (ul[n] + uh[n]) * 0.5f;
+        cur.v = (vl[n] + vh[n]) * 0.5f;
+        if (k >= kb) {
+          float fv[5];
+          level_features(k, cur, prev, fv);
+#pragma unroll
+          for (int q5 = 0; q5 < 5; ++q5) put(q5 * kNZ + k, fv[q5]);
+        }
+        prev = cur;
+      }
+      if (part == 3) {
+        put(5 * kNZ, float(double(ldg(a.th_s, unsigned(c))) + a.theta_off - kThetaRef));
+        put(5 * kNZ + 1, ldg(a.q_s, unsigned(c)));
+        put(5 * kNZ + 2, ldg(a.f0, unsigned(c)));
+        put(5 * kNZ + 3, ldg(a.ch, unsigned(c)));
+        for (int f = 5 * kNZ + 4; f < MLP_KIN; ++f) xr[f] = 0;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- hidden layer 1: H = relu(X W1^T + b1) ---------------------------------
+  f32x4 acc[8][4];
+  const int n0 = wave * 64;
+#pragma unroll
+  for (int x = 0; x < 8; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+  tile_gemm<8, 4>(acc, X, XLD, a.w1, MLP_KIN, n0, MLP_KIN, lane);
+  __syncthreads();   // every wave has read X
+  store_hidden<8, 4>(acc, a.b1, n0, H, lane);
+  __syncthreads();
+
+  // ---- hidden layer 2: H = relu(H W2^T + b2) ---------------------------------
+#pragma unroll
+  for (int x = 0; x < 8; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+  tile_gemm<8, 4>(acc, H, HLD, a.w2, MLP_NHID, n0, MLP_NHID, lane);
+  __syncthreads();
+  store_hidden<8, 4>(acc, a.b2, n0, H, lane);
+  __syncthreads();
+
+  // ---- output layer: Y = H W3^T + b3 (normalised tendencies) -----------------
+  f32x4 acc3[8][1];
+#pragma unroll
+  for (int x = 0; x < 8; ++x) acc3[x][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int n3 = wave * 16;
+  tile_gemm<8, 1>(acc3, H, HLD, a.w3, MLP_NHID, n3, MLP_NHID, lane);
+  __syncthreads();
+  {
+    const int n = n3 + (lane & 15);
+    const float bn = a.b3[n];
+#pragma unroll
+    for (int x = 0; x < 8; ++x)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Y[(x * 16 + 4 * (lane >> 4) + r) * YLD + n] = acc3[x][0][r] + bn;
+  }
+  __syncthreads();
+
+  // ---- outputs ----------------------------------------------------------------
+  if (rows_mode) {
+    for (int e = tid; e < FT * MLP_NOUTP; e += FTHREADS) {
+      const int m = e / MLP_NOUTP, o = e % MLP_NOUTP;
+      if (r0 + m < nrows) a.rows_out[(size_t)(r0 + m) * MLP_NOUTP + o] = Y[m * YLD + o];
+    }
+    return;
+  }
+  const int col = tid & (FT - 1), part = tid >> 7;
+  if (r0 + col >= nrows) return;
+  const int c = a.c0 + r0 + col;
+  if (a.judged && judge_sampled(a.seed, a.t, unsigned(c), a.rate)) return;
+  const int ny = a.g.ny;
+  const int i = c % nx, j = c / nx;
+  const unsigned g0 = a.g.origin + unsigned(i) + unsigned(j) * a.g.sj;
+  const int di = i < 2 ? nx : (i >= nx - 2 ? -nx : 0);
+  const int dj = j < 2 ? ny * int(a.g.sj) : (j >= ny - 2 ? -ny * int(a.g.sj) : 0);
+  float *fld = part < 2 ? a.th : a.q;
+  const int kb = (part & 1) ? kHalf : 0;
+  const int nk = (part & 1) ? kNZ - kHalf : kHalf;
+  const int ob = (part < 2 ? 0 : kNZ) + kb;
+  const float *yr = Y + col * YLD + ob;
+  const unsigned gb = g0 + unsigned(kb) * a.g.sk;
+  // all loads before any store: the stores may alias the loads, so a mixed
+  // order would serialise one HBM round trip per level
+  float old[kHalf];
+#pragma unroll
+  for (int k = 0; k < kHalf; ++k)
+    if (k < nk) old[k] = ldg(fld, gb + unsigned(k) * a.g.sk);
+#pragma unroll
+  for (int k = 0; k < kHalf; ++k) {
+    if (k >= nk) break;
+    const float tend = fmaf(yr[k], a.ystd[ob + k], a.ymean[ob + k]);
+    const float nv = fmaf(a.dt, tend, old[k]);
+    const unsigned g = gb + unsigned(k) * a.g.sk;
+    stg(fld, g, nv);
+    if (di != 0) stg(fld, g + di, nv);
+    if (dj != 0) {
+      stg(fld, g + dj, nv);
+      if (di != 0) stg(fld, g + dj + di, nv);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_surrogate_fused(const FusedArgs &a, hipStream_t s) {
+  const int rows = a.rows_out ? a.cap : a.ncols;
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_surrogate_fused, dim3((rows + FT - 1) / FT), dim3(FTHREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace wx

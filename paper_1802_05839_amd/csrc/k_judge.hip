@@ -1,5 +1,5 @@
 // Surrogate step kernels: the sampled-column judge and the application of
-// predicted tendencies.
+// the plain tendencies of the sampled columns.
 //
 // Judge (a reading; the paper has no learned component): at step t column c
 // is sampled when SplitMix64(seed ^ (t << 32) ^ c) mod rate == 0.  The plain
@@ -15,21 +15,10 @@
 namespace wx {
 namespace {
 
-__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
-  uint64_t z = x + 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-__device__ __forceinline__ bool sampled(uint64_t seed, uint64_t t, unsigned c, unsigned rate) {
-  return splitmix64(seed ^ (t << 32) ^ uint64_t(c)) % rate == 0;
-}
-
 // ---- deterministic compaction of the sampled column ids -------------------
 __global__ void k_sample_count(int ncol, uint64_t seed, uint64_t t, unsigned rate, int *block_count) {
   const int c = blockIdx.x * 256 + threadIdx.x;
-  const bool s = c < ncol && sampled(seed, t, unsigned(c), rate);
+  const bool s = c < ncol && judge_sampled(seed, t, unsigned(c), rate);
   const int n = __syncthreads_count(s);
   if (threadIdx.x == 0) block_count[blockIdx.x] = n;
 }
@@ -65,7 +54,7 @@ __global__ void k_sample_write(int ncol, uint64_t seed, uint64_t t, unsigned rat
                                int *list) {
   __shared__ int flags[256];
   const int c = blockIdx.x * 256 + threadIdx.x;
-  const int s = (c < ncol && sampled(seed, t, unsigned(c), rate)) ? 1 : 0;
+  const int s = (c < ncol && judge_sampled(seed, t, unsigned(c), rate)) ? 1 : 0;
   flags[threadIdx.x] = s;
   __syncthreads();
   if (s) {
@@ -78,21 +67,25 @@ __global__ void k_sample_write(int ncol, uint64_t seed, uint64_t t, unsigned rat
 
 // ---- RMSE of the surrogate on the sampled columns, fallback decision -------
 // y_hat: normalised outputs [cap][128]; t_ref: plain tendencies [cap][128].
-__global__ void k_judge(const float *y_hat, const float *t_ref, const int *n_list, int cap, const float *ymean,
-                        const float *ystd, const double *sigma, double rel, int nz, int *fallback,
-                        double *judge_out, int *flags) {
+// Two levels in a fixed order: block b sums the squared errors of the
+// elements e = b * 256 + t + i * (JUDGE_BLOCKS * 256) (tree within the
+// block), then one thread adds the block partials in block order.
+constexpr int JUDGE_BLOCKS = 120;
+
+__global__ void k_judge_part(const float *y_hat, const float *t_ref, const int *n_list, int cap, const float *ymean,
+                             const float *ystd, int nz, double *part) {
   __shared__ double sh[2][256];
   const int t = threadIdx.x;
   const int n = min(*n_list, cap);
+  const long long total = (long long)n * TEND_ROW;
   double e[2] = {0.0, 0.0};
-  for (int s = t; s < n; s += 256)
-    for (int v = 0; v < 2; ++v)
-      for (int k = 0; k < nz; ++k) {
-        const int o = v * nz + k;
-        const double pred = double(y_hat[(size_t)s * TEND_ROW + o]) * ystd[o] + ymean[o];
-        const double d = pred - double(t_ref[(size_t)s * TEND_ROW + o]);
-        e[v] += d * d;
-      }
+  for (long long x = (long long)blockIdx.x * 256 + t; x < total; x += (long long)JUDGE_BLOCKS * 256) {
+    const int o = int(x % TEND_ROW);
+    if (o >= 2 * nz) continue;
+    const double pred = double(y_hat[x]) * ystd[o] + ymean[o];
+    const double d = pred - double(t_ref[x]);
+    e[o >= nz] += d * d;
+  }
   sh[0][t] = e[0];
   sh[1][t] = e[1];
   __syncthreads();
@@ -104,50 +97,33 @@ __global__ void k_judge(const float *y_hat, const float *t_ref, const int *n_lis
     __syncthreads();
   }
   if (t == 0) {
-    const double cnt = double(n) * nz;
-    const double r0 = n > 0 ? sqrt(sh[0][0] / cnt) : 0.0;
-    const double r1 = n > 0 ? sqrt(sh[1][0] / cnt) : 0.0;
-    const int fb = (r0 > rel * sigma[0]) || (r1 > rel * sigma[1]);
-    *fallback = fb;
-    judge_out[0] = r0;
-    judge_out[1] = r1;
-    judge_out[2] = fb;
-    judge_out[3] = n;
-    if (fb) atomicAdd(&flags[3], 1);
+    part[2 * blockIdx.x] = sh[0][0];
+    part[2 * blockIdx.x + 1] = sh[1][0];
   }
 }
 
-// ---- apply tendencies ---------------------------------------------------------
-// Surrogate rows (normalised) for columns [c0, c0 + n): theta += dt T_theta,
-// q += dt T_q, with the periodic halo images; skipped entirely when the
-// fallback flag is set, and per column when the column is sampled (judged).
-template <typename T>
-__global__ void k_apply_surrogate(ApplyArgs<T> a, const float *y, int c0, int n) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  if (a.fallback && *a.fallback) return;
-  const int c = c0 + r;
-  if (a.judged && sampled(a.seed, a.t, unsigned(c), a.rate)) return;
-  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-  const int i = c % nx, j = c / nx;
-  const unsigned g0 = a.g.origin + unsigned(i) + unsigned(j) * a.g.sj;
-  const int di = i < 2 ? nx : (i >= nx - 2 ? -nx : 0);
-  const int dj = j < 2 ? ny * int(a.g.sj) : (j >= ny - 2 ? -ny * int(a.g.sj) : 0);
-  const float *row = y + (size_t)r * TEND_ROW;
-  for (int k = 0; k < nz; ++k) {
-    const unsigned g = g0 + unsigned(k) * a.g.sk;
-    const T tn = ldg(a.th, g) + a.dt * T(row[k] * a.ystd[k] + a.ymean[k]);
-    const T qn = ldg(a.q, g) + a.dt * T(row[nz + k] * a.ystd[nz + k] + a.ymean[nz + k]);
-    stg(a.th, g, tn);
-    stg(a.q, g, qn);
-    if (di != 0) { stg(a.th, g + di, tn); stg(a.q, g + di, qn); }
-    if (dj != 0) {
-      stg(a.th, g + dj, tn); stg(a.q, g + dj, qn);
-      if (di != 0) { stg(a.th, g + dj + di, tn); stg(a.q, g + dj + di, qn); }
-    }
+__global__ void k_judge_final(const double *part, const int *n_list, int cap, const double *sigma, double rel, int nz,
+                              int *fallback, double *judge_out, int *flags) {
+  if (threadIdx.x != 0) return;
+  const int n = min(*n_list, cap);
+  double e0 = 0.0, e1 = 0.0;
+  for (int b = 0; b < JUDGE_BLOCKS; ++b) {
+    e0 += part[2 * b];
+    e1 += part[2 * b + 1];
   }
+  const double cnt = double(n) * nz;
+  const double r0 = n > 0 ? sqrt(e0 / cnt) : 0.0;
+  const double r1 = n > 0 ? sqrt(e1 / cnt) : 0.0;
+  const int fb = (r0 > rel * sigma[0]) || (r1 > rel * sigma[1]);
+  *fallback = fb;
+  judge_out[0] = r0;
+  judge_out[1] = r1;
+  judge_out[2] = fb;
+  judge_out[3] = n;
+  if (fb) atomicAdd(&flags[3], 1);
 }
 
+// ---- apply the plain tendencies of the sampled columns ---------------------
 // Plain tendencies of the sampled columns (rows by slot), unless falling back.
 template <typename T>
 __global__ void k_apply_sampled(ApplyArgs<T> a, const float *tend, const int *list, const int *n_list, int cap) {
@@ -187,18 +163,16 @@ hipError_t launch_sample(int ncol, uint64_t seed, uint64_t t, unsigned rate, int
 }
 
 hipError_t launch_judge(const float *y_hat, const float *t_ref, const int *n_list, int cap, const float *ymean,
-                        const float *ystd, const double *sigma, double rel, int nz, int *fallback, double *judge_out,
-                        int *flags, hipStream_t s) {
-  hipLaunchKernelGGL(k_judge, dim3(1), dim3(256), 0, s, y_hat, t_ref, n_list, cap, ymean, ystd, sigma, rel, nz,
-                     fallback, judge_out, flags);
+                        const float *ystd, const double *sigma, double rel, int nz, double *part, int *fallback,
+                        double *judge_out, int *flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_judge_part, dim3(JUDGE_BLOCKS), dim3(256), 0, s, y_hat, t_ref, n_list, cap, ymean, ystd, nz,
+                     part);
+  hipLaunchKernelGGL(k_judge_final, dim3(1), dim3(64), 0, s, part, n_list, cap, sigma, rel, nz, fallback, judge_out,
+                     flags);
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_apply_surrogate(const ApplyArgs<T> &a, const float *y, int c0, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_apply_surrogate<T>, dim3((n + 127) / 128), dim3(128), 0, s, a, y, c0, n);
-  return hipGetLastError();
-}
+size_t judge_part_bytes() { return size_t(2) * JUDGE_BLOCKS * sizeof(double); }
 
 template <typename T>
 hipError_t launch_apply_sampled(const ApplyArgs<T> &a, const float *tend, const int *list, const int *n_list, int cap,
@@ -207,8 +181,6 @@ hipError_t launch_apply_sampled(const ApplyArgs<T> &a, const float *tend, const 
   return hipGetLastError();
 }
 
-template hipError_t launch_apply_surrogate<float>(const ApplyArgs<float> &, const float *, int, int, hipStream_t);
-template hipError_t launch_apply_surrogate<double>(const ApplyArgs<double> &, const float *, int, int, hipStream_t);
 template hipError_t launch_apply_sampled<float>(const ApplyArgs<float> &, const float *, const int *, const int *, int,
                                                 hipStream_t);
 template hipError_t launch_apply_sampled<double>(const ApplyArgs<double> &, const float *, const int *, const int *,

@@ -27,14 +27,6 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// FP32 -> BF16 bits, round to nearest even (finite inputs).
-__device__ __forceinline__ uint16_t f2bf(float x) {
-  uint32_t b = __float_as_uint(x);
-  b += 0x7FFFu + ((b >> 16) & 1u);
-  return uint16_t(b >> 16);
-}
-__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
-
 constexpr int GBM = 64, GBN = 64, GBK = 32, GLD = GBK + 8;  // LDS row stride (bf16 elements)
 
 // Load one 64 x 32 operand tile (rows r0.., k k0..) into LDS as [row][k].
@@ -230,12 +222,6 @@ __global__ void k_to_bf16(const float *w, size_t n, uint16_t *wb, uint16_t *wbt,
   }
 }
 
-__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
-  uint64_t z = x + 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
 
 // He-uniform init of a (fan_out x fan_in) block inside a padded (rows x ld)
 // FP32 matrix; element e = r * fan_in + c draws SplitMix64 of

@@ -1,27 +1,34 @@
 // Surrogate plumbing kernels: per-column feature rows, FP64 normalisation
-// statistics, normalisation to the network's input/target form, batch
-// gather, and applying predicted tendencies to the state.
+// statistics, normalisation to the network's input/target form, and batch
+// gather.
 //
 // Feature row of column c = i + nx j (5 nz + 4 values, padded to 320 with
-// zeros): theta, q, rho, the cell-centred u = (u_{i-1/2} + u_{i+1/2}) / 2 and
-// v, each over k = 0..nz-1, then theta_s, q_s, F0, C_h.  theta and theta_s
-// enter as deviations from 300 K (stored value + the state's theta offset -
-// 300, formed in FP64), which keeps horizontal variations far below the FP32
-// spacing at 300 K.  Target row: the 58 theta tendencies then the 58 q
-// tendencies, padded to 128.
+// zeros): five profiles over k = 0..nz-1 built from theta' = theta - 300 K
+// (stored value + the state's theta offset - 300, formed in FP64), q and the
+// cell-centred winds u = (u_{i-1/2} + u_{i+1/2}) / 2, v likewise: theta'_0 then
+// theta' differences; q_0 then q differences; the speed at k = 0 then the
+// shear S_k; 0 then S_k times the theta' difference; 0 then S_k times the q
+// difference; then theta_s - 300 K, q_s, F0, C_h.  Target row: the 58 theta
+// tendencies then the 58 q tendencies, padded to 128.
 #include "wx_internal.h"
 #include "wx_mlp_internal.h"
 
 namespace wx {
 namespace {
 
-__device__ __forceinline__ uint16_t f2bf(float x) {
-  uint32_t b = __float_as_uint(x);
-  b += 0x7FFFu + ((b >> 16) & 1u);
-  return uint16_t(b >> 16);
-}
-
 constexpr double kThetaRef = 300.0;   // theta features are theta - 300 K
+
+// One thread per column; writes the raw FP32 feature row (mode 0) or the
+// normalised BF16 row (mode 1: (x - mean) * inv_std).
+template <typename T>
+__device__ __forceinline__ LevelVals level_vals(const FeatArgs<T> &a, unsigned g) {
+  LevelVals l;
+  l.th = float(double(ldg(a.th, g)) + a.theta_off - kThetaRef);
+  l.q = float(ldg(a.q, g));
+  l.u = float((ldg(a.u, g - 1) + ldg(a.u, g)) * T(0.5));
+  l.v = float((ldg(a.v, g - a.g.sj) + ldg(a.v, g)) * T(0.5));
+  return l;
+}
 
 // One thread per column; writes the raw FP32 feature row (mode 0) or the
 // normalised BF16 row (mode 1: (x - mean) * inv_std).
@@ -49,13 +56,14 @@ __global__ void k_features(FeatArgs<T> a) {
     else
       a.out_bf16[(size_t)r * MLP_KIN + f] = f2bf((x - a.mean[f]) * a.inv_std[f]);
   };
+  LevelVals prev{};
   for (int k = 0; k < nz; ++k) {
-    const unsigned g = g0 + unsigned(k) * a.g.sk;
-    put(k, float(double(ldg(a.th, g)) + a.theta_off - kThetaRef));
-    put(nz + k, float(ldg(a.q, g)));
-    put(2 * nz + k, float(ldg(a.rho, g)));
-    put(3 * nz + k, float((ldg(a.u, g - 1) + ldg(a.u, g)) * T(0.5)));
-    put(4 * nz + k, float((ldg(a.v, g - a.g.sj) + ldg(a.v, g)) * T(0.5)));
+    const LevelVals cur = level_vals(a, g0 + unsigned(k) * a.g.sk);
+    float fv[5];
+    level_features(k, cur, prev, fv);
+#pragma unroll
+    for (int p = 0; p < 5; ++p) put(p * nz + k, fv[p]);
+    prev = cur;
   }
   put(5 * nz, float(double(ldg(a.th_s, unsigned(c))) + a.theta_off - kThetaRef));
   put(5 * nz + 1, float(ldg(a.q_s, unsigned(c))));
@@ -93,8 +101,10 @@ __global__ void k_stat_fold(const double *part, int nchunk, int cols, double sca
   out[col] = s * scale;
 }
 
-// Pooled variance of the theta and q tendencies from per-output statistics:
-// sigma_v^2 = mean over the 58 outputs of (var_o + (mean_o - pooled_mean)^2).
+// Statistics to the blob: feature mean and 1 / std, target mean per output,
+// and the pooled std of the theta and q tendencies from the per-output
+// statistics, sigma_v^2 = mean over the 58 outputs of (var_o + (mean_o -
+// pooled_mean)^2), which also scales every target of that variable.
 __global__ void k_norm_finish(const double *xmean, const double *xvar, const double *ymean, const double *yvar,
                               int nin, int nout, float *xm, float *xis, float *ym, float *ys, float *sig,
                               double *sig64) {
@@ -109,9 +119,21 @@ __global__ void k_norm_finish(const double *xmean, const double *xvar, const dou
       xis[f] = 0.f;
     }
   }
+  // pooled std of each variable (every thread computes both, same order)
+  const int h = nout / 2;
+  double pooled[2];
+  for (int var = 0; var < 2; ++var) {
+    const int o0 = var * h;
+    double mu = 0.0;
+    for (int o = 0; o < h; ++o) mu += ymean[o0 + o];
+    mu /= h;
+    double v = 0.0;
+    for (int o = 0; o < h; ++o) v += yvar[o0 + o] + (ymean[o0 + o] - mu) * (ymean[o0 + o] - mu);
+    pooled[var] = sqrt(v / h);
+  }
   for (int o = t; o < MLP_NOUTP; o += blockDim.x) {
     if (o < nout) {
-      const double sd = sqrt(yvar[o]);
+      const double sd = pooled[o < h ? 0 : 1];
       ym[o] = float(ymean[o]);
       ys[o] = float(sd < 1e-12 ? 1.0 : sd);
     } else {
@@ -120,15 +142,8 @@ __global__ void k_norm_finish(const double *xmean, const double *xvar, const dou
     }
   }
   if (t < 2) {
-    const int h = nout / 2, o0 = t * h;
-    double mu = 0.0;
-    for (int o = 0; o < h; ++o) mu += ymean[o0 + o];
-    mu /= h;
-    double v = 0.0;
-    for (int o = 0; o < h; ++o) v += yvar[o0 + o] + (ymean[o0 + o] - mu) * (ymean[o0 + o] - mu);
-    v /= h;
-    sig64[t] = sqrt(v);
-    sig[t] = float(sqrt(v));
+    sig64[t] = pooled[t];
+    sig[t] = float(pooled[t]);
   }
 }
 

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "wx.h"
@@ -133,13 +134,12 @@ int ensure_consts(wx_state *s, hipStream_t st) {
   return WX_OK;
 }
 
-// Surrogate workspace: chunk buffers for up to kChunk columns, the judge's
-// sample list (capacity for the current sampling rate), plain tendencies of
-// the sampled columns and a few counters.
-constexpr int kChunk = 262144;
+// Surrogate workspace: the judge's sample list (capacity for the current
+// sampling rate), the plain tendencies and the network outputs of the sampled
+// columns, and a few counters.
 struct SurrogateLayout {
-  size_t x, h, y, list, bcount, boff, nlist, fallback, tplain, total;
-  int chunk, cap, nblk;
+  size_t list, bcount, boff, nlist, fallback, jpart, tplain, yrows, total;
+  int cap, nblk;
 };
 
 SurrogateLayout surrogate_layout(const wx_state *s) {
@@ -150,8 +150,6 @@ SurrogateLayout surrogate_layout(const wx_state *s) {
   long long cap = (long long)(mean + 10.0 * std::sqrt(mean) + 64.0);
   if (cap > ncol) cap = ncol;
   L.cap = int(cap);
-  L.chunk = int(std::min<long long>(ncol, kChunk));
-  const int rows = std::max(L.chunk, L.cap);
   L.nblk = int((ncol + 255) / 256);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -159,20 +157,52 @@ SurrogateLayout surrogate_layout(const wx_state *s) {
     off += align256(bytes);
     return r;
   };
-  L.x = take(size_t(rows) * wx::MLP_KIN * 2);
-  L.h = take(wx_mlp_infer_work_bytes(rows));
-  L.y = take(size_t(rows) * wx::MLP_NOUTP * 4);
   L.list = take(size_t(L.cap) * 4);
   L.bcount = take(size_t(L.nblk) * 4);
   L.boff = take(size_t(L.nblk) * 4);
   L.nlist = take(4);
   L.fallback = take(4);
+  L.jpart = take(wx::judge_part_bytes());
   L.tplain = take(size_t(L.cap) * wx::TEND_ROW * 4);
+  L.yrows = take(size_t(L.cap) * wx::MLP_NOUTP * 4);
   L.total = off;
   return L;
 }
 
-// Launch-class timing hook used by wx_profile_step.
+// Arguments of the fused surrogate kernel for an FP32 state and a blob.
+wx::FusedArgs fused_args(const wx_state *s, const void *blob) {
+  wx::FusedArgs a{};
+  a.rho = static_cast<const float *>(s->rho);
+  a.th = static_cast<float *>(s->theta);
+  a.q = static_cast<float *>(s->q);
+  a.u = static_cast<const float *>(s->u);
+  a.v = static_cast<const float *>(s->v);
+  a.th_s = static_cast<const float *>(s->theta_s);
+  a.q_s = static_cast<const float *>(s->q_s);
+  a.f0 = static_cast<const float *>(s->f0);
+  a.ch = static_cast<const float *>(s->ch);
+  a.g = geom(s);
+  a.theta_off = impl_of(s)->param[WX_PARAM_THETA_OFFSET];
+  const unsigned char *b = static_cast<const unsigned char *>(blob);
+  a.w1 = reinterpret_cast<const uint16_t *>(b + wx_mlp_offset(WX_MLP_W1_BF16));
+  a.w2 = reinterpret_cast<const uint16_t *>(b + wx_mlp_offset(WX_MLP_W2_BF16));
+  a.w3 = reinterpret_cast<const uint16_t *>(b + wx_mlp_offset(WX_MLP_W3_BF16));
+  a.b1 = reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_B1));
+  a.b2 = reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_B2));
+  a.b3 = reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_B3));
+  a.xmean = reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_X_MEAN));
+  a.xinvstd = reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_X_INVSTD));
+  a.ymean = reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_Y_MEAN));
+  a.ystd = reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_Y_STD));
+  a.dt = float(s->dt);
+  return a;
+}
+
+// Launch-class timing hook used by wx_profile_step.  Classes: 0 halo fill,
+// 1-3 RK3 stages, 4 physics (or mass partials), 5 mass finalisation,
+// 6 judge prelude, 7 fused surrogate, 8 sampled-column apply and fallback
+// physics.
+constexpr int kProfileClasses = 9;
 struct Timer {
   std::vector<hipEvent_t> *ev = nullptr;
   std::vector<int> *cls = nullptr;
@@ -324,41 +354,20 @@ struct Plan {
     return tm.end();
   }
 
-  wx::FeatArgs<T> feat_args(uint16_t *out) {
-    wx::FeatArgs<T> a;
-    a.rho = base[0]; a.th = base[1]; a.q = base[2];
-    a.u = static_cast<const T *>(s->u);
-    a.v = static_cast<const T *>(s->v);
-    a.th_s = static_cast<const T *>(s->theta_s);
-    a.q_s = static_cast<const T *>(s->q_s);
-    a.f0 = static_cast<const T *>(s->f0);
-    a.ch = static_cast<const T *>(s->ch);
-    a.g = geom(s);
-    a.theta_off = impl_of(s)->param[WX_PARAM_THETA_OFFSET];
-    a.mode = 1;
-    a.out_f32 = nullptr;
-    a.out_bf16 = out;
-    const unsigned char *b = static_cast<const unsigned char *>(s->mlp);
-    a.mean = reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_X_MEAN));
-    a.inv_std = reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_X_INVSTD));
-    a.c0 = 0;
-    a.nrows = 0;
-    a.list = nullptr;
-    a.n_list = nullptr;
-    return a;
-  }
-
-  // Surrogate physics of step t on the post-dycore state (optionally judged).
+  // Surrogate physics of step t on the post-dycore state (optionally judged):
+  // judge prelude on the sampled columns, then one fused launch over all
+  // columns, then the plain tendencies of the sampled columns, or the plain
+  // physics everywhere when the judge rejected the step.
   int surrogate(bool judged, uint64_t t, Timer &tm) {
+    if (!std::is_same<T, float>::value) return fail(WX_E_UNSUPPORTED, "the surrogate needs an FP32 state");
     const Impl *im = impl_of(s);
     const SurrogateLayout L = surrogate_layout(s);
     unsigned char *w = static_cast<unsigned char *>(s->surrogate_work);
-    uint16_t *xb = reinterpret_cast<uint16_t *>(w + L.x);
-    float *y = reinterpret_cast<float *>(w + L.y);
     int *list = reinterpret_cast<int *>(w + L.list);
     int *n_list = reinterpret_cast<int *>(w + L.nlist);
     int *fallback = reinterpret_cast<int *>(w + L.fallback);
     float *tplain = reinterpret_cast<float *>(w + L.tplain);
+    float *yrows = reinterpret_cast<float *>(w + L.yrows);
     const unsigned char *b = static_cast<const unsigned char *>(s->mlp);
     const float *ymean = reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_Y_MEAN));
     const float *ystd = reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_Y_STD));
@@ -366,8 +375,8 @@ struct Plan {
     const uint64_t seed = uint64_t(im->param[WX_PARAM_JUDGE_SEED]);
     const unsigned rate = unsigned(im->param[WX_PARAM_JUDGE_RATE]);
     const int ncol = s->nx * s->ny;
-    WX_TRY(tm.begin(6));
     if (judged) {
+      WX_TRY(tm.begin(6));
       WX_HIP(wx::launch_sample(ncol, seed, t, rate, reinterpret_cast<int *>(w + L.bcount),
                                reinterpret_cast<int *>(w + L.boff), n_list, L.cap, list, st));
       wx::PhysArgs<T> pa = phys_args(1, 0, reinterpret_cast<T *>(tplain), nullptr);
@@ -376,43 +385,49 @@ struct Plan {
       pa.n_list = n_list;
       pa.list_cap = L.cap;
       WX_HIP(wx::launch_physics<T>(pa, st));
-      wx::FeatArgs<T> fa = feat_args(xb);
-      fa.nrows = L.cap;
-      fa.list = list;
-      fa.n_list = n_list;
-      WX_HIP(wx::launch_features<T>(fa, st));
-      if (int rc = wx_mlp_infer(s->mlp, w + L.h, xb, L.cap, y, st)) return rc;
-      WX_HIP(wx::launch_judge(y, tplain, n_list, L.cap, ymean, ystd, sigma, im->param[WX_PARAM_JUDGE_REL], s->nz,
-                              fallback, s->judge_out, s->flags_out, st));
+      wx::FusedArgs fr = fused_args(s, s->mlp);
+      fr.list = list;
+      fr.n_list = n_list;
+      fr.cap = L.cap;
+      fr.rows_out = yrows;
+      WX_HIP(wx::launch_surrogate_fused(fr, st));
+      WX_HIP(wx::launch_judge(yrows, tplain, n_list, L.cap, ymean, ystd, sigma, im->param[WX_PARAM_JUDGE_REL],
+                              s->nz, reinterpret_cast<double *>(w + L.jpart), fallback, s->judge_out,
+                              s->flags_out, st));
+      WX_TRY(tm.end());
     }
-    wx::ApplyArgs<T> aa;
-    aa.th = base[1];
-    aa.q = base[2];
-    aa.g = geom(s);
-    aa.dt = T(s->dt);
-    aa.ymean = ymean;
-    aa.ystd = ystd;
-    aa.fallback = judged ? fallback : nullptr;
-    aa.judged = judged ? 1 : 0;
-    aa.seed = seed;
-    aa.t = t;
-    aa.rate = rate;
-    for (int c0 = 0; c0 < ncol; c0 += L.chunk) {
-      const int n = std::min(L.chunk, ncol - c0);
-      wx::FeatArgs<T> fa = feat_args(xb);
-      fa.c0 = c0;
-      fa.nrows = n;
-      WX_HIP(wx::launch_features<T>(fa, st));
-      if (int rc = wx_mlp_infer(s->mlp, w + L.h, xb, n, y, st)) return rc;
-      WX_HIP(wx::launch_apply_surrogate<T>(aa, y, c0, n, st));
-    }
+    wx::FusedArgs fa = fused_args(s, s->mlp);
+    fa.c0 = 0;
+    fa.ncols = ncol;
+    fa.fallback = judged ? fallback : nullptr;
+    fa.judged = judged ? 1 : 0;
+    fa.seed = seed;
+    fa.t = t;
+    fa.rate = rate;
+    WX_TRY(tm.begin(7));
+    WX_HIP(wx::launch_surrogate_fused(fa, st));
+    WX_TRY(tm.end());
     if (judged) {
+      wx::ApplyArgs<T> aa;
+      aa.th = base[1];
+      aa.q = base[2];
+      aa.g = geom(s);
+      aa.dt = T(s->dt);
+      aa.ymean = ymean;
+      aa.ystd = ystd;
+      aa.fallback = fallback;
+      aa.judged = 1;
+      aa.seed = seed;
+      aa.t = t;
+      aa.rate = rate;
+      WX_TRY(tm.begin(8));
       WX_HIP(wx::launch_apply_sampled<T>(aa, tplain, list, n_list, L.cap, st));
       wx::PhysArgs<T> pa = phys_args(0, 0, nullptr, nullptr);
       pa.run_if = fallback;
       WX_HIP(wx::launch_physics<T>(pa, st));
+      WX_TRY(tm.end());
     }
-    return tm.end();
+    return WX_OK;
   }
 
   int run(int nsteps, Timer &tm) {
@@ -665,6 +680,24 @@ int wx_features(wx_state *s, int normalized, void *out, const void *blob) {
   return s->dtype == WX_F32 ? run(float()) : run(double());
 }
 
+int wx_surrogate_rows(wx_state *s, const void *blob, const int32_t *cols, int n, float *rows_out) {
+  if (!s || !s->impl) return fail(WX_E_INVAL, "state is NULL");
+  if (!blob || !rows_out || !aligned16(blob) || !aligned16(rows_out))
+    return fail(WX_E_INVAL, "blob and rows_out must be non-NULL and 16-byte aligned");
+  if (s->dtype != WX_F32) return fail(WX_E_UNSUPPORTED, "the surrogate needs an FP32 state");
+  if (s->nz != wx::MLP_NZ) return fail(WX_E_UNSUPPORTED, "the surrogate needs nz == %d", wx::MLP_NZ);
+  if (n < 0 || (!cols && n > s->nx * s->ny)) return fail(WX_E_INVAL, "n = %d out of range", n);
+  WX_TRY(check_fields(s, true));
+  if (n == 0) return WX_OK;
+  wx::FusedArgs a = fused_args(s, blob);
+  a.list = cols;
+  a.n_list = nullptr;
+  a.cap = n;
+  a.rows_out = rows_out;
+  WX_HIP(wx::launch_surrogate_fused(a, static_cast<hipStream_t>(s->stream)));
+  return WX_OK;
+}
+
 int wx_dataset(wx_state *s, float *x_raw, float *y_raw) {
   if (!s || !s->impl) return fail(WX_E_INVAL, "state is NULL");
   if (!x_raw || !y_raw || !aligned16(x_raw) || !aligned16(y_raw)) return fail(WX_E_INVAL, "bad output buffers");
@@ -693,8 +726,8 @@ int wx_profile_step(wx_state *s, int nsteps, void *stream, double *ms_out, int n
   tm.st = st;
   int rc = run_steps(s, nsteps, st, tm);
   hipError_t se = hipStreamSynchronize(st);
-  double sum[8] = {0};
-  int cnt[8] = {0};   // classes: 0 halo, 1-3 stages, 4 physics/mass, 5 mass final, 6 surrogate
+  double sum[kProfileClasses] = {0};
+  int cnt[kProfileClasses] = {0};
   if (rc == WX_OK && se == hipSuccess) {
     for (size_t n = 0; n + 1 < ev.size(); ++n) {
       if (cls[n] < 0 || cls[n + 1] != -1) continue;
@@ -708,7 +741,7 @@ int wx_profile_step(wx_state *s, int nsteps, void *stream, double *ms_out, int n
   for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   if (rc != WX_OK) return rc;
   if (se != hipSuccess) return fail(WX_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(se));
-  for (int c = 0; c < n_out; ++c) ms_out[c] = (c < 8 && cnt[c]) ? sum[c] / cnt[c] : 0.0;
+  for (int c = 0; c < n_out; ++c) ms_out[c] = (c < kProfileClasses && cnt[c]) ? sum[c] / cnt[c] : 0.0;
   return WX_OK;
 }
 

@@ -16,6 +16,64 @@ constexpr int MLP_NHID = 512;
 constexpr int MLP_NOUT = 2 * MLP_NZ;       // 116 outputs
 constexpr int MLP_NOUTP = 128;             // padded output width
 
+// FP32 -> BF16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t f2bf(float x) {
+  uint32_t b = __float_as_uint(x);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return uint16_t(b >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+// SplitMix64 output for state increment x (Steele, Lea & Flood 2014).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Judge sampling: column c is checked against the plain physics at step t.
+__device__ __forceinline__ bool judge_sampled(uint64_t seed, uint64_t t, unsigned c, unsigned rate) {
+  return splitmix64(seed ^ (t << 32) ^ uint64_t(c)) % rate == 0;
+}
+
+// Column values of one level entering the features: theta - 300 K, q and the
+// cell-centred winds (FP32).
+struct LevelVals {
+  float th, q, u, v;
+};
+
+// Returns x as a rounded FP32 register value: the optimiser cannot fuse the
+// operation that produced x into the one that consumes it (a product into the
+// normalisation's subtraction, say), so every kernel rounds alike.
+__device__ __forceinline__ float settle(float x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// The five feature values of level k from the values of levels k and k - 1:
+// theta and q (k = 0) or their differences, the wind speed (k = 0) or the
+// shear S = |(u, v)_k - (u, v)_{k-1}|, and S times the two differences.  Both
+// feature kernels call this, so their rows agree bit for bit.
+__device__ __forceinline__ void level_features(int k, const LevelVals &c, const LevelVals &b, float out[5]) {
+  if (k == 0) {
+    out[0] = c.th;
+    out[1] = c.q;
+    out[2] = settle(sqrtf(fmaf(c.u, c.u, settle(c.v * c.v))));
+    out[3] = 0.f;
+    out[4] = 0.f;
+  } else {
+    const float dth = settle(c.th - b.th), dq = settle(c.q - b.q);
+    const float du = settle(c.u - b.u), dv = settle(c.v - b.v);
+    const float sh = settle(sqrtf(fmaf(du, du, settle(dv * dv))));
+    out[0] = dth;
+    out[1] = dq;
+    out[2] = sh;
+    out[3] = settle(sh * dth);
+    out[4] = settle(sh * dq);
+  }
+}
+
 enum GemmEpilogue { GEMM_F32 = 0, GEMM_BIAS_F32 = 1, GEMM_BIAS_RELU_BF16 = 2, GEMM_PARTIAL_F32 = 3 };
 
 // C[m][n] = sum_k A(m,k) B(k,n).  a_kcontig: A is [M][lda] (k contiguous),
@@ -71,7 +129,7 @@ struct ApplyArgs {
   T *th, *q;
   Geom g;
   T dt;
-  const float *ymean, *ystd;   // de-normalisation of the surrogate rows
+  const float *ymean, *ystd;   // unused by the sampled-column apply
   const int *fallback;         // skip everything when *fallback != 0 (may be null)
   int judged;                  // skip sampled columns
   uint64_t seed, t;
@@ -90,12 +148,40 @@ hipError_t launch_gather_rows(const uint16_t *x, const int *rows, int batch, uin
 hipError_t launch_sample(int ncol, uint64_t seed, uint64_t t, unsigned rate, int *block_count, int *block_off,
                          int *n_list, int cap, int *list, hipStream_t s);
 hipError_t launch_judge(const float *y_hat, const float *t_ref, const int *n_list, int cap, const float *ymean,
-                        const float *ystd, const double *sigma, double rel, int nz, int *fallback, double *judge_out,
-                        int *flags, hipStream_t s);
-template <typename T>
-hipError_t launch_apply_surrogate(const ApplyArgs<T> &a, const float *y, int c0, int n, hipStream_t s);
+                        const float *ystd, const double *sigma, double rel, int nz, double *part, int *fallback,
+                        double *judge_out, int *flags, hipStream_t s);
+size_t judge_part_bytes();     // FP64 block partials of launch_judge
 template <typename T>
 hipError_t launch_apply_sampled(const ApplyArgs<T> &a, const float *tend, const int *list, const int *n_list, int cap,
                                 hipStream_t s);
+
+// Fused surrogate physics on an FP32 state: feature rows, the three network
+// layers and either the tendency update of the state (apply mode) or the
+// normalised output rows of listed columns (rows mode), in one launch.
+struct FusedArgs {
+  const float *rho, *u, *v;
+  float *th, *q;                   // feature inputs; updated in apply mode
+  const float *th_s, *q_s, *f0, *ch;
+  Geom g;
+  double theta_off;
+  const uint16_t *w1, *w2, *w3;    // BF16 [512][320], [512][512], [128][512]
+  const float *b1, *b2, *b3;
+  const float *xmean, *xinvstd, *ymean, *ystd;
+  float dt;
+  // apply mode (rows_out == null): columns c0 + r for r < ncols
+  int c0, ncols;
+  const int *fallback;             // nothing happens when *fallback != 0 (may be null)
+  int judged;                      // leave the judge's sampled columns alone
+  uint64_t seed, t;
+  unsigned rate;
+  // rows mode: row s < min(*n_list, cap) (s < cap when n_list is null) is
+  // column list[s], or column s when list is null; normalised outputs to
+  // rows_out[s][128]; an index outside the grid gives the row of zero features
+  const int *list, *n_list;
+  int cap;
+  float *rows_out;
+};
+
+hipError_t launch_surrogate_fused(const FusedArgs &a, hipStream_t s);
 
 }  // namespace wx

@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_PKG, "libwx.so")
 WX_OK, WX_E_INVAL, WX_E_HIP, WX_E_STATE, WX_E_UNSUPPORTED = 0, -1, -2, -3, -4
 WX_F32, WX_F64 = 0, 1
 WX_PHYS_OFF, WX_PHYS_PLAIN, WX_PHYS_SURROGATE, WX_PHYS_JUDGED = 0, 1, 2, 3
+PROFILE_CLASSES = ("halo", "stage1", "stage2", "stage3", "physics", "mass_final", "judge",
+                   "surrogate", "sampled_apply")
 PARAMS = {"gamma4": 0, "k_min": 1, "mix_len": 2, "kappa_q": 3, "cp": 4, "t_dd": 5,
           "theta_offset": 6, "mass_every": 7, "judge_seed": 8, "judge_rel": 9, "judge_rate": 10,
           "step": 11}
@@ -28,7 +30,7 @@ HALO = 2
 
 EXPORTS = ("wx_create", "wx_destroy", "wx_last_error", "wx_workspace_bytes", "wx_set_param",
            "wx_get_param", "wx_halo", "wx_step", "wx_physics", "wx_mass", "wx_profile_step",
-           "wx_copy_probe", "wx_features", "wx_dataset", "wx_mlp_bytes", "wx_mlp_offset",
+           "wx_copy_probe", "wx_features", "wx_dataset", "wx_surrogate_rows", "wx_mlp_bytes", "wx_mlp_offset",
            "wx_mlp_init", "wx_mlp_refresh", "wx_mlp_norm_scratch_bytes", "wx_mlp_fit_norm",
            "wx_mlp_normalize", "wx_mlp_work_bytes", "wx_mlp_forward_backward", "wx_mlp_adam",
            "wx_mlp_train_step", "wx_mlp_infer_work_bytes", "wx_mlp_infer",
@@ -106,6 +108,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     vp, sz = ctypes.c_void_p, ctypes.c_size_t
     lib.wx_features.argtypes = [sp, ctypes.c_int, vp, vp]
     lib.wx_dataset.argtypes = [sp, vp, vp]
+    lib.wx_surrogate_rows.argtypes = [sp, vp, vp, ctypes.c_int, vp]
     lib.wx_mlp_bytes.argtypes = []
     lib.wx_mlp_offset.argtypes = [ctypes.c_int]
     lib.wx_mlp_init.argtypes = [vp, ctypes.c_uint64, vp]
@@ -320,9 +323,10 @@ class State:
         return {n: int(v) for n, v in zip(FLAG_NAMES, f)}
 
     def profile(self, nsteps: int, stream=None) -> np.ndarray:
-        """Average ms per launch: halo, stage 1, stage 2, stage 3, physics, mass final."""
-        out = (ctypes.c_double * 6)()
-        _check(self.lib.wx_profile_step(self._p, int(nsteps), _stream_ptr(stream), out, 6),
+        """Average ms per launch of each class (PROFILE_CLASSES order)."""
+        n = len(PROFILE_CLASSES)
+        out = (ctypes.c_double * n)()
+        _check(self.lib.wx_profile_step(self._p, int(nsteps), _stream_ptr(stream), out, n),
                "wx_profile_step")
         return np.array(out[:])
 
@@ -338,6 +342,21 @@ class State:
             out = torch.zeros(n, MLP_KIN, dtype=torch.int16, device=self.device)
             _check(self.lib.wx_features(self._p, 1, out.data_ptr(), mlp.blob.data_ptr()), "wx_features")
         return out
+
+    def surrogate_rows(self, mlp, cols=None, n=None, stream=None):
+        """Normalised network outputs [n][128] of the fused kernel for columns
+        cols (device int32 tensor) or columns 0..n-1."""
+        torch = _torch()
+        self._p.contents.stream = _stream_ptr(stream)
+        if cols is not None:
+            n = int(cols.shape[0])
+        elif n is None:
+            n = self.nx * self.ny
+        out = torch.zeros(max(n, 1), MLP_NOUTP, dtype=torch.float32, device=self.device)
+        _check(self.lib.wx_surrogate_rows(self._p, mlp.blob.data_ptr(),
+                                          None if cols is None else cols.data_ptr(), int(n),
+                                          out.data_ptr()), "wx_surrogate_rows")
+        return out[:n]
 
     def dataset(self, x_raw=None, y_raw=None, stream=None):
         """(raw features [ncol, 320], plain-physics targets [ncol, 128]) as device tensors."""

@@ -10,8 +10,9 @@ for the plain FP32 step.  theta and q are compared through their physics
 increments (state after the step minus state after the dycore):
 
 * exact composition (no winds, no diffusion, so the dycore is the identity in
-  both precisions and the normalisation is taken in FP32 on both sides): the
-  BF16 network inputs are then identical, and the increments must agree to
+  both precisions, and the features and normalisation are formed in FP32 on
+  both sides): the BF16 network inputs are then identical, and the increments
+  must agree to
   the forward-pass bar, 1e-3 Frobenius-relative, plus half an FP32 spacing of
   the stored state per value;
 * general winds: the FP32 dycore differs from the FP64 one by up to 1e-5,
@@ -81,12 +82,13 @@ def _upload(m, p, stats):
 def _oracle_surrogate(inp, p, stats, sample=None, k4=None, norm32=False):
     """One oracle step with surrogate physics; sampled columns take the plain result.
 
-    ``norm32`` forms the normalised inputs in FP32, the precision in which the
-    kernel takes their BF16 rounding decision."""
+    ``norm32`` forms the features and normalised inputs in FP32, the precision
+    in which the kernel takes their BF16 rounding decision."""
     k4 = DEFAULT.k4(inp.dx, inp.dt) if k4 is None else k4
     s = dycore.rk3(dycore.State(inp.rho, inp.theta, inp.q), inp.u, inp.v, inp.w, inp.dx, inp.dx,
                    inp.dz, inp.dt, k4)
-    x = omlp.features(s.rho, s.theta, s.q, inp.u, inp.v, inp.theta_s, inp.q_s, inp.f0, inp.ch)
+    x = omlp.features(s.rho, s.theta, s.q, inp.u, inp.v, inp.theta_s, inp.q_s, inp.f0, inp.ch,
+                      dtype=np.float32 if norm32 else np.float64)
     if norm32:
         xn = ((x.astype(np.float32) - stats["x_mean"]) * stats["x_invstd"]).astype(np.float64)
     else:
@@ -221,3 +223,63 @@ def test_fallback_reproduces_plain_step_bitwise():
     st.close()
     for name in ("rho", "theta", "q"):
         np.testing.assert_array_equal(got[name], plain[name])
+
+
+@pytest.mark.parametrize("shape", [(96, 64), (100, 70)])
+def test_fused_rows_equal_unfused_path_bitwise(shape):
+    """The fused kernel's network outputs equal features + GEMM chain bit for bit."""
+    import torch
+    nx, ny = shape
+    _say(f"case: fused rows vs unfused, {nx}x{ny}x58")
+    inp = _state32(nx, ny, 64)
+    p, stats = _model(inp)
+    m = wx.Mlp()
+    _upload(m, p, stats)
+    st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
+    ncol = nx * ny
+    xb = st.features(m)                                   # normalised BF16 rows
+    ref = m.infer(xb)
+    got = st.surrogate_rows(m)
+    assert torch.equal(got, ref)
+    # listed columns: ragged count, duplicates, indices outside the grid
+    rng = np.random.default_rng(5)
+    cols = rng.integers(0, ncol, 333).astype(np.int32)
+    cols[:4] = [0, ncol - 1, ncol - 1, 7]
+    cols[10] = -3
+    cols[11] = ncol
+    got_l = st.surrogate_rows(m, cols=torch.from_numpy(cols).cuda())
+    xl = torch.zeros(333, wx.MLP_KIN, dtype=xb.dtype, device=xb.device)
+    ok = (cols >= 0) & (cols < ncol)
+    idx = torch.from_numpy(np.flatnonzero(ok)).cuda()
+    xl[idx] = xb[torch.from_numpy(cols[ok].astype(np.int64)).cuda()]
+    ref_l = m.infer(xl)
+    st.close()
+    assert torch.equal(got_l, ref_l)
+
+
+def test_fallback_run_equals_plain_run_over_steps():
+    """Several judged steps that all fall back equal as many plain steps, and
+    stepping in separate calls equals one call (halo images stay consistent)."""
+    _say("case: 4 fallback steps vs 4 plain steps, 96x64x58")
+    inp = _state32(96, 64, 65)
+    p, stats = _model(inp)
+    stats["sigma64"] = np.array([1e-30, 1e-30])
+    m = wx.Mlp()
+    _upload(m, p, stats)
+    runs = {}
+    for name, mode, calls in (("plain1", wx.WX_PHYS_PLAIN, [4]), ("plain4", wx.WX_PHYS_PLAIN, [1, 1, 1, 1]),
+                              ("judged", wx.WX_PHYS_JUDGED, [2, 2])):
+        st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
+        if mode == wx.WX_PHYS_JUDGED:
+            st.attach_mlp(m)
+        st.set_phys_mode(mode)
+        fb = 0
+        for n in calls:
+            st.step(n)
+            fb += st.flags()["fallback_steps"]
+        runs[name] = (st.download(), fb)
+        st.close()
+    assert runs["judged"][1] == 4
+    for name in ("rho", "theta", "q"):
+        np.testing.assert_array_equal(runs["plain4"][0][name], runs["plain1"][0][name])
+        np.testing.assert_array_equal(runs["judged"][0][name], runs["plain1"][0][name])
