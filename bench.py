@@ -108,7 +108,8 @@ def surrogate_leg(args, host_inp, stream):
     x, y = surrogate.build_dataset(log=log)
     torch.cuda.synchronize()
     out["dataset"] = {"rows": int(x.shape[0]),
-                      "states": "400x320x58 seeds 100-103 after " + "/".join(map(str, surrogate.SNAPSHOTS)) + " steps",
+                      "states": "post-dycore states of steps " + "/".join(map(str, surrogate.SNAPSHOTS))
+                                + " of 400x320x58 runs, seeds 100-103",
                       "seconds": round(time.perf_counter() - t0, 2)}
     log(f"dataset {x.shape[0]} rows in {out['dataset']['seconds']} s")
     mlp = wx.Mlp()
@@ -128,7 +129,8 @@ def surrogate_leg(args, host_inp, stream):
                     "samples_per_s": round(nsteps * 4096 / train_s, 1),
                     "TFLOPs": round(3 * MLP_FLOPS_PER_COL * 4096 * nsteps / train_s / 1e12, 1),
                     "loss_first_epoch": round(hist[0], 5), "loss_last_epoch": round(hist[-1], 5)}
-    out["held_out"] = {"state": "400x320x58 seed 104", "judge_bound_over_sigma": 0.05, **held}
+    out["held_out"] = {"state": "post-dycore states of a 400x320x58 run, seed 104", "judge_bound_over_sigma": 0.05,
+                       **held}
     log(f"trained {nsteps} steps in {train_s:.1f} s; held-out {out['held_out']}")
 
     # coupled runs on the benchmark grid: plain, judged and unjudged surrogate

@@ -153,9 +153,9 @@ const char *wx_last_error(void);
  * block partials of the mass sums and a few constants. */
 size_t wx_workspace_bytes(const wx_state *s, int dtype);
 
-/* Device workspace of the surrogate modes: feature, activation and output
- * buffers for chunks of up to 262144 columns, and the judge's sample list
- * sized for the current WX_PARAM_JUDGE_RATE. */
+/* Device workspace of the surrogate modes: the judge's sample list, the
+ * plain tendencies and network outputs of the sampled columns, the judge's
+ * block partials and counters; sized for the current WX_PARAM_JUDGE_RATE. */
 size_t wx_surrogate_work_bytes(const wx_state *s);
 
 /* Set / get a wx_param.  Values must be finite; GAMMA4, KMIN, MIXLEN, KAPPA_Q

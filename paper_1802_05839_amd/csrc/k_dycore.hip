@@ -14,8 +14,9 @@
 // GPU design (section "Architecture-Dependent Storage Order": i stride-1 on
 // GPUs; K marched sequentially inside each thread as in the paper's generated
 // kernels, appendix "Reduced Weather: Diffusion"):
-//   * a 256-thread block owns a 64 x 4 column tile and marches k = 0..nz-1;
-//   * each k-plane of rho*, theta*, q* is staged once into LDS as a 68 x 8
+//   * a 512-thread block owns a 64 x 8 column tile and marches k = 0..nz-1
+//     (8 rows keep the re-read 2-row halo of the staged fields at 1.5x);
+//   * each k-plane of rho*, theta*, q* is staged once into LDS as a 68 x 12
 //     tile (2-cell halo), giving all horizontal neighbours; a 4-deep LDS ring
 //     (planes k..k+3) lets the vertical stencil read k+1, k+2 and the global
 //     loads of plane k+3 overlap the arithmetic of plane k, with one barrier
@@ -32,8 +33,8 @@
 namespace wx {
 namespace {
 
-constexpr int BX = 64, BY = 4;
-constexpr int TW = BX + 4, TH = BY + 4, TN = TW * TH;  // 68 x 8 tile
+constexpr int BX = STAGE_BX, BY = STAGE_BY;
+constexpr int TW = BX + 4, TH = BY + 4, TN = TW * TH;  // 68 x 12 tile
 constexpr int NT = BX * BY;
 constexpr int NLOAD = (TN + NT - 1) / NT;               // tile elements per thread
 constexpr int NBUF = 4;

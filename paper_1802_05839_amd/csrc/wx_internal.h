@@ -97,8 +97,10 @@ hipError_t launch_fill_i32(int *p, int n, int value, hipStream_t s);
 constexpr int TEND_ROW = 128;      // row width of the row-major tendency layout
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 
-inline int stage_tiles_x(int nx) { return (nx + 63) / 64; }
-inline int stage_tiles_y(int ny) { return (ny + 3) / 4; }
+// RK3 stage tile: 64 columns in i (one wave per row) by 8 rows in j.
+constexpr int STAGE_BX = 64, STAGE_BY = 8;
+inline int stage_tiles_x(int nx) { return (nx + STAGE_BX - 1) / STAGE_BX; }
+inline int stage_tiles_y(int ny) { return (ny + STAGE_BY - 1) / STAGE_BY; }
 inline int phys_blocks(int nx, int ny) { return ((nx + PHYS_BX - 1) / PHYS_BX) * ny; }
 inline int phys_reg_blocks(int nx, int ny) { return ((nx + 63) / 64) * ((ny + 3) / 4); }
 // physics kernel variant for a state: register-resident columns for FP32 and these level counts

@@ -6,10 +6,12 @@ statistics from ``wx_mlp_fit_norm``, the training steps from
 ``wx_mlp_train_step`` (BF16 MFMA forward/backward + Adam).  This module only
 decides which states to sample, the seeded batch order and the bookkeeping.
 
-Recipe: states are the plain-method runs on 400 x 320 x 58 grids (one GPU's
-share of the 1581 x 1301 x 58 grid) with seeds 100..103, sampled after 25,
-100, 200 and 300 steps: 16 snapshots x 128,000 columns = 2,048,000 rows.  The
-first steps are left out on purpose: the implicit diffusion removes the
+Recipe: rows are the columns of post-dycore states -- the state that the
+physics of step n sees inside a coupled step -- of plain-method runs on
+400 x 320 x 58 grids (one GPU's share of the 1581 x 1301 x 58 grid) with
+seeds 100..103 at n = 25, 100, 200 and 300: 16 snapshots x 128,000 columns =
+2,048,000 rows, labelled with the plain-physics tendencies of that state.
+The first steps are left out on purpose: the implicit diffusion removes the
 initial white-noise layering of q within a few steps, with q tendencies a
 hundred times those of the settled flow, and a training set holding them
 would set the q scale (and the judge's bound) by that transient.  Those
@@ -34,23 +36,35 @@ HELD_OUT_STEPS = (10, 50, 300)
 EPOCHS = 120
 
 
+def _post_dycore_rows(inp, steps: Sequence[int]):
+    """(features, targets) of the state that the physics of step n sees, for
+    each n in steps: n - 1 plain steps, then the dycore of step n alone."""
+    import torch
+    out = []
+    for n in steps:
+        st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
+        if n > 1:
+            st.step(n - 1)
+        st.set_phys_mode(wx.WX_PHYS_OFF)
+        st.step(1)
+        out.append(st.dataset())
+        torch.cuda.synchronize()
+        st.close()
+    return out
+
+
 def build_dataset(seeds: Sequence[int] = TRAIN_SEEDS, snapshots: Sequence[int] = SNAPSHOTS,
                   nx: int = 400, ny: int = 320, log=None):
-    """Raw (features, targets) device tensors over all seeds and snapshots."""
+    """Raw (features, targets) device tensors over all seeds and snapshots:
+    the post-dycore state of step n and its plain-physics tendencies, which
+    is what the surrogate replaces inside a coupled step."""
     import torch
     xs, ys = [], []
     for seed in seeds:
         inp = inputs.generate(nx, ny, 58, seed=seed, dtype=np.float32)
-        st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
-        done = 0
-        for snap in snapshots:
-            st.step(snap - done)
-            done = snap
-            x, y = st.dataset()
+        for x, y in _post_dycore_rows(inp, snapshots):
             xs.append(x)
             ys.append(y)
-        torch.cuda.synchronize()
-        st.close()
         if log:
             log(f"dataset seed {seed}: {len(snapshots)} snapshots")
     return torch.cat(xs), torch.cat(ys)
@@ -103,17 +117,9 @@ def tendency_rmse(mlp: "wx.Mlp", x_raw, y_raw) -> Dict[str, float]:
 
 
 def held_out(nx: int = 400, ny: int = 320, seed: int = HELD_OUT_SEED, steps: Sequence[int] = HELD_OUT_STEPS):
-    """{step: (raw features, targets)} of one held-out run sampled after each step count."""
+    """{step n: (raw features, targets)} of one held-out run, post-dycore states."""
     inp = inputs.generate(nx, ny, 58, seed=seed, dtype=np.float32)
-    st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
-    out = {}
-    done = 0
-    for n in steps:
-        st.step(n - done)
-        done = n
-        out[n] = st.dataset()
-    st.close()
-    return out
+    return dict(zip(steps, _post_dycore_rows(inp, steps)))
 
 
 def fit(mlp: "wx.Mlp", x_raw, y_raw, epochs: int = EPOCHS, batch: int = 4096, lr: float = 1e-3,
