@@ -39,14 +39,6 @@ constexpr int NT = BX * BY;
 constexpr int NLOAD = (TN + NT - 1) / NT;               // tile elements per thread
 constexpr int NBUF = 4;
 
-// Workgroups are dispatched round-robin over the 8 XCDs; map them so that XCD
-// x receives the contiguous logical range [x*q + min(x, r), ...).
-__device__ __forceinline__ int xcd_remap(int b, int n) {
-  const int q = n >> 3, r = n & 7;
-  const int x = b & 7, slot = b >> 3;
-  return x * q + min(x, r) + slot;
-}
-
 // Third-order upwind face value from the far-upstream, upstream and
 // downstream cells: b + (2 (c - b) + (b - a)) / 6.
 template <typename T>

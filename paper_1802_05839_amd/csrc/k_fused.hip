@@ -9,11 +9,14 @@
 //             consecutive columns of one field level, so state reads coalesce;
 //             part p forms levels [15 p, 15 p + 15) of the five profiles (part
 //             3 also the surface values and the padding);
-//   layers    wave w owns output columns [64 w, 64 w + 64) of the two hidden
-//             layers (8 x 4 tiles of v_mfma_f32_16x16x32_bf16) and [16 w,
-//             16 w + 16) of the output layer; A operands come from LDS, the
-//             BF16 weights stream from global memory (L2-resident, 0.98 MB),
-//             one k-step ahead;
+//   layers    wave w owns hidden units [64 w, 64 w + 64) of the two hidden
+//             layers (8 x 4 tiles of v_mfma_f32_16x16x32_bf16) and outputs
+//             [16 w, 16 w + 16) of the last; the weights are the first MFMA
+//             operand (streamed from global memory, L2-resident, 0.98 MB, one
+//             k-step ahead) and the activations the second (from LDS, the
+//             eight fragments of a k-step read before its MFMAs), so a lane
+//             ends with four consecutive units of one sample and stores them
+//             as one 8-byte LDS write;
 //   outputs   thread (column, part) updates 29 levels of theta or q with
 //             coalesced read-modify-writes and the periodic halo images.
 // The k order of every dot product (steps of 32 from k = 0, the same lane
@@ -62,33 +65,40 @@ __device__ __forceinline__ void tile_gemm(f32x4 (&acc)[MT][NT], const uint16_t *
     const int kn = k0 + 32 < K ? k0 + 32 : k0;   // last step reloads its own slice
 #pragma unroll
     for (int y = 0; y < NT; ++y) bnext[y] = *reinterpret_cast<const bf16x8 *>(bp + (size_t)y * 16 * ldb + kn);
+    bf16x8 fa[MT];
+#pragma unroll
+    for (int x = 0; x < MT; ++x) fa[x] = *reinterpret_cast<const bf16x8 *>(A + (x * 16 + rl) * lda + k0 + kl);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int x = 0; x < MT; ++x) {
-      const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(A + (x * 16 + rl) * lda + k0 + kl);
 #pragma unroll
-      for (int y = 0; y < NT; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, bcur[y], acc[x][y], 0, 0, 0);
+      for (int y = 0; y < NT; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bcur[y], fa[x], acc[x][y], 0, 0, 0);
     }
 #pragma unroll
     for (int y = 0; y < NT; ++y) bcur[y] = bnext[y];
   }
 }
 
-// Hidden-layer epilogue: H[m][n] = bf16(relu(acc + b[n])); lane holds rows
-// 4 (lane / 16) + r of each 16 x 16 tile at column lane % 16.
+// Hidden-layer epilogue: H[m][n] = bf16(relu(acc + b[n])).  The MFMA ran with
+// the weights as the first operand, so lane holds hidden units n0 + 16 y +
+// 4 (lane / 16) + r (r = 0..3) of sample 16 x + lane % 16: four consecutive
+// BF16 values, one 8-byte LDS store.
 template <int MT, int NT>
 __device__ __forceinline__ void store_hidden(const f32x4 (&acc)[MT][NT], const float *b, int n0, uint16_t *H,
                                              int lane) {
 #pragma unroll
   for (int y = 0; y < NT; ++y) {
-    const int n = n0 + y * 16 + (lane & 15);
-    const float bn = b[n];
+    const int n = n0 + y * 16 + 4 * (lane >> 4);
+    const float4 bn = *reinterpret_cast<const float4 *>(b + n);
 #pragma unroll
-    for (int x = 0; x < MT; ++x)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float v = acc[x][y][r] + bn;
-        H[(x * 16 + 4 * (lane >> 4) + r) * HLD + n] = f2bf(v > 0.f ? v : 0.f);
-      }
+    for (int x = 0; x < MT; ++x) {
+      const float v0 = acc[x][y][0] + bn.x, v1 = acc[x][y][1] + bn.y;
+      const float v2 = acc[x][y][2] + bn.z, v3 = acc[x][y][3] + bn.w;
+      uint2 pk;
+      pk.x = uint32_t(f2bf(v0 > 0.f ? v0 : 0.f)) | (uint32_t(f2bf(v1 > 0.f ? v1 : 0.f)) << 16);
+      pk.y = uint32_t(f2bf(v2 > 0.f ? v2 : 0.f)) | (uint32_t(f2bf(v3 > 0.f ? v3 : 0.f)) << 16);
+      *reinterpret_cast<uint2 *>(H + (x * 16 + (lane & 15)) * HLD + n) = pk;
+    }
   }
 }
 
@@ -199,12 +209,11 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
   tile_gemm<8, 1>(acc3, H, HLD, a.w3, MLP_NHID, n3, MLP_NHID, lane);
   __syncthreads();
   {
-    const int n = n3 + (lane & 15);
-    const float bn = a.b3[n];
+    const int n = n3 + 4 * (lane >> 4);
 #pragma unroll
     for (int x = 0; x < 8; ++x)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Y[(x * 16 + 4 * (lane >> 4) + r) * YLD + n] = acc3[x][0][r] + bn;
+      for (int r = 0; r < 4; ++r) Y[(x * 16 + (lane & 15)) * YLD + n + r] = acc3[x][0][r] + a.b3[n + r];
   }
   __syncthreads();
 

@@ -261,9 +261,10 @@ __device__ __forceinline__ void block_finish(const PhysArgs<float> *ap, double *
 // FP32 state with a compile-time level count NZ: the production path.
 //
 // 64 x 4 columns per block, one thread per column.  The forward elimination
-// keeps c' in LDS (one float per level and column) and d'_theta, d'_q in
-// registers (every loop over k is unrolled, so each array element is a fixed
-// VGPR).  Both passes prefetch the inputs of level k +- PF while working on
+// keeps c' in LDS (one float per level and column) and d'_theta, d'_q and the
+// column's rho, theta, q in registers (every loop over k is unrolled, so each
+// array element is a fixed register), so the downward pass reads nothing from
+// HBM.  The upward pass prefetches the inputs of level k + PF while working on
 // level k (a register ring of PF levels), so a wave never waits on the load it
 // is about to use; a scheduling barrier per level keeps the compiler from
 // hoisting further and running out of registers.  Columns whose dominance
@@ -276,7 +277,8 @@ __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
   if (a.run_if && *a.run_if == 0) return;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
   const int nbx = (a.g.nx + 63) / 64;
-  const int i = (blockIdx.x % nbx) * 64 + tx, j = (blockIdx.x / nbx) * 4 + ty;
+  const int L = xcd_remap(blockIdx.x, gridDim.x);   // j-neighbours share an XCD's L2 (the v row below)
+  const int i = (L % nbx) * 64 + tx, j = (L / nbx) * 4 + ty;
   const bool active = (i < a.g.nx) && (j < a.g.ny);
   Kahan mass[3];
   Counters cnt;
@@ -308,6 +310,7 @@ __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
     const float beta = dt * r0 * ldg(a.ch, unsigned(col));
     const float ths = ldg(a.th_s, unsigned(col)), qs = ldg(a.q_s, unsigned(col));
     float dtr[NZ], dqr[NZ];
+    float colr[NZ], colt[NZ], colq[NZ];   // the column itself, kept for the downward pass
     float alo = 0.f, tm1 = t0, qm1 = q0, cpv = 0.f, dtp = 0.f, dqp = 0.f, rmax = 0.f;
 #pragma unroll
     for (int k = 0; k < NZ; ++k) {
@@ -325,6 +328,9 @@ __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
         const float kz = kmin + l2 * (__builtin_amdgcn_sqrtf(du * du + dv * dv) * rdzi);
         ahi = dt * ((r0 + r1) * 0.5f) * kz * rdzi;
       }
+      colr[k] = r0;
+      colt[k] = t0;
+      colq[k] = q0;
       const float m = r0 * a.dz[k];
       float diag = m + alo + ahi;
       float rt = ahi * (t1 - t0) - alo * (t0 - tm1);
@@ -364,27 +370,14 @@ __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
       const float kappa = a.kappa, cpa = a.cp;
       const int di = i < 2 ? nx : (i >= nx - 2 ? -nx : 0);
       const int dj = j < 2 ? ny * int(sj) : (j >= ny - 2 ? -ny * int(sj) : 0);
-      // an opaque copy of the column offset and a compiler memory barrier: the
-      // downward pass recomputes its addresses and re-reads c' from LDS
-      // instead of keeping the upward pass's per-level values alive
-      unsigned gd = g0;
-      asm volatile("" : "+v"(gd)::"memory");
-      float xr[PF], xt[PF], xq[PF];                 // prefetch ring (levels k-1 .. k-PF)
-      auto fetch_dn = [&](int lev, int slot) {
-        const unsigned g = gd + unsigned(lev) * sk;
-        xr[slot] = ldg(a.rho, g);
-        xt[slot] = ldg(a.th, g);
-        xq[slot] = ldg(a.q, g);
-      };
-#pragma unroll
-      for (int l = 0; l < PF; ++l)
-        if (NZ - 1 - l >= 0) fetch_dn(NZ - 1 - l, (NZ - 1 - l) % PF);
+      // the column's rho, theta, q come from registers (kept by the upward
+      // pass; the 512-register budget of a lone wave holds them), so this
+      // pass reads nothing from HBM
+      const unsigned gd = g0;
       float dtn = 0.f, dqn = 0.f, tau = 0.f, tr_hi = 1.f;
 #pragma unroll
       for (int k = NZ - 1; k >= 0; --k) {
-        const int sl = k % PF;
-        const float r = xr[sl], t = xt[sl], q = xq[sl];
-        if (k - PF >= 0) fetch_dn(k - PF, sl);
+        const float r = colr[k], t = colt[k], q = colq[k];
         const float ck = s_c[k * 256 + tid];
         const float dth = dtr[k] - ck * dtn;
         const float dqq = dqr[k] - ck * dqn;

@@ -30,6 +30,15 @@ __device__ __forceinline__ T &ref(T *base, unsigned idx) {
   return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + idx * unsigned(sizeof(T)));
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs; map dispatch index b
+// of n so that XCD x works on the contiguous logical range [x*q + min(x, r),
+// ...), and tiles that share halo rows share one L2.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int q = n >> 3, r = n & 7;
+  const int x = b & 7, slot = b >> 3;
+  return x * q + min(x, r) + slot;
+}
+
 // Reciprocal in the arithmetic precision: the hardware estimate (1 ulp) in
 // FP32, an exact division in FP64.
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
