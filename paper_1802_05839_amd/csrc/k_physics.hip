@@ -272,7 +272,7 @@ __device__ __forceinline__ void block_finish(const PhysArgs<float> *ap, double *
 // scratch).
 template <int NZ, int MODE>
 __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
-  constexpr int PF = 4;
+  constexpr int PF = 8;
   extern __shared__ float s_c[];          // [NZ][256]
   if (a.run_if && *a.run_if == 0) return;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
@@ -375,6 +375,9 @@ __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
       // pass reads nothing from HBM
       const unsigned gd = g0;
       float dtn = 0.f, dqn = 0.f, tau = 0.f, tr_hi = 1.f;
+      // the column's 58 mass terms are summed in plain FP64 (relative error
+      // at most 57 ulp) and enter the compensated sums once per column
+      double cm = 0.0, cmt = 0.0, cmq = 0.0;
 #pragma unroll
       for (int k = NZ - 1; k >= 0; --k) {
         const float r = colr[k], t = colt[k], q = colq[k];
@@ -415,12 +418,17 @@ __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
           if (!(r > 0.f)) cnt.rho_le0++;
           if (a.do_mass) {
             const double mv = double(r) * a.vol[k];
-            mass[0].add(mv);
-            mass[1].add(mv * (double(tn) + a.theta_off));
-            mass[2].add(mv * double(qn));
+            cm += mv;
+            cmt += mv * (double(tn) + a.theta_off);
+            cmq += mv * double(qn);
           }
         }
         __builtin_amdgcn_sched_barrier(0);
+      }
+      if (MODE == 0 && a.do_mass) {
+        mass[0].add(cm);
+        mass[1].add(cmt);
+        mass[2].add(cmq);
       }
     }
   }
