@@ -8,7 +8,9 @@ scan) + the compensated FP64 mass sums, all in the HIP library.
 
 Prints one JSON line:  metric Mcell-steps/s (interior cells x steps / s),
 the roofline of the dominant kernel (the RK3 stage kernel) and the FP64 CPU
-oracle timed on a bounded sample of the same workload.  Unless --no-surrogate,
+oracle timed on a bounded sample of the same workload, and the FP32 error
+against FP64 after 100 steps on the one-GPU share 400 x 320 x 58.  Unless
+--no-surrogate,
 the line also carries the learned-physics leg: the MLP surrogate trained on
 2,048,000 columns of 400 x 320 x 58 states, its held-out tendency RMSE, and
 surrogate and judged steps on the same grid timed against plain steps, with
@@ -85,6 +87,43 @@ def cpu_baseline(budget_s: float = 15.0):
     return {"value": cells * n / t / 1e6, "unit": "Mcell-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} steps of the 256x256x58 seed-3 grid (NumPy FP64, single thread), "
                       f"{t:.1f} s"}
+
+
+def share_error(steps: int = 100):
+    """FP32 against FP64 on the one-GPU share 400 x 320 x 58 after `steps`
+    steps of the same library (the FP64 path is pinned to the oracle at
+    1e-12): relative L2 and max error per field, theta as theta - 300 K, and
+    the mass drift of both runs."""
+    import torch
+
+    from paper_1802_05839_amd import inputs, wx
+
+    cfg = inputs.CONFIGS["share"]
+    inp = inputs.generate(cfg["nx"], cfg["ny"], cfg["nz"], seed=cfg["seed"])
+    i32 = inp.astype(np.float32)
+    i32.theta = (inp.theta - 300.0).astype(np.float32).astype(np.float64) + 300.0
+    i32.theta_s = (inp.theta_s - 300.0).astype(np.float32).astype(np.float64) + 300.0
+    runs = {}
+    for name, src, dt, off in (("f64", i32, "f64", 0.0), ("f32", i32, "f32", 300.0)):
+        st = wx.state_from_inputs(src, dtype=dt, theta_offset=off)
+        m0 = st.mass(compute=True)
+        st.step(steps)
+        m1 = st.mass()
+        f = {k: st.interior(k).double().clone() for k in ("rho", "theta", "q")}
+        f["theta"] = f["theta"] + (off - 300.0)
+        runs[name] = (f, m0, m1)
+        st.close()
+    torch.cuda.synchronize()
+    out = {"grid": "400x320x58 seed 1", "steps": steps,
+           "reference": "FP64 run of the same library (parity-pinned to the oracle at 1e-12)"}
+    for k, label in (("rho", "rho"), ("theta", "theta_minus_300"), ("q", "q")):
+        a, b = runs["f32"][0][k], runs["f64"][0][k]
+        out[label] = {"rel_l2": float(f"{(torch.linalg.norm(a - b) / torch.linalg.norm(b)).item():.3e}"),
+                      "rel_max": float(f"{(torch.max(torch.abs(a - b)) / torch.max(torch.abs(b))).item():.3e}")}
+    for name in ("f64", "f32"):
+        _, m0, m1 = runs[name]
+        out[f"mass_drift_{name}"] = [float(f"{x:.3e}") for x in np.abs(m1 - m0) / np.abs(m0)]
+    return out
 
 
 def surrogate_leg(args, host_inp, stream):
@@ -214,6 +253,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-share-error", action="store_true")
     ap.add_argument("--train-epochs", type=int, default=120)
     ap.add_argument("--coupled-steps", type=int, default=500)
     args = ap.parse_args()
@@ -313,6 +353,9 @@ def main() -> int:
     }
     if not args.no_surrogate and nz == 58:
         out["surrogate"] = surrogate_leg(args, inp, stream)
+    if not args.no_share_error:
+        log("FP32 against FP64 on the one-GPU share")
+        out["fp32_error_share"] = share_error()
     del inp
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
