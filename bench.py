@@ -208,6 +208,8 @@ def surrogate_leg(args, host_inp, stream):
             r["judge_rmse_theta"] = [float(f"{j[0]:.3e}") for j in rmse]
             r["judge_rmse_q"] = [float(f"{j[1]:.3e}") for j in rmse]
             r["judge_sampled_columns"] = int(rmse[-1][3])
+            r["judge_columns_over_bound_theta"] = [round(j[4], 4) for j in rmse]
+            r["judge_columns_over_bound_q"] = [round(j[5], 4) for j in rmse]
             r["fallback_steps"] = flags["fallback_steps"]
         # the state after exactly n steps, before the profiling steps below
         if mode_name in ("plain", "judged"):

@@ -127,8 +127,10 @@ typedef struct wx_state {
   /* surrogate modes only (WX_PHYS_SURROGATE / WX_PHYS_JUDGED; FP32 state, nz 58): */
   void *mlp;               /* trained parameter blob (wx_mlp_bytes)               */
   void *surrogate_work;    /* >= wx_surrogate_work_bytes(...) device bytes        */
-  double *judge_out;       /* 4 doubles, last judged step: RMSE theta [K/s], RMSE
-                              q [1/s], fallback (0/1), sampled columns            */
+  double *judge_out;       /* 6 doubles, last judged step: RMSE theta [K/s], RMSE
+                              q [1/s], fallback (0/1), sampled columns, and the
+                              fractions of sampled columns whose own RMSE over
+                              the levels exceeds the bound (theta, q)            */
   void *impl;              /* private                                             */
 } wx_state;
 

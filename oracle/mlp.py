@@ -35,7 +35,9 @@ plain physics reads and its outputs are the physics tendencies.  Readings:
 * Judge: column c is sampled at step t when SplitMix64(seed ^ (t << 32) ^ c)
   mod 100 == 0; per variable the RMSE pooled over the sampled columns and all
   levels is compared with 0.05 times the training-set standard deviation of
-  that tendency; strictly greater means the whole step falls back.
+  that tendency; strictly greater means the whole step falls back.  Also
+  reported: the fraction of sampled columns whose own RMSE over the levels
+  of a variable exceeds the same bound.
 
 Arrays are float64 unless stated.  Weight matrices are (fan_out, fan_in).
 """
@@ -229,3 +231,17 @@ def judge(t_hat: np.ndarray, t_ref: np.ndarray, mask: np.ndarray, sigma_theta: f
     r_theta = float(np.sqrt(np.mean(d[:, :nz] ** 2)))
     r_q = float(np.sqrt(np.mean(d[:, nz:] ** 2)))
     return r_theta, r_q, (r_theta > rel * sigma_theta) or (r_q > rel * sigma_q)
+
+
+def judge_columns(t_hat: np.ndarray, t_ref: np.ndarray, mask: np.ndarray, sigma_theta: float,
+                  sigma_q: float, rel: float = 0.05):
+    """Fractions of the sampled columns whose own RMSE over the levels of one
+    variable exceeds rel * sigma of that variable (theta, q)."""
+    nz = t_hat.shape[1] // 2
+    d = (t_hat - t_ref)[mask]
+    if d.shape[0] == 0:
+        return 0.0, 0.0
+    r_theta = np.sqrt(np.mean(d[:, :nz] ** 2, axis=1))
+    r_q = np.sqrt(np.mean(d[:, nz:] ** 2, axis=1))
+    return float(np.mean(r_theta > rel * sigma_theta)), float(np.mean(r_q > rel * sigma_q))
+

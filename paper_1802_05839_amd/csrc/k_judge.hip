@@ -7,7 +7,8 @@
 // the surrogate's tendencies pooled over the sampled columns and all levels is
 // compared with rel * sigma_v (sigma_v: training-set std of that tendency).
 // Strictly greater for theta or q means the whole step falls back to the
-// plain physics.  Sampled columns always take the plain result.  The decision
+// plain physics.  Also reported: the fraction of sampled columns whose own
+// RMSE (over the levels of one variable) exceeds the same bound.  Sampled columns always take the plain result.  The decision
 // stays on the device: later launches read the flag and exit early.
 #include "wx_internal.h"
 #include "wx_mlp_internal.h"
@@ -71,6 +72,8 @@ __global__ void k_sample_write(int ncol, uint64_t seed, uint64_t t, unsigned rat
 // elements e = b * 256 + t + i * (JUDGE_BLOCKS * 256) (tree within the
 // block), then one thread adds the block partials in block order.
 constexpr int JUDGE_BLOCKS = 120;
+// block partials: 2 doubles per block, then two int counters (see k_judge_cols)
+constexpr int JUDGE_COUNT_OFF = 2 * JUDGE_BLOCKS;
 
 __global__ void k_judge_part(const float *y_hat, const float *t_ref, const int *n_list, int cap, const float *ymean,
                              const float *ystd, int nz, double *part) {
@@ -99,7 +102,30 @@ __global__ void k_judge_part(const float *y_hat, const float *t_ref, const int *
   if (t == 0) {
     part[2 * blockIdx.x] = sh[0][0];
     part[2 * blockIdx.x + 1] = sh[1][0];
+    if (blockIdx.x == 0) {
+      int *cnt = reinterpret_cast<int *>(part + JUDGE_COUNT_OFF);
+      cnt[0] = 0;
+      cnt[1] = 0;
+    }
   }
+}
+
+// Per sampled column: its own RMSE over the levels of each variable against
+// the same bound; counts the columns that exceed it (integer atomics, so the
+// counts do not depend on the order).
+__global__ void k_judge_cols(const float *y_hat, const float *t_ref, const int *n_list, int cap, const float *ymean,
+                             const float *ystd, const double *sigma, double rel, int nz, double *part) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= min(*n_list, cap)) return;
+  double e[2] = {0.0, 0.0};
+  for (int o = 0; o < 2 * nz; ++o) {
+    const double pred = double(y_hat[(size_t)s * TEND_ROW + o]) * ystd[o] + ymean[o];
+    const double d = pred - double(t_ref[(size_t)s * TEND_ROW + o]);
+    e[o >= nz] += d * d;
+  }
+  int *cnt = reinterpret_cast<int *>(part + JUDGE_COUNT_OFF);
+  for (int v = 0; v < 2; ++v)
+    if (sqrt(e[v] / nz) > rel * sigma[v]) atomicAdd(&cnt[v], 1);
 }
 
 __global__ void k_judge_final(const double *part, const int *n_list, int cap, const double *sigma, double rel, int nz,
@@ -116,10 +142,13 @@ __global__ void k_judge_final(const double *part, const int *n_list, int cap, co
   const double r1 = n > 0 ? sqrt(e1 / cnt) : 0.0;
   const int fb = (r0 > rel * sigma[0]) || (r1 > rel * sigma[1]);
   *fallback = fb;
+  const int *over = reinterpret_cast<const int *>(part + JUDGE_COUNT_OFF);
   judge_out[0] = r0;
   judge_out[1] = r1;
   judge_out[2] = fb;
   judge_out[3] = n;
+  judge_out[4] = n > 0 ? double(over[0]) / n : 0.0;
+  judge_out[5] = n > 0 ? double(over[1]) / n : 0.0;
   if (fb) atomicAdd(&flags[3], 1);
 }
 
@@ -167,12 +196,15 @@ hipError_t launch_judge(const float *y_hat, const float *t_ref, const int *n_lis
                         double *judge_out, int *flags, hipStream_t s) {
   hipLaunchKernelGGL(k_judge_part, dim3(JUDGE_BLOCKS), dim3(256), 0, s, y_hat, t_ref, n_list, cap, ymean, ystd, nz,
                      part);
+  if (cap > 0)
+    hipLaunchKernelGGL(k_judge_cols, dim3((cap + 127) / 128), dim3(128), 0, s, y_hat, t_ref, n_list, cap, ymean, ystd,
+                       sigma, rel, nz, part);
   hipLaunchKernelGGL(k_judge_final, dim3(1), dim3(64), 0, s, part, n_list, cap, sigma, rel, nz, fallback, judge_out,
                      flags);
   return hipGetLastError();
 }
 
-size_t judge_part_bytes() { return size_t(2) * JUDGE_BLOCKS * sizeof(double); }
+size_t judge_part_bytes() { return size_t(2) * JUDGE_BLOCKS * sizeof(double) + 2 * sizeof(int); }
 
 template <typename T>
 hipError_t launch_apply_sampled(const ApplyArgs<T> &a, const float *tend, const int *list, const int *n_list, int cap,

@@ -276,16 +276,17 @@ class State:
         s.mlp = mlp.blob.data_ptr()
         self.t["surrogate_work"] = torch.zeros(int(self.lib.wx_surrogate_work_bytes(self._p)),
                                                dtype=torch.uint8, device=self.device)
-        self.t["judge_out"] = torch.zeros(4, dtype=torch.float64, device=self.device)
+        self.t["judge_out"] = torch.zeros(6, dtype=torch.float64, device=self.device)
         s.surrogate_work = self.t["surrogate_work"].data_ptr()
         s.judge_out = self.t["judge_out"].data_ptr()
 
     def judge(self):
-        """(RMSE theta, RMSE q, fallback, sampled columns) of the last judged step."""
+        """(RMSE theta, RMSE q, fallback, sampled columns, fraction of sampled
+        columns over the bound in theta, in q) of the last judged step."""
         torch = _torch()
         torch.cuda.synchronize(self.device)
         j = self.t["judge_out"].cpu().numpy()
-        return float(j[0]), float(j[1]), bool(j[2]), int(j[3])
+        return float(j[0]), float(j[1]), bool(j[2]), int(j[3]), float(j[4]), float(j[5])
 
     def tendencies(self, stream=None):
         """Plain-physics tendencies (dtheta/dt, dq/dt) of the current state, (nz, ny, nx) float64."""

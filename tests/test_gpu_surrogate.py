@@ -191,12 +191,14 @@ def test_judged_step_matches_oracle_without_fallback():
     mask = omlp.sample_mask(seed, 0, inp.nx * inp.ny)
     s, th, q, t_hat, t_ref, _ = _oracle_surrogate(inp, p, stats, sample=mask)
     r_t, r_q, fb = omlp.judge(t_hat, t_ref, mask, 1e3, 1e3)
-    g_rt, g_rq, g_fb, g_n = got["judge"]
+    g_rt, g_rq, g_fb, g_n, g_ct, g_cq = got["judge"]
     e_rho = nmax(got["rho"], s.rho)
     e_inc = _incr_err(got, base, th, q, s)
     _say(f"judged step: rho {e_rho:.3e}, increments {e_inc}, rmse {g_rt:.3e} {g_rq:.3e} "
          f"vs {r_t:.3e} {r_q:.3e}, n={g_n}")
     assert g_n == int(mask.sum()) and not g_fb and not fb
+    # per-column exceedance against the same (never reached) bound
+    assert g_ct == 0.0 and g_cq == 0.0
     assert abs(g_rt - r_t) <= 1e-2 * r_t and abs(g_rq - r_q) <= 1e-2 * r_q
     assert e_rho <= 1e-5
     assert max(e_inc) <= 1e-2
@@ -210,6 +212,25 @@ def test_judged_step_matches_oracle_without_fallback():
     assert got["flags"]["fallback_steps"] == 0
 
 
+def test_judge_column_fractions_match_oracle():
+    """The fraction of sampled columns over the bound, with the bound at the
+    median column RMSE so that about half of them exceed it."""
+    _say("case: judge per-column fractions, 160x128x58")
+    inp = _state32(160, 128, 66)
+    p, stats = _model(inp)
+    seed, rel = 91, 0.05
+    mask = omlp.sample_mask(seed, 0, inp.nx * inp.ny)
+    _, _, _, t_hat, t_ref, _ = _oracle_surrogate(inp, p, stats, sample=mask)
+    d = (t_hat - t_ref)[mask]
+    med = [np.median(np.sqrt(np.mean(d[:, :NZ] ** 2, axis=1))), np.median(np.sqrt(np.mean(d[:, NZ:] ** 2, axis=1)))]
+    stats["sigma64"] = np.array([med[0] / rel, med[1] / rel])
+    ref = omlp.judge_columns(t_hat, t_ref, mask, stats["sigma64"][0], stats["sigma64"][1], rel)
+    got = _run(inp, p, stats, wx.WX_PHYS_JUDGED, seed=seed)
+    n = int(mask.sum())
+    _say(f"over-bound fractions {got['judge'][4:]} vs oracle {ref}, n={n}")
+    assert abs(got["judge"][4] - ref[0]) <= 2.0 / n and abs(got["judge"][5] - ref[1]) <= 2.0 / n
+
+
 def test_fallback_reproduces_plain_step_bitwise():
     _say("case: forced fallback equals the plain step")
     inp = _state32(96, 64, 63)
@@ -217,6 +238,7 @@ def test_fallback_reproduces_plain_step_bitwise():
     stats["sigma64"] = np.array([1e-30, 1e-30])      # any error exceeds the bound
     got = _run(inp, p, stats, wx.WX_PHYS_JUDGED, seed=5)
     assert got["judge"][2] and got["flags"]["fallback_steps"] == 1
+    assert got["judge"][4] == 1.0 and got["judge"][5] == 1.0    # every column is over a zero bound
     st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
     st.step(1)
     plain = st.download()

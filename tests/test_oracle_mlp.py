@@ -194,3 +194,22 @@ def test_sample_mask_and_judge():
     assert r_t == pytest.approx(0.3) and r_q == 0.0
     assert fb is False                      # 0.3 == 0.05 * 6 is not strictly greater
     assert mlp.judge(hat, ref, mask, sigma_theta=5.9, sigma_q=1.0)[2] is True
+
+
+def test_judge_columns_hand_built():
+    """Four sampled columns (nz = 2) with column RMSE 1, 2, 3, 4 in theta and
+    4, 3, 2, 1 in q; a fifth, unsampled column with a huge error is ignored."""
+    nz = 2
+    ref = np.zeros((5, 2 * nz))
+    hat = np.zeros((5, 2 * nz))
+    for c, (a, b) in enumerate([(1, 4), (2, 3), (3, 2), (4, 1)]):
+        hat[c, :nz] = a          # RMSE over the two levels is a
+        hat[c, nz:] = b
+    hat[4] = 1e9
+    mask = np.array([True, True, True, True, False])
+    ft, fq = mlp.judge_columns(hat, ref, mask, sigma_theta=50.0, sigma_q=50.0, rel=0.05)   # bound 2.5
+    assert (ft, fq) == (0.5, 0.5)
+    ft, fq = mlp.judge_columns(hat, ref, mask, sigma_theta=60.0, sigma_q=20.0, rel=0.05)   # bounds 3, 1
+    assert (ft, fq) == (0.25, 0.75)
+    assert mlp.judge_columns(hat, ref, np.zeros(5, bool), 1.0, 1.0) == (0.0, 0.0)
+
