@@ -10,13 +10,14 @@
 //             part p forms levels [15 p, 15 p + 15) of the five profiles (part
 //             3 also the surface values and the padding);
 //   layers    wave w owns hidden units [64 w, 64 w + 64) of the two hidden
-//             layers (8 x 4 tiles of v_mfma_f32_16x16x32_bf16) and outputs
-//             [16 w, 16 w + 16) of the last; the weights are the first MFMA
+//             layers (2 x 4 tiles of v_mfma_f32_32x32x16_bf16, the shape that
+//             runs at the full matrix-core rate on gfx950) and a 32-output by
+//             64-sample block of the last; the weights are the first MFMA
 //             operand (streamed from global memory, L2-resident, 0.98 MB, one
-//             k-step ahead) and the activations the second (from LDS, the
-//             eight fragments of a k-step read before its MFMAs), so a lane
-//             ends with four consecutive units of one sample and stores them
-//             as one 8-byte LDS write;
+//             k step ahead) and the activations the second (from LDS, the
+//             fragments of a k step read before its MFMAs), so a lane ends
+//             with four consecutive units of one sample and stores them as
+//             one 8-byte LDS write;
 //   outputs   thread (column, part) updates 29 levels of theta or q with
 //             coalesced read-modify-writes and the periodic halo images.
 // The k order of every dot product (steps of 32 from k = 0, the same lane
@@ -34,7 +35,7 @@ namespace wx {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int FT = 128;                  // columns per tile
 constexpr int FTHREADS = 512;
@@ -50,56 +51,73 @@ constexpr int kHalf = (kNZ + 1) / 2;     // levels per thread in the update
 constexpr int kPartLev = 15;             // levels per thread in the feature phase
 static_assert(4 * kPartLev >= kNZ, "four parts must cover the column");
 
-// acc[x][y] += A(rows 16x.., k) * B(cols n0 + 16y.., k) over k = 0..K-1.
-// A: LDS [rows][lda]; B: global [N][ldb], k contiguous.
-template <int MT, int NT>
-__device__ __forceinline__ void tile_gemm(f32x4 (&acc)[MT][NT], const uint16_t *A, int lda, const uint16_t *B,
-                                          int ldb, int n0, int K, int lane) {
-  const int kl = (lane >> 4) * 8, rl = lane & 15;
-  const uint16_t *bp = B + (size_t)(n0 + rl) * ldb + kl;
-  bf16x8 bcur[NT], bnext[NT];
+// acc[y][x] += W(units n0 + 32 y.., k) X(samples s0 + 32 x.., k) over
+// k = 0..K-1 in steps of 16 (ascending, as in the stand-alone GEMM), on
+// v_mfma_f32_32x32x16_bf16.  The weights are the first operand (global
+// [N][ldb], k contiguous, one 32-wide k step fetched ahead), the activations
+// the second (LDS [samples][lda], the fragments of a k step read before its
+// MFMAs).  A lane feeds row (or column) lane % 32 at k = 8 (lane / 32)..+7.
+template <int NU, int NS>
+__device__ __forceinline__ void tile_gemm(f32x16 (&acc)[NU][NS], const uint16_t *X, int lda, int s0,
+                                          const uint16_t *W, int ldb, int n0, int K, int lane) {
+  const int kl = 8 * (lane >> 5), rl = lane & 31;
+  const uint16_t *wp = W + (size_t)(n0 + rl) * ldb + kl;
+  const uint16_t *xp = X + (s0 + rl) * lda + kl;
+  bf16x8 wcur[2][NU], wnext[2][NU];
 #pragma unroll
-  for (int y = 0; y < NT; ++y) bcur[y] = *reinterpret_cast<const bf16x8 *>(bp + (size_t)y * 16 * ldb);
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int y = 0; y < NU; ++y) wcur[h][y] = *reinterpret_cast<const bf16x8 *>(wp + (size_t)y * 32 * ldb + 16 * h);
 #pragma unroll 1
   for (int k0 = 0; k0 < K; k0 += 32) {
     const int kn = k0 + 32 < K ? k0 + 32 : k0;   // last step reloads its own slice
 #pragma unroll
-    for (int y = 0; y < NT; ++y) bnext[y] = *reinterpret_cast<const bf16x8 *>(bp + (size_t)y * 16 * ldb + kn);
-    bf16x8 fa[MT];
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int x = 0; x < MT; ++x) fa[x] = *reinterpret_cast<const bf16x8 *>(A + (x * 16 + rl) * lda + k0 + kl);
+      for (int y = 0; y < NU; ++y)
+        wnext[h][y] = *reinterpret_cast<const bf16x8 *>(wp + (size_t)y * 32 * ldb + kn + 16 * h);
+    bf16x8 xf[2][NS];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int x = 0; x < NS; ++x) xf[h][x] = *reinterpret_cast<const bf16x8 *>(xp + x * 32 * lda + k0 + 16 * h);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int x = 0; x < MT; ++x) {
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int y = 0; y < NT; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bcur[y], fa[x], acc[x][y], 0, 0, 0);
-    }
+      for (int y = 0; y < NU; ++y)
 #pragma unroll
-    for (int y = 0; y < NT; ++y) bcur[y] = bnext[y];
+        for (int x = 0; x < NS; ++x)
+          acc[y][x] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wcur[h][y], xf[h][x], acc[y][x], 0, 0, 0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int y = 0; y < NU; ++y) wcur[h][y] = wnext[h][y];
   }
 }
 
-// Hidden-layer epilogue: H[m][n] = bf16(relu(acc + b[n])).  The MFMA ran with
-// the weights as the first operand, so lane holds hidden units n0 + 16 y +
-// 4 (lane / 16) + r (r = 0..3) of sample 16 x + lane % 16: four consecutive
-// BF16 values, one 8-byte LDS store.
-template <int MT, int NT>
-__device__ __forceinline__ void store_hidden(const f32x4 (&acc)[MT][NT], const float *b, int n0, uint16_t *H,
+// Hidden-layer epilogue: H[m][n] = bf16(relu(acc + b[n])).  Accumulator
+// 4 q + c of the lane holds unit n0 + 32 y + 8 q + 4 (lane / 32) + c of sample
+// 32 x + lane % 32: four consecutive BF16 values, one 8-byte LDS store.
+template <int NU, int NS>
+__device__ __forceinline__ void store_hidden(const f32x16 (&acc)[NU][NS], const float *b, int n0, uint16_t *H,
                                              int lane) {
 #pragma unroll
-  for (int y = 0; y < NT; ++y) {
-    const int n = n0 + y * 16 + 4 * (lane >> 4);
-    const float4 bn = *reinterpret_cast<const float4 *>(b + n);
+  for (int y = 0; y < NU; ++y)
 #pragma unroll
-    for (int x = 0; x < MT; ++x) {
-      const float v0 = acc[x][y][0] + bn.x, v1 = acc[x][y][1] + bn.y;
-      const float v2 = acc[x][y][2] + bn.z, v3 = acc[x][y][3] + bn.w;
-      uint2 pk;
-      pk.x = uint32_t(f2bf(v0 > 0.f ? v0 : 0.f)) | (uint32_t(f2bf(v1 > 0.f ? v1 : 0.f)) << 16);
-      pk.y = uint32_t(f2bf(v2 > 0.f ? v2 : 0.f)) | (uint32_t(f2bf(v3 > 0.f ? v3 : 0.f)) << 16);
-      *reinterpret_cast<uint2 *>(H + (x * 16 + (lane & 15)) * HLD + n) = pk;
+    for (int q = 0; q < 4; ++q) {
+      const int n = n0 + 32 * y + 8 * q + 4 * (lane >> 5);
+      const float4 bn = *reinterpret_cast<const float4 *>(b + n);
+#pragma unroll
+      for (int x = 0; x < NS; ++x) {
+        const float v0 = acc[y][x][4 * q] + bn.x, v1 = acc[y][x][4 * q + 1] + bn.y;
+        const float v2 = acc[y][x][4 * q + 2] + bn.z, v3 = acc[y][x][4 * q + 3] + bn.w;
+        uint2 pk;
+        pk.x = uint32_t(f2bf(v0 > 0.f ? v0 : 0.f)) | (uint32_t(f2bf(v1 > 0.f ? v1 : 0.f)) << 16);
+        pk.y = uint32_t(f2bf(v2 > 0.f ? v2 : 0.f)) | (uint32_t(f2bf(v3 > 0.f ? v3 : 0.f)) << 16);
+        *reinterpret_cast<uint2 *>(H + (32 * x + (lane & 31)) * HLD + n) = pk;
+      }
     }
-  }
 }
 
 __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
@@ -180,40 +198,48 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
   __syncthreads();
 
   // ---- hidden layer 1: H = relu(X W1^T + b1) ---------------------------------
-  f32x4 acc[8][4];
+  f32x16 acc[2][4];
   const int n0 = wave * 64;
 #pragma unroll
-  for (int x = 0; x < 8; ++x)
+  for (int y = 0; y < 2; ++y)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
-  tile_gemm<8, 4>(acc, X, XLD, a.w1, MLP_KIN, n0, MLP_KIN, lane);
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[y][x][r] = 0.f;
+  tile_gemm<2, 4>(acc, X, XLD, 0, a.w1, MLP_KIN, n0, MLP_KIN, lane);
   __syncthreads();   // every wave has read X
-  store_hidden<8, 4>(acc, a.b1, n0, H, lane);
+  store_hidden<2, 4>(acc, a.b1, n0, H, lane);
   __syncthreads();
 
   // ---- hidden layer 2: H = relu(H W2^T + b2) ---------------------------------
 #pragma unroll
-  for (int x = 0; x < 8; ++x)
+  for (int y = 0; y < 2; ++y)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
-  tile_gemm<8, 4>(acc, H, HLD, a.w2, MLP_NHID, n0, MLP_NHID, lane);
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[y][x][r] = 0.f;
+  tile_gemm<2, 4>(acc, H, HLD, 0, a.w2, MLP_NHID, n0, MLP_NHID, lane);
   __syncthreads();
-  store_hidden<8, 4>(acc, a.b2, n0, H, lane);
+  store_hidden<2, 4>(acc, a.b2, n0, H, lane);
   __syncthreads();
 
   // ---- output layer: Y = H W3^T + b3 (normalised tendencies) -----------------
-  f32x4 acc3[8][1];
+  // wave w: outputs [32 (w % 4), +32) of samples [64 (w / 4), +64)
+  f32x16 acc3[1][2];
 #pragma unroll
-  for (int x = 0; x < 8; ++x) acc3[x][0] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int n3 = wave * 16;
-  tile_gemm<8, 1>(acc3, H, HLD, a.w3, MLP_NHID, n3, MLP_NHID, lane);
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc3[0][x][r] = 0.f;
+  const int o3 = 32 * (wave & 3), s3 = 64 * (wave >> 2);
+  tile_gemm<1, 2>(acc3, H, HLD, s3, a.w3, MLP_NHID, o3, MLP_NHID, lane);
   __syncthreads();
-  {
-    const int n = n3 + 4 * (lane >> 4);
 #pragma unroll
-    for (int x = 0; x < 8; ++x)
+  for (int q = 0; q < 4; ++q) {
+    const int o = o3 + 8 * q + 4 * (lane >> 5);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Y[(x * 16 + (lane & 15)) * YLD + n + r] = acc3[x][0][r] + a.b3[n + r];
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Y[(s3 + 32 * x + (lane & 31)) * YLD + o + c] = acc3[0][x][4 * q + c] + a.b3[o + c];
   }
   __syncthreads();
 

@@ -9,12 +9,14 @@
 // gradients / Adam are FP32; weights are stored FP32 (master) with BF16
 // copies refreshed after each update.
 //
-// GEMM: C[m][n] = sum_k A(m,k) B(k,n) on 64 x 64 output tiles, K in steps of
-// 32, four waves each owning a 32 x 32 quarter as 2 x 2 tiles of
-// v_mfma_f32_16x16x32_bf16.  Operands are staged through LDS in [row][k]
-// order (k contiguous) so each lane feeds the matrix core with one 16-byte
-// LDS read per tile; global operands may be k-contiguous (row-major [rows][K])
-// or row-contiguous ([K][rows]); the latter are transposed on the way into LDS.
+// GEMM: C[m][n] = sum_k A(m,k) B(k,n) on 64 x 64 output tiles, K staged in
+// steps of 32, four waves each owning a 32 x 32 quarter as one tile of
+// v_mfma_f32_32x32x16_bf16 (two instructions per 32-wide k step, k ascending;
+// on gfx950 this shape runs at twice the rate of the 16x16x32 one).  Operands
+// are staged through LDS in [row][k] order (k contiguous) so each lane feeds
+// the matrix core with one 16-byte LDS read per operand and instruction;
+// global operands may be k-contiguous (row-major [rows][K]) or row-contiguous
+// ([K][rows]); the latter are transposed on the way into LDS.
 // Every output element is produced by one lane with a fixed k order, and a
 // split over K writes partial tiles that a second kernel sums in a fixed order,
 // so results are bitwise reproducible.
@@ -25,7 +27,7 @@ namespace wx {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int GBM = 64, GBN = 64, GBK = 32, GLD = GBK + 8;  // LDS row stride (bf16 elements)
 
@@ -80,11 +82,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   const int ke = min(a.K, kb + a.k_split);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  f32x4 acc[2][2];
+  f32x16 acc;
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
 
   const int nsteps = (ke - kb + GBK - 1) / GBK;
   if (nsteps > 0) {
@@ -92,46 +92,42 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
     load_tile<BK_>(sB[0], a.B, a.ldb, n0, kb, a.N, ke, nullptr);
   }
   __syncthreads();
+  // lane holds row (or column) lane % 32 of its operand at k = 8 (lane / 32)..+7
+  const int ra = (wm + (lane & 31)) * GLD + 8 * (lane >> 5);
+  const int rb = (wn + (lane & 31)) * GLD + 8 * (lane >> 5);
   for (int s = 0; s < nsteps; ++s) {
     const int cur = s & 1;
     if (s + 1 < nsteps) {
       load_tile<AK>(sA[cur ^ 1], a.A, a.lda, m0, kb + (s + 1) * GBK, a.M, ke, a.rows_a);
       load_tile<BK_>(sB[cur ^ 1], a.B, a.ldb, n0, kb + (s + 1) * GBK, a.N, ke, nullptr);
     }
-    const int kl = (lane >> 4) * 8;
 #pragma unroll
-    for (int x = 0; x < 2; ++x) {
-      const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(sA[cur] + (wm + x * 16 + (lane & 15)) * GLD + kl);
-#pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        const bf16x8 fb = *reinterpret_cast<const bf16x8 *>(sB[cur] + (wn + y * 16 + (lane & 15)) * GLD + kl);
-        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[x][y], 0, 0, 0);
-      }
+    for (int kk = 0; kk < GBK; kk += 16) {
+      const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(sA[cur] + ra + kk);
+      const bf16x8 fb = *reinterpret_cast<const bf16x8 *>(sB[cur] + rb + kk);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb, acc, 0, 0, 0);
     }
     __syncthreads();
   }
-  // lane holds C[4 * (lane / 16) + r][lane % 16] of each 16 x 16 tile
+  // accumulator r of the lane holds C[8 (r / 4) + 4 (lane / 32) + r % 4][lane % 32]
+  // of the wave's 32 x 32 tile
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm + x * 16 + 4 * (lane >> 4) + r;
-        const int n = n0 + wn + y * 16 + (lane & 15);
-        if (m >= a.M || n >= a.N) continue;
-        float v = acc[x][y][r];
-        if (EP == EP_F32) {
-          static_cast<float *>(a.C)[(size_t)m * a.ldc + n] = v;
-        } else if (EP == EP_BIAS_F32) {
-          static_cast<float *>(a.C)[(size_t)m * a.ldc + n] = v + a.bias[n];
-        } else if (EP == EP_BIAS_RELU_BF16) {
-          v += a.bias[n];
-          static_cast<uint16_t *>(a.C)[(size_t)m * a.ldc + n] = f2bf(v > 0.f ? v : 0.f);
-        } else {
-          static_cast<float *>(a.C)[blockIdx.z * a.split_stride + (size_t)m * a.ldc + n] = v;
-        }
-      }
+  for (int r = 0; r < 16; ++r) {
+    const int m = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    const int n = n0 + wn + (lane & 31);
+    if (m >= a.M || n >= a.N) continue;
+    float v = acc[r];
+    if (EP == EP_F32) {
+      static_cast<float *>(a.C)[(size_t)m * a.ldc + n] = v;
+    } else if (EP == EP_BIAS_F32) {
+      static_cast<float *>(a.C)[(size_t)m * a.ldc + n] = v + a.bias[n];
+    } else if (EP == EP_BIAS_RELU_BF16) {
+      v += a.bias[n];
+      static_cast<uint16_t *>(a.C)[(size_t)m * a.ldc + n] = f2bf(v > 0.f ? v : 0.f);
+    } else {
+      static_cast<float *>(a.C)[blockIdx.z * a.split_stride + (size_t)m * a.ldc + n] = v;
+    }
+  }
 }
 
 // Sum nsplit partial slices in order: out[i] = sum_s part[s][i].
