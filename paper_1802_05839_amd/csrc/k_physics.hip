@@ -274,8 +274,20 @@ template <int NZ, int MODE>
 __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
   constexpr int PF = 8;
   extern __shared__ float s_c[];          // [NZ][256]
+  // the per-level constants, staged once per block: read through LDS they
+  // never wait behind the kernel's own global stores (on this target the
+  // vector-memory counter tracks stores too, and vector loads of these
+  // read-only arrays would drain it every level)
+  __shared__ float s_dz[NZ], s_rdzi[NZ];
+  __shared__ double s_vol[NZ];
   if (a.run_if && *a.run_if == 0) return;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
+  for (int k = tid; k < NZ; k += 256) {
+    s_dz[k] = a.dz[k];
+    s_rdzi[k] = k + 1 < NZ ? a.rdzi[k] : 0.f;
+    s_vol[k] = a.vol[k];
+  }
+  __syncthreads();
   const int nbx = (a.g.nx + 63) / 64;
   const int L = xcd_remap(blockIdx.x, gridDim.x);   // j-neighbours share an XCD's L2 (the v row below)
   const int i = (L % nbx) * 64 + tx, j = (L / nbx) * 4 + ty;
@@ -323,7 +335,7 @@ __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
         ub1 = (pu[sl] + pe[sl]) * 0.5f;
         vb1 = (pv[sl] + pn[sl]) * 0.5f;
         if (k + 1 + PF < NZ) fetch_up(k + 1 + PF, sl);
-        const float rdzi = a.rdzi[k];
+        const float rdzi = s_rdzi[k];
         const float du = ub1 - ub0, dv = vb1 - vb0;
         const float kz = kmin + l2 * (__builtin_amdgcn_sqrtf(du * du + dv * dv) * rdzi);
         ahi = dt * ((r0 + r1) * 0.5f) * kz * rdzi;
@@ -331,7 +343,7 @@ __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
       colr[k] = r0;
       colt[k] = t0;
       colq[k] = q0;
-      const float m = r0 * a.dz[k];
+      const float m = r0 * s_dz[k];
       float diag = m + alo + ahi;
       float rt = ahi * (t1 - t0) - alo * (t0 - tm1);
       float rq = ahi * (q1 - q0) - alo * (q0 - qm1);
@@ -386,7 +398,7 @@ __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
         const float dqq = dqr[k] - ck * dqn;
         dtn = dth;
         dqn = dqq;
-        const float dzk = a.dz[k];
+        const float dzk = s_dz[k];
         tau += kappa * r * (q > 0.f ? q : 0.f) * dzk;
         const float tr_lo = expf(-tau);
         const float heat = f0 * (tr_hi - tr_lo) * fast_rcp(cpa * (r * dzk));
@@ -417,7 +429,7 @@ __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
           if (!(isfinite(r) && isfinite(tn) && isfinite(qn))) cnt.nonfinite++;
           if (!(r > 0.f)) cnt.rho_le0++;
           if (a.do_mass) {
-            const double mv = double(r) * a.vol[k];
+            const double mv = double(r) * s_vol[k];
             cm += mv;
             cmt += mv * (double(tn) + a.theta_off);
             cmq += mv * double(qn);
