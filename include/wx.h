@@ -86,7 +86,7 @@ typedef enum wx_param {
                                 always on the last step; 0 = never [1]          */
   WX_PARAM_JUDGE_SEED = 8,   /* judge sample seed, integer < 2^32 [0]           */
   WX_PARAM_JUDGE_REL = 9,    /* fallback when a pooled RMSE > rel * sigma [0.05] */
-  WX_PARAM_JUDGE_RATE = 10,  /* one column in `rate` is sampled, integer >= 1;
+  WX_PARAM_JUDGE_RATE = 10,  /* one column in `rate` is sampled, integer 1..2^32-1;
                                 fixed once the surrogate workspace is sized [100] */
   WX_PARAM_STEP = 11,        /* index t of the next step (sample hash), integer
                                 >= 0; wx_step advances it by nsteps [0]          */

@@ -573,7 +573,8 @@ int wx_set_param(wx_state *s, int param, double value) {
        param == WX_PARAM_STEP) && value != std::floor(value))
     return fail(WX_E_INVAL, "param %d must be an integer", param);
   if (param == WX_PARAM_JUDGE_SEED && value >= 4294967296.0) return fail(WX_E_INVAL, "judge seed must be < 2^32");
-  if (param == WX_PARAM_JUDGE_RATE && value < 1) return fail(WX_E_INVAL, "judge rate must be >= 1");
+  if (param == WX_PARAM_JUDGE_RATE && (value < 1 || value > 4294967295.0))
+    return fail(WX_E_INVAL, "judge rate must be in 1..2^32-1");
   impl_of(s)->param[param] = value;
   return WX_OK;
 }

@@ -105,3 +105,58 @@ def test_step_rejects_incomplete_state_before_any_launch(lib):
     assert lib.wx_physics(p, None, 7) == wx.WX_E_UNSUPPORTED
     assert lib.wx_copy_probe(None, None, 16, None) == wx.WX_E_INVAL
     lib.wx_destroy(p)
+
+
+def test_surrogate_modes_validate_before_any_launch(lib):
+    """Surrogate modes need an FP32 state with nz = 58, a blob, a workspace
+    and (judged) judge_out; wx_surrogate_rows checks its arguments likewise."""
+    def filled(nz, dtype):
+        p = lib.wx_create(8, 8, nz, 2.0, 100.0, _dz(nz))
+        s = p.contents
+        for name in ("rho", "theta", "q", "u", "v", "w", "workspace", "mass_out", "flags_out",
+                     "theta_s", "q_s", "f0", "ch"):
+            setattr(s, name, 4096)      # never dereferenced: validation fails first
+        s.dtype = dtype
+        return p
+    p = filled(4, wx.WX_F32)
+    p.contents.phys_mode = wx.WX_PHYS_SURROGATE
+    assert lib.wx_step(p, 1, None) == wx.WX_E_UNSUPPORTED and b"nz" in lib.wx_last_error()
+    assert lib.wx_surrogate_rows(p, 4096, None, 1, 4096) == wx.WX_E_UNSUPPORTED
+    lib.wx_destroy(p)
+    p = filled(58, wx.WX_F64)
+    p.contents.phys_mode = wx.WX_PHYS_JUDGED
+    assert lib.wx_step(p, 1, None) == wx.WX_E_UNSUPPORTED and b"FP32" in lib.wx_last_error()
+    assert lib.wx_surrogate_rows(p, 4096, None, 1, 4096) == wx.WX_E_UNSUPPORTED
+    lib.wx_destroy(p)
+    p = filled(58, wx.WX_F32)
+    s = p.contents
+    s.phys_mode = wx.WX_PHYS_SURROGATE
+    assert lib.wx_step(p, 1, None) == wx.WX_E_STATE               # no blob, no workspace
+    s.mlp, s.surrogate_work = 4096, 4096
+    s.phys_mode = wx.WX_PHYS_JUDGED
+    assert lib.wx_step(p, 1, None) == wx.WX_E_STATE and b"judge_out" in lib.wx_last_error()
+    assert lib.wx_surrogate_rows(p, None, None, 1, 4096) == wx.WX_E_INVAL
+    assert lib.wx_surrogate_rows(p, 4096, None, -1, 4096) == wx.WX_E_INVAL
+    assert lib.wx_surrogate_rows(p, 4096, None, 8 * 8 + 1, 4096) == wx.WX_E_INVAL
+    assert lib.wx_surrogate_rows(p, 4100, None, 1, 4096) == wx.WX_E_INVAL   # misaligned blob
+    lib.wx_destroy(p)
+
+
+def test_mlp_entry_points_validate(lib):
+    assert lib.wx_mlp_work_bytes(0) == 0 and lib.wx_mlp_work_bytes(65537) == 0
+    assert lib.wx_mlp_forward_backward(4096, 4096, 4096, 4096, 4096, 0, 4096, None) == wx.WX_E_INVAL
+    assert lib.wx_mlp_forward_backward(None, 4096, 4096, 4096, 4096, 16, 4096, None) == wx.WX_E_INVAL
+    assert lib.wx_mlp_adam(4096, 1e-3, 0, None) == wx.WX_E_INVAL
+    assert lib.wx_mlp_adam(4100, 1e-3, 1, None) == wx.WX_E_INVAL
+    assert lib.wx_mlp_infer(4096, 4096, 4096, 0, 4096, None) == wx.WX_E_INVAL
+    assert lib.wx_mlp_offset(-1) == -1 and lib.wx_mlp_offset(35) == -1
+
+
+def test_judge_rate_range(lib):
+    p = lib.wx_create(8, 8, 4, 2.0, 100.0, _dz(4))
+    assert lib.wx_set_param(p, 10, 0.0) == wx.WX_E_INVAL
+    assert lib.wx_set_param(p, 10, 1e12) == wx.WX_E_INVAL          # the kernels take a 32-bit rate
+    assert lib.wx_set_param(p, 10, 2.5) == wx.WX_E_INVAL
+    assert lib.wx_set_param(p, 10, 4294967295.0) == wx.WX_OK
+    lib.wx_destroy(p)
+

@@ -305,3 +305,27 @@ def test_fallback_run_equals_plain_run_over_steps():
     for name in ("rho", "theta", "q"):
         np.testing.assert_array_equal(runs["plain4"][0][name], runs["plain1"][0][name])
         np.testing.assert_array_equal(runs["judged"][0][name], runs["plain1"][0][name])
+
+
+def test_judged_step_with_no_sampled_column_equals_surrogate_step():
+    """A sampling rate so large that no column is drawn: the judge sees zero
+    columns, does not fall back, and the step equals the unjudged one bitwise."""
+    _say("case: judged step with an empty sample, 96x64x58")
+    inp = _state32(96, 64, 67)
+    p, stats = _model(inp)
+    runs = {}
+    for name, mode in (("judged", wx.WX_PHYS_JUDGED), ("surrogate", wx.WX_PHYS_SURROGATE)):
+        m = wx.Mlp()
+        _upload(m, p, stats)
+        st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
+        st.set_param("judge_rate", 4e9)
+        st.attach_mlp(m)
+        st.set_phys_mode(mode)
+        st.step(1)
+        runs[name] = (st.download(), st.judge() if mode == wx.WX_PHYS_JUDGED else None, st.flags())
+        st.close()
+    j = runs["judged"][1]
+    assert j[3] == 0 and not j[2] and j[0] == 0.0 and j[1] == 0.0 and j[4] == 0.0 and j[5] == 0.0
+    assert runs["judged"][2]["fallback_steps"] == 0
+    for name in ("rho", "theta", "q"):
+        np.testing.assert_array_equal(runs["judged"][0][name], runs["surrogate"][0][name])
