@@ -163,17 +163,6 @@ __global__ void k_loss(const float *y, const float *t, const int *rows, int batc
   if (n == 0) row_loss[m] = sh[0];
 }
 
-// Column sums over rows in a fixed order, two levels: chunk partials
-// part[c][col] = sum of rows [c*chunk, (c+1)*chunk), then k_sum_splits.
-__global__ void k_colsum_part(const float *a, int rows, int cols, int lda, int chunk, float *part) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= cols) return;
-  const int r0 = blockIdx.y * chunk, r1 = min(rows, r0 + chunk);
-  float s = 0.f;
-  for (int r = r0; r < r1; ++r) s += a[(size_t)r * lda + col];
-  part[(size_t)blockIdx.y * cols + col] = s;
-}
-
 // Hidden-layer gradient: g = (upstream @ W) * (h > 0) in place (FP32) and its
 // BF16 GEMM operand.
 __global__ void k_mask_round(float *a, const uint16_t *mask, size_t n, uint16_t *out) {
@@ -184,24 +173,76 @@ __global__ void k_mask_round(float *a, const uint16_t *mask, size_t n, uint16_t 
   out[i] = f2bf(g);
 }
 
-// Adam on FP32 master weights; refresh the BF16 copy (and its transpose).
-__global__ void k_adam(float *w, const float *g, float *m, float *v, size_t n, float lr, float bc1,
-                       float bc2, uint16_t *wb, uint16_t *wbt, int rows, int cols) {
-  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float gi = g[i];
-  const float mi = 0.9f * m[i] + 0.1f * gi;
-  const float vi = 0.999f * v[i] + 0.001f * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  const float wi = w[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
-  w[i] = wi;
-  if (wb) {
+// Column sums of up to four [rows][lda] FP32 matrices in one launch.  Block b
+// covers 16 columns of one matrix; thread (quad q, group g) sums columns
+// 16b + 4q .. 16b + 4q + 3 over rows g, g + 64, ... in order (float4 loads
+// when the matrix allows), then the 64 group sums are folded in a fixed tree.
+__global__ void __launch_bounds__(256) k_colsum_multi(ColsumArgs a) {
+  __shared__ float sh[64][17];
+  int b = blockIdx.x, jb = 0;
+  while (jb + 1 < a.njobs && b >= a.job[jb].blocks) {
+    b -= a.job[jb].blocks;
+    ++jb;
+  }
+  const ColsumJob &J = a.job[jb];
+  const int q = threadIdx.x & 3, g = threadIdx.x >> 2;
+  const int c = b * 16 + 4 * q;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  if (J.vec) {
+    if (c < J.cols) {
+      for (int r = g; r < a.rows; r += 64) {
+        const float4 x = *reinterpret_cast<const float4 *>(J.a + (size_t)r * J.lda + c);
+        s0 += x.x;
+        s1 += x.y;
+        s2 += x.z;
+        s3 += x.w;
+      }
+    }
+  } else {
+    for (int r = g; r < a.rows; r += 64) {
+      const float *row = J.a + (size_t)r * J.lda;
+      if (c < J.cols) s0 += row[c];
+      if (c + 1 < J.cols) s1 += row[c + 1];
+      if (c + 2 < J.cols) s2 += row[c + 2];
+      if (c + 3 < J.cols) s3 += row[c + 3];
+    }
+  }
+  sh[g][4 * q] = s0;
+  sh[g][4 * q + 1] = s1;
+  sh[g][4 * q + 2] = s2;
+  sh[g][4 * q + 3] = s3;
+  __syncthreads();
+  const int col = threadIdx.x & 15, grp = threadIdx.x >> 4;   // 16 columns x 16 lanes
+#pragma unroll
+  for (int h = 32; h >= 1; h >>= 1) {
+    for (int gg = grp; gg < h; gg += 16) sh[gg][col] += sh[gg + h][col];
+    __syncthreads();
+  }
+  if (threadIdx.x < 16 && b * 16 + col < J.cols) J.out[b * 16 + col] = sh[0][col];
+}
+
+// Adam over the six parameter tensors in one launch (element i of the
+// concatenation belongs to the tensor whose range holds it).
+__global__ void k_adam_multi(AdamArgs a) {
+  const size_t gi = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int t = 0;
+  while (t + 1 < 6 && gi >= a.seg[t + 1].start) ++t;
+  const AdamSeg &S = a.seg[t];
+  const size_t i = gi - S.start;
+  if (i >= S.n) return;
+  const float g = S.g[i];
+  const float mi = 0.9f * S.m[i] + 0.1f * g;
+  const float vi = 0.999f * S.v[i] + 0.001f * g * g;
+  S.m[i] = mi;
+  S.v[i] = vi;
+  const float wi = S.w[i] - a.lr * (mi / a.bc1) / (sqrtf(vi / a.bc2) + 1e-8f);
+  S.w[i] = wi;
+  if (S.wb) {
     const uint16_t h = f2bf(wi);
-    wb[i] = h;
-    if (wbt) {
-      const int r = int(i / cols), c = int(i % cols);
-      wbt[(size_t)c * rows + r] = h;
+    S.wb[i] = h;
+    if (S.wbt) {
+      const int r = int(i / S.cols), c = int(i % S.cols);
+      S.wbt[(size_t)c * S.rows + r] = h;
     }
   }
 }
@@ -280,23 +321,22 @@ hipError_t launch_loss(const float *y, const float *t, const int *rows, int batc
   return hipGetLastError();
 }
 
-hipError_t launch_colsum(const float *a, int rows, int cols, int lda, float *part, float *out, hipStream_t s) {
-  const int chunk = 64, nchunk = (rows + chunk - 1) / chunk;
-  hipLaunchKernelGGL(k_colsum_part, dim3((cols + 127) / 128, nchunk), dim3(128), 0, s, a, rows, cols, lda, chunk, part);
-  hipLaunchKernelGGL(k_sum_splits, dim3((cols + 255) / 256), dim3(256), 0, s, part, nchunk, size_t(cols), out,
-                     size_t(cols));
+hipError_t launch_colsum_multi(const ColsumArgs &a, hipStream_t s) {
+  int blocks = 0;
+  for (int j = 0; j < a.njobs; ++j) blocks += a.job[j].blocks;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_colsum_multi, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam_multi(const AdamArgs &a, hipStream_t s) {
+  const size_t n = a.seg[5].start + a.seg[5].n;
+  hipLaunchKernelGGL(k_adam_multi, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_mask_round(float *a, const uint16_t *mask, size_t n, uint16_t *out, hipStream_t s) {
   hipLaunchKernelGGL(k_mask_round, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, a, mask, n, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_adam(float *w, const float *g, float *m, float *v, size_t n, float lr, float bc1, float bc2,
-                       uint16_t *wb, uint16_t *wbt, int rows, int cols, hipStream_t s) {
-  hipLaunchKernelGGL(k_adam, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, w, g, m, v, n, lr, bc1, bc2, wb,
-                     wbt, rows, cols);
   return hipGetLastError();
 }
 

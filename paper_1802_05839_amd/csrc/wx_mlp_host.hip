@@ -76,7 +76,7 @@ bool al16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 // Training workspace for a batch of B rows.
 struct Work {
   uint16_t *xb, *h1, *h2, *d3b, *g2b, *g1b;
-  float *y, *d3f, *g2f, *g1f, *row_loss, *part, *cpart;
+  float *y, *d3f, *g2f, *g1f, *row_loss, *part;
   size_t total;
   static constexpr int kSplitRows = 256;   // batch rows per dW split
 };
@@ -103,7 +103,6 @@ Work work_layout(void *base, int B) {
   w.row_loss = reinterpret_cast<float *>(take(size_t(B) * 4));
   const size_t splits = (size_t(B) + Work::kSplitRows - 1) / Work::kSplitRows;
   w.part = reinterpret_cast<float *>(take(splits * MLP_NHID * MLP_NHID * 4));
-  w.cpart = reinterpret_cast<float *>(take(((size_t(B) + 63) / 64) * MLP_NHID * 4));
   w.total = off;
   return w;
 }
@@ -251,7 +250,6 @@ int wx_mlp_forward_backward(void *blob, void *work, const void *x, const float *
   if (int rc = weight_grad(w.d3b, MLP_NOUTP, MLP_NOUTP, w.h2, MLP_NHID, MLP_NHID, B, w.part,
                            sec<float>(blob, WX_MLP_GRAD + 4), st))
     return rc;
-  MLP_HIP(launch_colsum(w.d3f, B, MLP_NOUTP, MLP_NOUTP, w.cpart, sec<float>(blob, WX_MLP_GRAD + 5), st));
   // hidden layer 2
   if (int rc = input_grad(w.d3b, MLP_NOUTP, MLP_NOUTP, sec<uint16_t>(blob, WX_MLP_W3T_BF16), MLP_NHID, B, w.g2f, st))
     return rc;
@@ -259,7 +257,6 @@ int wx_mlp_forward_backward(void *blob, void *work, const void *x, const float *
   if (int rc = weight_grad(w.g2b, MLP_NHID, MLP_NHID, w.h1, MLP_NHID, MLP_NHID, B, w.part,
                            sec<float>(blob, WX_MLP_GRAD + 2), st))
     return rc;
-  MLP_HIP(launch_colsum(w.g2f, B, MLP_NHID, MLP_NHID, w.cpart, sec<float>(blob, WX_MLP_GRAD + 3), st));
   // hidden layer 1
   if (int rc = input_grad(w.g2b, MLP_NHID, MLP_NHID, sec<uint16_t>(blob, WX_MLP_W2T_BF16), MLP_NHID, B, w.g1f, st))
     return rc;
@@ -267,9 +264,16 @@ int wx_mlp_forward_backward(void *blob, void *work, const void *x, const float *
   if (int rc = weight_grad(w.g1b, MLP_NHID, MLP_NHID, w.xb, MLP_KIN, MLP_KIN, B, w.part,
                            sec<float>(blob, WX_MLP_GRAD + 0), st))
     return rc;
-  MLP_HIP(launch_colsum(w.g1f, B, MLP_NHID, MLP_NHID, w.cpart, sec<float>(blob, WX_MLP_GRAD + 1), st));
-  // loss: ordered sum of the per-row sums
-  MLP_HIP(launch_colsum(w.row_loss, B, 1, 1, w.cpart, loss_sum, st));
+  // bias gradients (column sums of the unrounded FP32 deltas) and the loss
+  // (sum of the per-row sums), one launch, fixed order
+  ColsumArgs cs{};
+  cs.rows = B;
+  cs.njobs = 4;
+  cs.job[0] = {w.d3f, MLP_NOUTP, MLP_NOUTP, sec<float>(blob, WX_MLP_GRAD + 5), MLP_NOUTP / 16, 1};
+  cs.job[1] = {w.g2f, MLP_NHID, MLP_NHID, sec<float>(blob, WX_MLP_GRAD + 3), MLP_NHID / 16, 1};
+  cs.job[2] = {w.g1f, MLP_NHID, MLP_NHID, sec<float>(blob, WX_MLP_GRAD + 1), MLP_NHID / 16, 1};
+  cs.job[3] = {w.row_loss, 1, 1, loss_sum, 1, 0};
+  MLP_HIP(launch_colsum_multi(cs, st));
   return WX_OK;
 }
 
@@ -284,10 +288,17 @@ int wx_mlp_adam(void *blob, float lr, int t, void *stream) {
                       sec<uint16_t>(blob, WX_MLP_W3T_BF16), nullptr};
   const int rows[6] = {MLP_NHID, 1, MLP_NHID, 1, MLP_NOUTP, 1};
   const int cols[6] = {MLP_KIN, MLP_NHID, MLP_NHID, MLP_NHID, MLP_NHID, MLP_NOUTP};
-  for (int p = 0; p < 6; ++p)
-    MLP_HIP(launch_adam(sec<float>(blob, p), sec<float>(blob, WX_MLP_GRAD + p), sec<float>(blob, WX_MLP_ADAM_M + p),
-                        sec<float>(blob, WX_MLP_ADAM_V + p), kParamElems[p], lr, bc1, bc2, wb[p], wbt[p], rows[p],
-                        cols[p], st));
+  AdamArgs aa{};
+  aa.lr = lr;
+  aa.bc1 = bc1;
+  aa.bc2 = bc2;
+  size_t start = 0;
+  for (int p = 0; p < 6; ++p) {
+    aa.seg[p] = {sec<float>(blob, p), sec<float>(blob, WX_MLP_GRAD + p), sec<float>(blob, WX_MLP_ADAM_M + p),
+                 sec<float>(blob, WX_MLP_ADAM_V + p), wb[p], wbt[p], start, kParamElems[p], rows[p], cols[p]};
+    start += kParamElems[p];
+  }
+  MLP_HIP(launch_adam_multi(aa, st));
   return WX_OK;
 }
 

@@ -96,10 +96,36 @@ hipError_t launch_gemm(const GemmSpec &g, hipStream_t s);
 hipError_t launch_sum_splits(const float *part, int nsplit, size_t stride, float *out, size_t n, hipStream_t s);
 hipError_t launch_loss(const float *y, const float *t, const int *rows, int batch, int nout, int ldy, float *d32,
                        uint16_t *d16, float *row_loss, hipStream_t s);
-hipError_t launch_colsum(const float *a, int rows, int cols, int lda, float *part, float *out, hipStream_t s);
 hipError_t launch_mask_round(float *a, const uint16_t *mask, size_t n, uint16_t *out, hipStream_t s);
-hipError_t launch_adam(float *w, const float *g, float *m, float *v, size_t n, float lr, float bc1, float bc2,
-                       uint16_t *wb, uint16_t *wbt, int rows, int cols, hipStream_t s);
+
+// Column sums of up to four matrices in one launch (fixed order).
+struct ColsumJob {
+  const float *a;   // [rows][lda]
+  int cols, lda;
+  float *out;       // [cols]
+  int blocks;       // (cols + 15) / 16
+  int vec;          // cols and lda multiples of 4, a 16-byte aligned
+};
+struct ColsumArgs {
+  ColsumJob job[4];
+  int njobs, rows;
+};
+hipError_t launch_colsum_multi(const ColsumArgs &a, hipStream_t s);
+
+// Adam over the six parameter tensors in one launch.
+struct AdamSeg {
+  float *w;
+  const float *g;
+  float *m, *v;
+  uint16_t *wb, *wbt;   // BF16 copy and transpose (may be null)
+  size_t start, n;      // range in the concatenation
+  int rows, cols;
+};
+struct AdamArgs {
+  AdamSeg seg[6];
+  float lr, bc1, bc2;
+};
+hipError_t launch_adam_multi(const AdamArgs &a, hipStream_t s);
 hipError_t launch_to_bf16(const float *w, size_t n, uint16_t *wb, uint16_t *wbt, int rows, int cols, hipStream_t s);
 hipError_t launch_he_init(float *w, int ld, int fan_out, int fan_in, uint64_t seed, int tensor, float bound,
                           hipStream_t s);
