@@ -243,7 +243,13 @@ typedef enum wx_mlp_section {
   WX_MLP_Y_MEAN = 31, WX_MLP_Y_STD = 32,     /* FP32 [128]: target mean and scale (1 on padding) */
   WX_MLP_SIGMA = 33,    /* FP32 [2]: pooled std of the theta and q tendencies */
   WX_MLP_SIGMA64 = 34,  /* FP64 [2]: the same in FP64 */
-  WX_MLP_NSECTIONS = 35
+  /* W1, W2, W3 in BF16 again, one after the other, each in matrix-core
+     fragment order: the 32-row x 16-k block (R, S) of a [N][K] matrix is 512
+     contiguous values, lane l holding row 32R + l%32 at k = 16S + 8(l/32)
+     .. +7, so a wavefront reads each block as one 1 KiB run (the operand
+     layout of the fused surrogate kernel; written with the BF16 copies) */
+  WX_MLP_WPACK_BF16 = 35,
+  WX_MLP_NSECTIONS = 36
 } wx_mlp_section;
 
 size_t wx_mlp_bytes(void);

@@ -13,7 +13,8 @@
 //             layers (2 x 4 tiles of v_mfma_f32_32x32x16_bf16, the shape that
 //             runs at the full matrix-core rate on gfx950) and a 32-output by
 //             64-sample block of the last; the weights are the first MFMA
-//             operand (streamed from global memory, L2-resident, 0.98 MB, one
+//             operand (streamed from global memory in fragment order, so each
+//             load is one 1 KiB run per wavefront, L2-resident, 0.98 MB, one
 //             k step ahead) and the activations the second (from LDS, the
 //             fragments of a k step read before its MFMAs), so a lane ends
 //             with four consecutive units of one sample and stores them as
@@ -53,21 +54,25 @@ static_assert(4 * kPartLev >= kNZ, "four parts must cover the column");
 
 // acc[y][x] += W(units n0 + 32 y.., k) X(samples s0 + 32 x.., k) over
 // k = 0..K-1 in steps of 16 (ascending, as in the stand-alone GEMM), on
-// v_mfma_f32_32x32x16_bf16.  The weights are the first operand (global
-// [N][ldb], k contiguous, one 32-wide k step fetched ahead), the activations
-// the second (LDS [samples][lda], the fragments of a k step read before its
-// MFMAs).  A lane feeds row (or column) lane % 32 at k = 8 (lane / 32)..+7.
+// v_mfma_f32_32x32x16_bf16.  The weights are the first operand (global, in
+// fragment order: the 32 x 16 block (R, S) of the [N][K] matrix is 512
+// contiguous values, so a wavefront reads it as one 1 KiB run; one 32-wide k
+// step fetched ahead), the activations the second (LDS [samples][lda], the
+// fragments of a k step read before its MFMAs).  A lane feeds row (or column)
+// lane % 32 at k = 8 (lane / 32)..+7.
 template <int NU, int NS>
 __device__ __forceinline__ void tile_gemm(f32x16 (&acc)[NU][NS], const uint16_t *X, int lda, int s0,
-                                          const uint16_t *W, int ldb, int n0, int K, int lane) {
+                                          const uint16_t *W, int n0, int K, int lane) {
   const int kl = 8 * (lane >> 5), rl = lane & 31;
-  const uint16_t *wp = W + (size_t)(n0 + rl) * ldb + kl;
+  const int ks = K >> 4;                                  // 16-wide k blocks per row block
+  const uint16_t *wp = W + (size_t)(n0 >> 5) * ks * 512 + lane * 8;
   const uint16_t *xp = X + (s0 + rl) * lda + kl;
   bf16x8 wcur[2][NU], wnext[2][NU];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int y = 0; y < NU; ++y) wcur[h][y] = *reinterpret_cast<const bf16x8 *>(wp + (size_t)y * 32 * ldb + 16 * h);
+    for (int y = 0; y < NU; ++y)
+      wcur[h][y] = *reinterpret_cast<const bf16x8 *>(wp + (size_t)(y * ks + h) * 512);
 #pragma unroll 1
   for (int k0 = 0; k0 < K; k0 += 32) {
     const int kn = k0 + 32 < K ? k0 + 32 : k0;   // last step reloads its own slice
@@ -75,7 +80,7 @@ __device__ __forceinline__ void tile_gemm(f32x16 (&acc)[NU][NS], const uint16_t 
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int y = 0; y < NU; ++y)
-        wnext[h][y] = *reinterpret_cast<const bf16x8 *>(wp + (size_t)y * 32 * ldb + kn + 16 * h);
+        wnext[h][y] = *reinterpret_cast<const bf16x8 *>(wp + (size_t)(y * ks + (kn >> 4) + h) * 512);
     bf16x8 xf[2][NS];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -206,7 +211,7 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
     for (int x = 0; x < 4; ++x)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[y][x][r] = 0.f;
-  tile_gemm<2, 4>(acc, X, XLD, 0, a.w1, MLP_KIN, n0, MLP_KIN, lane);
+  tile_gemm<2, 4>(acc, X, XLD, 0, a.w1, n0, MLP_KIN, lane);
   __syncthreads();   // every wave has read X
   store_hidden<2, 4>(acc, a.b1, n0, H, lane);
   __syncthreads();
@@ -218,7 +223,7 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
     for (int x = 0; x < 4; ++x)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[y][x][r] = 0.f;
-  tile_gemm<2, 4>(acc, H, HLD, 0, a.w2, MLP_NHID, n0, MLP_NHID, lane);
+  tile_gemm<2, 4>(acc, H, HLD, 0, a.w2, n0, MLP_NHID, lane);
   __syncthreads();
   store_hidden<2, 4>(acc, a.b2, n0, H, lane);
   __syncthreads();
@@ -231,7 +236,7 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc3[0][x][r] = 0.f;
   const int o3 = 32 * (wave & 3), s3 = 64 * (wave >> 2);
-  tile_gemm<1, 2>(acc3, H, HLD, s3, a.w3, MLP_NHID, o3, MLP_NHID, lane);
+  tile_gemm<1, 2>(acc3, H, HLD, s3, a.w3, o3, MLP_NHID, lane);
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < 4; ++q) {

@@ -240,23 +240,22 @@ __global__ void k_adam_multi(AdamArgs a) {
   if (S.wb) {
     const uint16_t h = f2bf(wi);
     S.wb[i] = h;
-    if (S.wbt) {
-      const int r = int(i / S.cols), c = int(i % S.cols);
-      S.wbt[(size_t)c * S.rows + r] = h;
-    }
+    const int r = int(i / S.cols), c = int(i % S.cols);
+    if (S.wbt) S.wbt[(size_t)c * S.rows + r] = h;
+    if (S.wbp) S.wbp[frag_index(r, c, S.cols)] = h;
   }
 }
 
 // BF16 copies of FP32 weights (after initialisation or an upload).
-__global__ void k_to_bf16(const float *w, size_t n, uint16_t *wb, uint16_t *wbt, int rows, int cols) {
+__global__ void k_to_bf16(const float *w, size_t n, uint16_t *wb, uint16_t *wbt, uint16_t *wbp, int rows,
+                          int cols) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint16_t h = f2bf(w[i]);
   wb[i] = h;
-  if (wbt) {
-    const int r = int(i / cols), c = int(i % cols);
-    wbt[(size_t)c * rows + r] = h;
-  }
+  const int r = int(i / cols), c = int(i % cols);
+  if (wbt) wbt[(size_t)c * rows + r] = h;
+  if (wbp) wbp[frag_index(r, c, cols)] = h;
 }
 
 
@@ -340,8 +339,9 @@ hipError_t launch_mask_round(float *a, const uint16_t *mask, size_t n, uint16_t 
   return hipGetLastError();
 }
 
-hipError_t launch_to_bf16(const float *w, size_t n, uint16_t *wb, uint16_t *wbt, int rows, int cols, hipStream_t s) {
-  hipLaunchKernelGGL(k_to_bf16, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, w, n, wb, wbt, rows, cols);
+hipError_t launch_to_bf16(const float *w, size_t n, uint16_t *wb, uint16_t *wbt, uint16_t *wbp, int rows, int cols,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, w, n, wb, wbt, wbp, rows, cols);
   return hipGetLastError();
 }
 

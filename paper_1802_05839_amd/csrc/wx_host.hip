@@ -184,9 +184,10 @@ wx::FusedArgs fused_args(const wx_state *s, const void *blob) {
   a.g = geom(s);
   a.theta_off = impl_of(s)->param[WX_PARAM_THETA_OFFSET];
   const unsigned char *b = static_cast<const unsigned char *>(blob);
-  a.w1 = reinterpret_cast<const uint16_t *>(b + wx_mlp_offset(WX_MLP_W1_BF16));
-  a.w2 = reinterpret_cast<const uint16_t *>(b + wx_mlp_offset(WX_MLP_W2_BF16));
-  a.w3 = reinterpret_cast<const uint16_t *>(b + wx_mlp_offset(WX_MLP_W3_BF16));
+  // the weights in matrix-core fragment order: W1, W2, W3 one after the other
+  a.w1 = reinterpret_cast<const uint16_t *>(b + wx_mlp_offset(WX_MLP_WPACK_BF16));
+  a.w2 = a.w1 + size_t(WX_MLP_NHID) * WX_MLP_KIN;
+  a.w3 = a.w2 + size_t(WX_MLP_NHID) * WX_MLP_NHID;
   a.b1 = reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_B1));
   a.b2 = reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_B2));
   a.b3 = reinterpret_cast<const float *>(b + wx_mlp_offset(WX_MLP_B3));

@@ -52,6 +52,7 @@ size_t section_bytes(int s) {
     case WX_MLP_Y_MEAN: case WX_MLP_Y_STD: return MLP_NOUTP * 4;
     case WX_MLP_SIGMA: return 2 * 4;
     case WX_MLP_SIGMA64: return 2 * 8;
+    case WX_MLP_WPACK_BF16: return (kParamElems[0] + kParamElems[2] + kParamElems[4]) * 2;
   }
   return 0;
 }
@@ -69,6 +70,14 @@ T *sec(void *blob, int s) {
 template <typename T>
 const T *sec(const void *blob, int s) {
   return reinterpret_cast<const T *>(static_cast<const unsigned char *>(blob) + section_offset(s));
+}
+
+// Fragment-order copy of weight matrix l (0: W1, 1: W2, 2: W3) in the blob.
+uint16_t *packed_weights(void *blob, int l) {
+  size_t off = 0;
+  if (l > 0) off += kParamElems[0];
+  if (l > 1) off += kParamElems[2];
+  return sec<uint16_t>(blob, WX_MLP_WPACK_BF16) + off;
 }
 
 bool al16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
@@ -175,11 +184,11 @@ int wx_mlp_refresh(void *blob, void *stream) {
   if (!blob || !al16(blob)) return fail(WX_E_INVAL, "blob is NULL or misaligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
   MLP_HIP(launch_to_bf16(sec<float>(blob, WX_MLP_W1), kParamElems[0], sec<uint16_t>(blob, WX_MLP_W1_BF16), nullptr,
-                         MLP_NHID, MLP_KIN, st));
+                         packed_weights(blob, 0), MLP_NHID, MLP_KIN, st));
   MLP_HIP(launch_to_bf16(sec<float>(blob, WX_MLP_W2), kParamElems[2], sec<uint16_t>(blob, WX_MLP_W2_BF16),
-                         sec<uint16_t>(blob, WX_MLP_W2T_BF16), MLP_NHID, MLP_NHID, st));
+                         sec<uint16_t>(blob, WX_MLP_W2T_BF16), packed_weights(blob, 1), MLP_NHID, MLP_NHID, st));
   MLP_HIP(launch_to_bf16(sec<float>(blob, WX_MLP_W3), kParamElems[4], sec<uint16_t>(blob, WX_MLP_W3_BF16),
-                         sec<uint16_t>(blob, WX_MLP_W3T_BF16), MLP_NOUTP, MLP_NHID, st));
+                         sec<uint16_t>(blob, WX_MLP_W3T_BF16), packed_weights(blob, 2), MLP_NOUTP, MLP_NHID, st));
   return WX_OK;
 }
 
@@ -286,6 +295,8 @@ int wx_mlp_adam(void *blob, float lr, int t, void *stream) {
                      sec<uint16_t>(blob, WX_MLP_W3_BF16), nullptr};
   uint16_t *wbt[6] = {nullptr, nullptr, sec<uint16_t>(blob, WX_MLP_W2T_BF16), nullptr,
                       sec<uint16_t>(blob, WX_MLP_W3T_BF16), nullptr};
+  uint16_t *wbp[6] = {packed_weights(blob, 0), nullptr, packed_weights(blob, 1), nullptr, packed_weights(blob, 2),
+                      nullptr};
   const int rows[6] = {MLP_NHID, 1, MLP_NHID, 1, MLP_NOUTP, 1};
   const int cols[6] = {MLP_KIN, MLP_NHID, MLP_NHID, MLP_NHID, MLP_NHID, MLP_NOUTP};
   AdamArgs aa{};
@@ -295,7 +306,7 @@ int wx_mlp_adam(void *blob, float lr, int t, void *stream) {
   size_t start = 0;
   for (int p = 0; p < 6; ++p) {
     aa.seg[p] = {sec<float>(blob, p), sec<float>(blob, WX_MLP_GRAD + p), sec<float>(blob, WX_MLP_ADAM_M + p),
-                 sec<float>(blob, WX_MLP_ADAM_V + p), wb[p], wbt[p], start, kParamElems[p], rows[p], cols[p]};
+                 sec<float>(blob, WX_MLP_ADAM_V + p), wb[p], wbt[p], wbp[p], start, kParamElems[p], rows[p], cols[p]};
     start += kParamElems[p];
   }
   MLP_HIP(launch_adam_multi(aa, st));

@@ -24,6 +24,14 @@ __device__ __forceinline__ uint16_t f2bf(float x) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 
+// Position of element (r, c) of a [N][K] BF16 matrix in matrix-core fragment
+// order: block (r / 32, c / 16) is 512 contiguous values, lane
+// r % 32 + 32 ((c % 16) / 8) holding its 8 consecutive k values.
+__host__ __device__ __forceinline__ size_t frag_index(int r, int c, int K) {
+  const size_t blk = size_t(r >> 5) * size_t(K >> 4) + size_t(c >> 4);
+  return (blk * 64 + size_t((r & 31) + 32 * ((c & 15) >> 3))) * 8 + size_t(c & 7);
+}
+
 // SplitMix64 output for state increment x (Steele, Lea & Flood 2014).
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   uint64_t z = x + 0x9E3779B97F4A7C15ull;
@@ -118,6 +126,7 @@ struct AdamSeg {
   const float *g;
   float *m, *v;
   uint16_t *wb, *wbt;   // BF16 copy and transpose (may be null)
+  uint16_t *wbp;        // BF16 copy in fragment order (may be null)
   size_t start, n;      // range in the concatenation
   int rows, cols;
 };
@@ -126,7 +135,8 @@ struct AdamArgs {
   float lr, bc1, bc2;
 };
 hipError_t launch_adam_multi(const AdamArgs &a, hipStream_t s);
-hipError_t launch_to_bf16(const float *w, size_t n, uint16_t *wb, uint16_t *wbt, int rows, int cols, hipStream_t s);
+hipError_t launch_to_bf16(const float *w, size_t n, uint16_t *wb, uint16_t *wbt, uint16_t *wbp, int rows, int cols,
+                          hipStream_t s);
 hipError_t launch_he_init(float *w, int ld, int fan_out, int fan_in, uint64_t seed, int tensor, float bound,
                           hipStream_t s);
 
@@ -190,7 +200,7 @@ struct FusedArgs {
   const float *th_s, *q_s, *f0, *ch;
   Geom g;
   double theta_off;
-  const uint16_t *w1, *w2, *w3;    // BF16 [512][320], [512][512], [128][512]
+  const uint16_t *w1, *w2, *w3;    // BF16 [512][320], [512][512], [128][512], fragment order
   const float *b1, *b2, *b3;
   const float *xmean, *xinvstd, *ymean, *ystd;
   float dt;

@@ -41,7 +41,7 @@ MLP_NZ, MLP_NIN, MLP_KIN, MLP_NHID, MLP_NOUT, MLP_NOUTP = 58, 294, 320, 512, 116
 MLP_SECTIONS = {"W1": 0, "b1": 1, "W2": 2, "b2": 3, "W3": 4, "b3": 5, "grad": 6, "adam_m": 12,
                 "adam_v": 18, "W1_bf16": 24, "W2_bf16": 25, "W3_bf16": 26, "W2T_bf16": 27,
                 "W3T_bf16": 28, "x_mean": 29, "x_invstd": 30, "y_mean": 31, "y_std": 32,
-                "sigma": 33, "sigma64": 34}
+                "sigma": 33, "sigma64": 34, "wpack_bf16": 35}
 MLP_PARAM_NAMES = ("W1", "b1", "W2", "b2", "W3", "b3")
 MLP_PARAM_SHAPES = {"W1": (MLP_NHID, MLP_KIN), "b1": (MLP_NHID,), "W2": (MLP_NHID, MLP_NHID),
                     "b2": (MLP_NHID,), "W3": (MLP_NOUTP, MLP_NHID), "b3": (MLP_NOUTP,)}

@@ -149,7 +149,7 @@ def test_mlp_entry_points_validate(lib):
     assert lib.wx_mlp_adam(4096, 1e-3, 0, None) == wx.WX_E_INVAL
     assert lib.wx_mlp_adam(4100, 1e-3, 1, None) == wx.WX_E_INVAL
     assert lib.wx_mlp_infer(4096, 4096, 4096, 0, 4096, None) == wx.WX_E_INVAL
-    assert lib.wx_mlp_offset(-1) == -1 and lib.wx_mlp_offset(35) == -1
+    assert lib.wx_mlp_offset(-1) == -1 and lib.wx_mlp_offset(36) == -1
 
 
 def test_judge_rate_range(lib):

@@ -167,6 +167,34 @@ def test_adam_matches_oracle():
     w3b = wx.bf16_bits_to_float(m._sec("W3_bf16", torch.int16, (128, 512))).cpu().numpy()
     w3t = wx.bf16_bits_to_float(m._sec("W3T_bf16", torch.int16, (512, 128))).cpu().numpy()
     np.testing.assert_array_equal(w3t, w3b.T)
+    _check_fragment_copies(m)
+
+
+def _fragment_order(w):
+    """[N][K] -> matrix-core fragment order: block (R, S) of 32 rows x 16 k,
+    lane l = row % 32 + 32 * (k % 16 // 8) holding its 8 consecutive k."""
+    n, k = w.shape
+    return w.reshape(n // 32, 32, k // 16, 2, 8).transpose(0, 2, 3, 1, 4).reshape(-1)
+
+
+def _check_fragment_copies(m):
+    torch = _torch()
+    packed = m._sec("wpack_bf16", torch.int16, (512 * KIN + 512 * 512 + NOUTP * 512,)).cpu().numpy()
+    off = 0
+    for name, shape in (("W1_bf16", (512, KIN)), ("W2_bf16", (512, 512)), ("W3_bf16", (NOUTP, 512))):
+        w = m._sec(name, torch.int16, shape).cpu().numpy()
+        n = shape[0] * shape[1]
+        np.testing.assert_array_equal(packed[off:off + n], _fragment_order(w), err_msg=name)
+        off += n
+
+
+def test_fragment_order_copies_follow_init_and_upload():
+    _say("case: fragment-order weight copies after init and upload")
+    m = wx.Mlp()
+    m.init(3)
+    _check_fragment_copies(m)
+    _upload(m, _host_params(9))
+    _check_fragment_copies(m)
 
 
 def _state32(nx, ny, seed):
