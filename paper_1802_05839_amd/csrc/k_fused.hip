@@ -27,7 +27,8 @@
 //
 // LDS (133,120 B, one workgroup per CU): the input tile [128][328] BF16, the
 // hidden tile [128][520] BF16 and the output tile [128][129] FP32 alias one
-// buffer; barriers separate the phases.  Padded row strides keep the 16-byte
+// buffer, with the normalisation constants of the inputs (outputs) just past
+// the input (output) tile; barriers separate the phases.  Padded row strides keep the 16-byte
 // fragment reads free of bank conflicts.
 #include "wx_internal.h"
 #include "wx_mlp_internal.h"
@@ -46,6 +47,13 @@ constexpr int YLD = MLP_NOUTP + 1;       // 129 (FP32)
 constexpr int LDS_BYTES = FT * HLD * 2;  // 133,120
 static_assert(FT * XLD * 2 <= LDS_BYTES, "input tile must fit the shared buffer");
 static_assert(FT * YLD * 4 <= LDS_BYTES, "output tile must fit the shared buffer");
+// (mean, 1/std) of the features beside the input tile, and (mean, std) of the
+// targets beside the output tile: read from LDS, the same value for a whole
+// wavefront, instead of one vector load per feature and thread
+constexpr int XNORM_OFF = FT * XLD * 2;
+constexpr int YNORM_OFF = FT * YLD * 4;
+static_assert(XNORM_OFF % 16 == 0 && XNORM_OFF + MLP_KIN * 8 <= LDS_BYTES, "feature constants must fit");
+static_assert(YNORM_OFF % 16 == 0 && YNORM_OFF + MLP_NOUTP * 8 <= LDS_BYTES, "target constants must fit");
 constexpr double kThetaRef = 300.0;      // theta features are theta - 300 K
 constexpr int kNZ = MLP_NZ;              // levels (the network is built for 58)
 constexpr int kHalf = (kNZ + 1) / 2;     // levels per thread in the update
@@ -139,6 +147,9 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
   float *Y = reinterpret_cast<float *>(lds);
 
   // ---- feature rows -> X ---------------------------------------------------
+  float2 *xn = reinterpret_cast<float2 *>(lds + XNORM_OFF);
+  for (int f = tid; f < MLP_KIN; f += FTHREADS) xn[f] = make_float2(a.xmean[f], a.xinvstd[f]);
+  __syncthreads();
   {
     const int col = tid & (FT - 1), part = tid >> 7;
     const int r = r0 + col;
@@ -146,7 +157,10 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
     if (r < nrows) c = rows_mode ? (a.list ? a.list[r] : r) : a.c0 + r;
     if (c >= nx * a.g.ny) c = -1;                    // not a column: zero row
     uint16_t *xr = X + col * XLD;
-    auto put = [&](int f, float x) { xr[f] = f2bf((x - a.xmean[f]) * a.xinvstd[f]); };
+    auto put = [&](int f, float x) {
+      const float2 mn = xn[f];
+      xr[f] = f2bf((x - mn.x) * mn.y);
+    };
     if (c < 0) {
       for (int f = part; f < MLP_KIN; f += 4) xr[f] = 0;
     } else {
@@ -246,6 +260,9 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) Y[(s3 + 32 * x + (lane & 31)) * YLD + o + c] = acc3[0][x][4 * q + c] + a.b3[o + c];
   }
+  float2 *yn = reinterpret_cast<float2 *>(lds + YNORM_OFF);
+  if (!rows_mode)
+    for (int o = tid; o < MLP_NOUTP; o += FTHREADS) yn[o] = make_float2(a.ymean[o], a.ystd[o]);
   __syncthreads();
 
   // ---- outputs ----------------------------------------------------------------
@@ -280,7 +297,8 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
 #pragma unroll
   for (int k = 0; k < kHalf; ++k) {
     if (k >= nk) break;
-    const float tend = fmaf(yr[k], a.ystd[ob + k], a.ymean[ob + k]);
+    const float2 ms = yn[ob + k];
+    const float tend = fmaf(yr[k], ms.y, ms.x);
     const float nv = fmaf(a.dt, tend, old[k]);
     const unsigned g = gb + unsigned(k) * a.g.sk;
     stg(fld, g, nv);
