@@ -19,6 +19,8 @@ physics  implicit vertical diffusion (Thomas) and the transmissivity k-scan
 step     one full step = RK3 dycore followed by column physics
 mass     compensated global mass sums
 mlp      the surrogate network: forward, backward, Adam, with BF16 rounding
+reduced  the paper's reduced weather application (7-point diffusion, column
+         radiation and boundary heat exchange), to the last bit
 
 Parity status: every function here is pinned by the CPU tests
 (``tests/test_oracle_*.py``) against closed forms, invariants, a dense LAPACK

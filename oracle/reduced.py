@@ -1,0 +1,140 @@
+"""FP64 oracle of the paper's reduced weather application (test infrastructure only).
+
+What the paper fixes (section "Reduced Weather Application" and the appendix
+sources "Reduced Weather: Diffusion", "Physical Processes", "Radiation",
+"Heat Exchange" and "Time Integration"):
+
+* one field, the thermal energy E, over i = 0..nx+1, j = 0..ny+1 (a one-cell
+  ring around the nx x ny interior) and k = 1..nz, stored with i fastest,
+  then j, then k;
+* a time step is the column physics on every column (ring included) followed
+  by one explicit-Euler diffusion step into a second array, after which the
+  two arrays swap roles;
+* physics, per column and in this order: radiation adds 0.1 to every level;
+  the bottom level (k = 1) gives up 0.01 times its excess over the surface
+  value; the top level (k = nz) gives up 0.01 times its excess over the
+  boundary-layer value;
+* diffusion with the diffusion number nu:
+    interior columns, levels 2..nz-1: E (1 - 6 nu) + nu (sum of the six
+        face neighbours, added in the order i-1, i+1, j-1, j+1, k-1, k+1);
+    interior columns, level 1 and level nz: E (1 - 5 nu) + nu (the four
+        horizontal neighbours in the same order, then the one vertical
+        neighbour);
+    ring rows j = 0 and j = ny+1 (every i): E (1 - 2 nu) + nu (the row's
+        inner neighbour, then the opposite ring row);
+    ring columns i = 0 and i = nx+1 (every j, written after the rows, so the
+        four corner columns take this rule): E (1 - 2 nu) + nu (the inner
+        neighbour, then the opposite ring column);
+* initial state 0 with a 300 box over the middle half of each dimension;
+  the surface and boundary-layer values are 330 and 200; the time step is
+  0.1 s.
+
+Readings (the paper leaves them open):
+
+* R-rw-nu: the diffusion number nu (the printed code's diffusion velocity
+  has no value in the paper) is a parameter, 0.1 by default (stable: the
+  interior weight 1 - 6 nu stays positive).
+* R-rw-box: a cell (1-based interior indices i, j, k) lies in the initial box
+  when n/4 < index <= 3 n/4 in each dimension; the ring starts at 0.
+* R-rw-names: the printed diffusion writes its interior result under one
+  array name and its boundary results under another; both are the output
+  array.
+* nz >= 2 (the level-nz rule reads level nz - 1).
+
+Every operation is done in the order written above, in float64, with no
+fused multiply-add: the result is the printed program's to the last bit.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SURFACE = 330.0
+PBL = 200.0
+RADIATION = 0.1
+TRANSFER = 0.01
+DT = 0.1
+NU_DEFAULT = 0.1
+
+
+def shape(nx: int, ny: int, nz: int):
+    """Array shape (k, j, i) of the field, ring included."""
+    return (nz, ny + 2, nx + 2)
+
+
+def box_init(nx: int, ny: int, nz: int) -> np.ndarray:
+    """The initial field: 300 on the middle half of each dimension, else 0 (R-rw-box)."""
+    e = np.zeros(shape(nx, ny, nz))
+
+    def inside(n, idx):
+        return (idx * 4 > n) & (idx * 4 <= 3 * n)
+
+    ii = inside(nx, np.arange(nx + 2))
+    jj = inside(ny, np.arange(ny + 2))
+    kk = inside(nz, np.arange(1, nz + 1))
+    e[np.ix_(kk, jj, ii)] = 300.0
+    return e
+
+
+def boundary_fields(nx: int, ny: int):
+    """Surface and boundary-layer values over the (ny + 2) x (nx + 2) columns."""
+    return np.full((ny + 2, nx + 2), SURFACE), np.full((ny + 2, nx + 2), PBL)
+
+
+def run_physics(e: np.ndarray, surf: np.ndarray, pbl: np.ndarray) -> np.ndarray:
+    """Radiation, then the surface exchange, then the boundary-layer exchange."""
+    nz = e.shape[0]
+    out = e + RADIATION
+    lost = TRANSFER * (out[0] - surf)
+    out[0] = out[0] - lost
+    lost = TRANSFER * (out[nz - 1] - pbl)
+    out[nz - 1] = out[nz - 1] - lost
+    return out
+
+
+def diffuse(e: np.ndarray, nu: float) -> np.ndarray:
+    """One explicit-Euler diffusion step into a new array (rules in the module docstring)."""
+    nz, nyp, nxp = e.shape
+    if nz < 2:
+        raise ValueError("the reduced application needs nz >= 2")
+    ny, nx = nyp - 2, nxp - 2
+    out = np.zeros_like(e)
+    J, I = slice(1, ny + 1), slice(1, nx + 1)
+    c6 = 1.0 - 6.0 * nu
+    c5 = 1.0 - 5.0 * nu
+    c2 = 1.0 - 2.0 * nu
+
+    # interior columns, levels 2..nz-1 (0-based 1..nz-2)
+    if nz > 2:
+        K = slice(1, nz - 1)
+        s = e[K, J, 0:nx] + e[K, J, 2:nx + 2]
+        s = s + e[K, 0:ny, I]
+        s = s + e[K, 2:ny + 2, I]
+        s = s + e[0:nz - 2, J, I]
+        s = s + e[2:nz, J, I]
+        out[K, J, I] = e[K, J, I] * c6 + nu * s
+
+    # interior columns, level 1 and level nz
+    for k, kv in ((0, 1), (nz - 1, nz - 2)):
+        s = e[k, J, 0:nx] + e[k, J, 2:nx + 2]
+        s = s + e[k, 0:ny, I]
+        s = s + e[k, 2:ny + 2, I]
+        s = s + e[kv, J, I]
+        out[k, J, I] = e[k, J, I] * c5 + nu * s
+
+    # ring rows, then ring columns (the corners keep the column rule)
+    out[:, 0, :] = e[:, 0, :] * c2 + nu * (e[:, 1, :] + e[:, ny + 1, :])
+    out[:, ny + 1, :] = e[:, ny + 1, :] * c2 + nu * (e[:, ny, :] + e[:, 0, :])
+    out[:, :, 0] = e[:, :, 0] * c2 + nu * (e[:, :, 1] + e[:, :, nx + 1])
+    out[:, :, nx + 1] = e[:, :, nx + 1] * c2 + nu * (e[:, :, nx] + e[:, :, 0])
+    return out
+
+
+def step(e: np.ndarray, surf: np.ndarray, pbl: np.ndarray, nu: float = NU_DEFAULT) -> np.ndarray:
+    """One time step: column physics, then diffusion (the swap is the return)."""
+    return diffuse(run_physics(e, surf, pbl), nu)
+
+
+def simulate(e: np.ndarray, surf: np.ndarray, pbl: np.ndarray, nsteps: int, nu: float = NU_DEFAULT) -> np.ndarray:
+    for _ in range(nsteps):
+        e = step(e, surf, pbl, nu)
+    return e

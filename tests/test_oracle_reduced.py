@@ -1,0 +1,134 @@
+"""Pins of the reduced weather application oracle (CPU only).
+
+Each pin fixes the rules of the paper's printed reduced application by a
+value that follows from them independently of the oracle's code: a constant
+field is a fixed point, single-cell impulses give the stencil weights and
+which cells each rule reaches (including the corner columns, which take the
+ring-column rule), a quadratic field gives the exact discrete Laplacian, and
+the physics relaxes the boundary levels to the closed-form fixed point.
+Dyadic values (nu = 1/8, integer fields) make the expected values exact.
+"""
+import numpy as np
+import pytest
+
+from oracle import reduced as rw
+
+NU = 0.125
+
+
+def _impulse(nx, ny, nz, k, j, i):
+    e = np.zeros(rw.shape(nx, ny, nz))
+    e[k, j, i] = 1.0
+    return e
+
+
+def _nonzero(a):
+    return {tuple(int(v) for v in idx): a[tuple(idx)] for idx in np.argwhere(a != 0)}
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(5, 4, 2), (6, 7, 3), (9, 5, 6)])
+def test_constant_field_is_a_fixed_point_of_diffusion(nx, ny, nz):
+    e = np.full(rw.shape(nx, ny, nz), 256.0)
+    np.testing.assert_array_equal(rw.diffuse(e, NU), e)
+
+
+def test_interior_impulse_gives_the_seven_point_weights():
+    nx, ny, nz = 8, 7, 6
+    out = rw.diffuse(_impulse(nx, ny, nz, 3, 4, 5), NU)
+    want = {(3, 4, 5): 1 - 6 * NU, (3, 4, 4): NU, (3, 4, 6): NU, (3, 3, 5): NU, (3, 5, 5): NU,
+            (2, 4, 5): NU, (4, 4, 5): NU}
+    assert _nonzero(out) == want
+
+
+def test_bottom_and_top_levels_use_five_neighbours():
+    nx, ny, nz = 6, 6, 4
+    out = rw.diffuse(_impulse(nx, ny, nz, 0, 3, 3), NU)
+    assert _nonzero(out) == {(0, 3, 3): 1 - 5 * NU, (0, 3, 2): NU, (0, 3, 4): NU, (0, 2, 3): NU,
+                             (0, 4, 3): NU, (1, 3, 3): NU}
+    out = rw.diffuse(_impulse(nx, ny, nz, nz - 1, 2, 5), NU)
+    assert _nonzero(out) == {(nz - 1, 2, 5): 1 - 5 * NU, (nz - 1, 2, 4): NU, (nz - 1, 2, 6): NU,
+                             (nz - 1, 1, 5): NU, (nz - 1, 3, 5): NU, (nz - 2, 2, 5): NU}
+
+
+def test_two_level_columns():
+    # nz = 2: both levels take the five-neighbour rule, each other's vertical neighbour
+    nx, ny = 4, 3
+    out = rw.diffuse(_impulse(nx, ny, 2, 1, 2, 2), NU)
+    assert out[1, 2, 2] == 1 - 5 * NU and out[0, 2, 2] == NU
+
+
+def test_ring_row_reaches_the_opposite_row_and_not_the_corner_rule():
+    nx, ny, nz = 5, 4, 3
+    # a cell of ring row j = 0 at an interior i: itself, the opposite ring row,
+    # and the interior cell above it (its j-1 neighbour)
+    out = rw.diffuse(_impulse(nx, ny, nz, 1, 0, 2), NU)
+    assert _nonzero(out) == {(1, 0, 2): 1 - 2 * NU, (1, ny + 1, 2): NU, (1, 1, 2): NU}
+
+
+def test_corner_columns_take_the_ring_column_rule():
+    nx, ny, nz = 5, 4, 3
+    # corner (j = 0, i = 0): the column rule pairs it with (0, nx+1) only; the
+    # row rule (written first, then overwritten) would have reached (ny+1, 0)
+    out = rw.diffuse(_impulse(nx, ny, nz, 2, 0, 0), NU)
+    assert _nonzero(out) == {(2, 0, 0): 1 - 2 * NU, (2, 0, nx + 1): NU}
+    assert out[2, ny + 1, 0] == 0.0
+    # a ring-column cell at an interior j reaches the opposite column and the
+    # interior cell to its right
+    out = rw.diffuse(_impulse(nx, ny, nz, 0, 2, nx + 1), NU)
+    assert _nonzero(out) == {(0, 2, nx + 1): 1 - 2 * NU, (0, 2, 0): NU, (0, 2, nx): NU}
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_quadratic_field_gives_the_exact_laplacian(axis):
+    # interior levels of interior columns: E + nu (sum of neighbours - 6 E)
+    # and a quadratic along one axis has second difference 2
+    nx, ny, nz = 7, 6, 7
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny + 2), np.arange(nx + 2), indexing="ij")
+    e = ((k, j, i)[axis] ** 2).astype(np.float64)
+    out = rw.diffuse(e, NU)
+    inner = (slice(1, nz - 1), slice(1, ny + 1), slice(1, nx + 1))
+    np.testing.assert_array_equal(out[inner], e[inner] + 2 * NU)
+
+
+def test_physics_closed_forms():
+    nx, ny, nz = 3, 2, 5
+    e = np.full(rw.shape(nx, ny, nz), 300.0)
+    surf, pbl = rw.boundary_fields(nx, ny)
+    out = rw.run_physics(e, surf, pbl)
+    np.testing.assert_array_equal(out[1:nz - 1], 300.0 + 0.1)
+    b = 300.0 + 0.1
+    np.testing.assert_allclose(out[0], b - 0.01 * (b - 330.0), rtol=1e-15)
+    np.testing.assert_allclose(out[nz - 1], b - 0.01 * (b - 200.0), rtol=1e-15)
+    assert out[0, 0, 0] > b > out[nz - 1, 0, 0]
+
+
+def test_boundary_levels_relax_to_the_heat_well_fixed_point():
+    # without diffusion the bottom level obeys e <- 0.99 (e + 0.1) + 0.01 * 330,
+    # whose fixed point is 330 + 0.1 * 0.99 / 0.01 = 339.9 (and 209.9 on top)
+    nx, ny, nz = 2, 2, 3
+    e = np.zeros(rw.shape(nx, ny, nz))
+    surf, pbl = rw.boundary_fields(nx, ny)
+    for _ in range(6000):
+        e = rw.run_physics(e, surf, pbl)
+    np.testing.assert_allclose(e[0], 339.9, rtol=1e-9)
+    np.testing.assert_allclose(e[nz - 1], 209.9, rtol=1e-9)
+    np.testing.assert_allclose(e[1], 600.0, rtol=1e-9)   # 6000 steps of +0.1
+
+
+def test_box_init_covers_the_middle_half():
+    e = rw.box_init(8, 12, 4)
+    assert e.shape == (4, 14, 10)
+    assert set(np.unique(e)) == {0.0, 300.0}
+    # 1-based interior indices 3..6 of 8, 4..9 of 12, 2..3 of 4; ring and outside are 0
+    box = np.zeros_like(e, dtype=bool)
+    box[1:3, 4:10, 3:7] = True
+    np.testing.assert_array_equal(e == 300.0, box)
+
+
+def test_step_is_physics_then_diffusion_and_rejects_flat_columns():
+    nx, ny, nz = 6, 5, 4
+    e = rw.box_init(nx, ny, nz)
+    surf, pbl = rw.boundary_fields(nx, ny)
+    np.testing.assert_array_equal(rw.step(e, surf, pbl, NU), rw.diffuse(rw.run_physics(e, surf, pbl), NU))
+    with pytest.raises(ValueError):
+        rw.diffuse(np.zeros(rw.shape(nx, ny, 1)), NU)
