@@ -310,6 +310,39 @@ int wx_features(wx_state *s, int normalized, void *out, const void *blob);
  * feature rows and the plain-physics tendency rows (targets), nx*ny each. */
 int wx_dataset(wx_state *s, float *x_raw, float *y_raw);
 
+/* ---- The paper's reduced weather application ---------------------------
+ * Section "Reduced Weather Application" and its appendix sources (diffusion,
+ * physical processes, radiation, heat exchange, time integration).  One FP64
+ * field E over i = 0..nx+1, j = 0..ny+1 (a one-cell ring around the nx x ny
+ * interior) and nz levels, stored dense with i fastest, then j, then k:
+ * element (i, j, k) at k (nx+2)(ny+2) + j (nx+2) + i, k = 0 the bottom.
+ * surf and pbl are [ny+2][nx+2] FP64 (the surface and boundary-layer values
+ * of each column).  All pointers are device memory, 8-byte aligned; the
+ * caller owns them.
+ *
+ * A step is the printed one: on every column radiation adds 0.1 to each
+ * level, then the bottom level loses 0.01 (E - surf) and the top level
+ * 0.01 (E - pbl); then one explicit-Euler diffusion step with diffusion
+ * number nu writes the other array: interior columns take the 7-point rule
+ * E (1 - 6 nu) + nu (six neighbours) inside and the 6-point rule
+ * E (1 - 5 nu) + nu (five neighbours) on the bottom and top levels; ring
+ * rows and then ring columns (corners included) take
+ * E (1 - 2 nu) + nu (inner neighbour + opposite ring cell).  Sums run in the
+ * printed order and no multiply-add is fused: results equal the printed
+ * FP64 program bit for bit.
+ *
+ * Requires nx, ny >= 1, nz >= 2, (nx+2)(ny+2) nz <= 2^29 and a finite nu;
+ * otherwise WX_E_INVAL and nothing is launched. */
+
+/* One step from e_in into e_out (distinct arrays) on stream. */
+int wx_rw_step(const double *e_in, double *e_out, const double *surf, const double *pbl, int nx, int ny, int nz,
+               double nu, void *stream);
+/* nsteps steps alternating between e0 and e1 (the printed pointer swap),
+ * starting from e0; *which (host) receives 0 or 1, the array that holds the
+ * result (0 when nsteps = 0). */
+int wx_rw_run(double *e0, double *e1, const double *surf, const double *pbl, int nx, int ny, int nz, double nu,
+              int nsteps, int *which, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,221 @@
+// The paper's reduced weather application (section "Reduced Weather
+// Application" and the appendix sources of its diffusion, physical processes,
+// radiation, heat exchange and time integration), one fused kernel per time
+// step.
+//
+// Method (FP64 as printed): a step applies the column physics to every column
+// (radiation adds 0.1 to every level, then the bottom level loses 0.01 times
+// its excess over the surface value and the top level 0.01 times its excess
+// over the boundary-layer value) and then one explicit-Euler diffusion step
+// into the other array:
+//   interior column, inner level:  E (1 - 6 nu) + nu (i-1 + i+1 + j-1 + j+1 + k-1 + k+1)
+//   interior column, level 1 / nz: E (1 - 5 nu) + nu (i-1 + i+1 + j-1 + j+1 + the one vertical)
+//   ring row j = 0 / ny+1:         E (1 - 2 nu) + nu (inner row + opposite ring row)
+//   ring column i = 0 / nx+1:      E (1 - 2 nu) + nu (inner column + opposite ring column),
+//                                  corners included (the column rule is written last).
+// Every sum is taken in that order and no multiply-add is fused, so the result
+// is the printed program's to the last bit.
+//
+// GPU design: the physics is applied on the fly to every value the diffusion
+// reads (it is pointwise in each column apart from its own surface and
+// boundary-layer values), so a step reads the field once and writes it once:
+// 16 B per cell.  A 64 x 4 block of threads owns a tile of interior columns
+// (i fastest, coalesced 512-byte rows) and marches a chunk of levels,
+// carrying the vertical window k-1, k, k+1 in registers and loading the next
+// level's horizontal neighbours one level ahead; those come through L1/L2.
+// Tiles of one level chunk are numbered i-fastest and mapped XCD by XCD, so
+// the rows shared by j-neighbouring tiles meet in one L2.  The ring cells
+// (about 1% of a large grid) take extra blocks of the same launch, one cell
+// per thread, so no wavefront mixes the two rules.
+#include "wx_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace wx {
+namespace {
+
+constexpr int RW_BX = 64, RW_BY = 4;
+
+struct RwArgs {
+  const double *e;
+  double *out;
+  const double *surf, *pbl;      // [ny+2][nx+2]
+  int nx, ny, nz, kchunk, nchunk;
+  int tiles_x, tiles_y;          // interior tiles (i = 1..nx, j = 1..ny)
+  double nu, c6, c5, c2;
+};
+
+// The column physics of level k applied to the value v of column ij.
+__device__ __forceinline__ double phys(const RwArgs &a, double v, int k, unsigned ij) {
+  double r = v + 0.1;
+  if (k == 0) {
+    const double lost = 0.01 * (r - a.surf[ij]);
+    r = r - lost;
+  }
+  if (k == a.nz - 1) {
+    const double lost = 0.01 * (r - a.pbl[ij]);
+    r = r - lost;
+  }
+  return r;
+}
+
+// Ring columns: i = 0 or nx + 1 (every j, corners included), then j = 0 or
+// ny + 1 for i = 1..nx.  Column c of the 2 (ny + 2) + 2 nx ring columns.
+__device__ __forceinline__ void ring_column(int c, int nx, int ny, int &i, int &j) {
+  const int ncol_i = ny + 2;
+  if (c < 2 * ncol_i) {
+    i = c < ncol_i ? 0 : nx + 1;
+    j = c < ncol_i ? c : c - ncol_i;
+  } else {
+    c -= 2 * ncol_i;
+    j = c < nx ? 0 : ny + 1;
+    i = 1 + (c < nx ? c : c - nx);
+  }
+}
+
+__global__ __launch_bounds__(RW_BX *RW_BY) void k_rw_step(RwArgs a) {
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const unsigned sj = unsigned(nx + 2), sk = sj * unsigned(ny + 2);
+  const double nu = a.nu;
+  const int nint = a.tiles_x * a.tiles_y * a.nchunk;
+
+  if (int(blockIdx.x) >= nint) {
+    // ---- ring cells, one per thread: the one-dimensional ring rule (the
+    // inner neighbour, then the opposite ring cell)
+    const int nring = 2 * (ny + 2) + 2 * nx;
+    const int r = (int(blockIdx.x) - nint) * (RW_BX * RW_BY) + int(threadIdx.y * RW_BX + threadIdx.x);
+    if (r >= nring * nz) return;
+    const int k = r / nring;
+    int i, j;
+    ring_column(r % nring, nx, ny, i, j);
+    const unsigned ij = unsigned(i) + unsigned(j) * sj;
+    unsigned inner, opp;
+    if (i == 0 || i == nx + 1) {
+      inner = i == 0 ? ij + 1 : ij - 1;
+      opp = i == 0 ? ij + unsigned(nx + 1) : ij - unsigned(nx + 1);
+    } else {
+      inner = j == 0 ? ij + sj : ij - sj;
+      opp = j == 0 ? ij + unsigned(ny + 1) * sj : ij - unsigned(ny + 1) * sj;
+    }
+    const unsigned o = unsigned(k) * sk;
+    const double c = phys(a, a.e[o + ij], k, ij);
+    const double ni = phys(a, a.e[o + inner], k, inner);
+    const double no = phys(a, a.e[o + opp], k, opp);
+    a.out[o + ij] = c * a.c2 + nu * (ni + no);
+    return;
+  }
+
+  // ---- interior columns: a 64 x 4 tile marching a chunk of levels
+  const int ntile = a.tiles_x * a.tiles_y;
+  const int L = xcd_remap(blockIdx.x, nint);
+  const int chunk = L / ntile, t = L % ntile;
+  const int i = 1 + (t % a.tiles_x) * RW_BX + threadIdx.x;
+  const int j = 1 + (t / a.tiles_x) * RW_BY + threadIdx.y;
+  if (i > nx || j > ny) return;
+  const int k0 = chunk * a.kchunk, k1 = min(nz, k0 + a.kchunk);
+  const unsigned ij = unsigned(i) + unsigned(j) * sj;
+  const unsigned iw = ij - 1, ie = ij + 1, is = ij - sj, in = ij + sj;
+
+  // the surface and boundary-layer values of the column and its four
+  // neighbours, read before the march: they are used on the bottom and top
+  // level, which the column's window (levels k0 - 1 .. k1) may reach from
+  // outside the chunk
+  double sc = 0.0, sw = 0.0, se = 0.0, ss = 0.0, sn = 0.0;
+  double bc = 0.0, bw = 0.0, be = 0.0, bs = 0.0, bn = 0.0;
+  if (k0 <= 1) {
+    sc = a.surf[ij]; sw = a.surf[iw]; se = a.surf[ie]; ss = a.surf[is]; sn = a.surf[in];
+  }
+  if (k1 >= nz - 1) {
+    bc = a.pbl[ij]; bw = a.pbl[iw]; be = a.pbl[ie]; bs = a.pbl[is]; bn = a.pbl[in];
+  }
+  // the column physics of level k on a value whose column has surface value
+  // sv and boundary-layer value bv (the same operations as phys)
+  auto ph = [&](double v, int k, double sv, double bv) {
+    double r = v + 0.1;
+    if (k == 0) {
+      const double lost = 0.01 * (r - sv);
+      r = r - lost;
+    }
+    if (k == nz - 1) {
+      const double lost = 0.01 * (r - bv);
+      r = r - lost;
+    }
+    return r;
+  };
+
+  // vertical window of this column: levels k-1 and k after physics, level
+  // k+1 raw; the raw horizontal neighbours of level k.  Every value is loaded
+  // one level before the level that uses it, and every iteration issues the
+  // same five loads (clamped to a valid level past the chunk), so the wait
+  // for the previous level's loads never drains the ones just issued.
+  const double *__restrict__ E = a.e;
+  double *__restrict__ OUT = a.out;
+  double pm = 0.0, pc = ph(E[unsigned(k0) * sk + ij], k0, sc, bc), pnr = 0.0;
+  if (k0 > 0) pm = ph(E[unsigned(k0 - 1) * sk + ij], k0 - 1, sc, bc);
+  if (k0 + 1 < nz) pnr = E[unsigned(k0 + 1) * sk + ij];
+  unsigned o = unsigned(k0) * sk;
+  double w = E[o + iw], e = E[o + ie], s = E[o + is], n = E[o + in];
+  for (int k = k0; k < k1; ++k) {
+    const unsigned o1 = k + 1 < k1 ? o + sk : o;
+    const unsigned o2 = k + 2 < nz ? o + 2 * sk : o;
+    const double w1 = E[o1 + iw], e1 = E[o1 + ie], s1 = E[o1 + is], n1 = E[o1 + in];
+    const double c2 = E[o2 + ij];
+    const double pn = k + 1 < nz ? ph(pnr, k + 1, sc, bc) : 0.0;
+    double sum = ph(w, k, sw, bw) + ph(e, k, se, be);
+    sum = sum + ph(s, k, ss, bs);
+    sum = sum + ph(n, k, sn, bn);
+    double r;
+    if (k == 0) {
+      sum = sum + pn;
+      r = pc * a.c5 + nu * sum;
+    } else if (k == nz - 1) {
+      sum = sum + pm;
+      r = pc * a.c5 + nu * sum;
+    } else {
+      sum = sum + pm;
+      sum = sum + pn;
+      r = pc * a.c6 + nu * sum;
+    }
+    OUT[o + ij] = r;
+    pm = pc;
+    pc = pn;
+    pnr = c2;
+    w = w1;
+    e = e1;
+    s = s1;
+    n = n1;
+    o += sk;
+  }
+}
+
+}  // namespace
+
+int rw_chunk(int nz) { return nz < 16 ? nz : 16; }
+
+hipError_t launch_rw_step(const double *e, double *out, const double *surf, const double *pbl, int nx, int ny,
+                          int nz, double nu, hipStream_t s) {
+  RwArgs a;
+  a.e = e;
+  a.out = out;
+  a.surf = surf;
+  a.pbl = pbl;
+  a.nx = nx;
+  a.ny = ny;
+  a.nz = nz;
+  a.kchunk = rw_chunk(nz);
+  a.tiles_x = (nx + RW_BX - 1) / RW_BX;
+  a.tiles_y = (ny + RW_BY - 1) / RW_BY;
+  a.nu = nu;
+  // the weights as the printed program forms them: 1 - (n nu), two roundings
+  const double n6 = 6.0 * nu, n5 = 5.0 * nu, n2 = 2.0 * nu;
+  a.c6 = 1.0 - n6;
+  a.c5 = 1.0 - n5;
+  a.c2 = 1.0 - n2;
+  a.nchunk = (nz + a.kchunk - 1) / a.kchunk;
+  const int ring_cells = (2 * (ny + 2) + 2 * nx) * nz;
+  const int blocks = a.tiles_x * a.tiles_y * a.nchunk + (ring_cells + RW_BX * RW_BY - 1) / (RW_BX * RW_BY);
+  hipLaunchKernelGGL(k_rw_step, dim3(blocks), dim3(RW_BX, RW_BY), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace wx

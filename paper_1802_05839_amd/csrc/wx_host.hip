@@ -747,6 +747,43 @@ int wx_profile_step(wx_state *s, int nsteps, void *stream, double *ms_out, int n
   return WX_OK;
 }
 
+static int rw_check(const void *a, const void *b, const double *surf, const double *pbl, int nx, int ny, int nz,
+                    double nu) {
+  if (!a || !b || !surf || !pbl) return fail(WX_E_INVAL, "NULL pointer");
+  if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(surf) |
+       reinterpret_cast<uintptr_t>(pbl)) & 7)
+    return fail(WX_E_INVAL, "arrays must be 8-byte aligned");
+  if (a == b) return fail(WX_E_INVAL, "the two field arrays must be distinct");
+  if (nx < 1 || ny < 1 || nz < 2) return fail(WX_E_INVAL, "grid %d x %d x %d outside nx, ny >= 1, nz >= 2", nx, ny, nz);
+  if (double(nx + 2) * double(ny + 2) * double(nz) > double(1u << 29))
+    return fail(WX_E_INVAL, "grid %d x %d x %d exceeds 2^29 cells", nx, ny, nz);
+  if (!std::isfinite(nu)) return fail(WX_E_INVAL, "nu must be finite");
+  return WX_OK;
+}
+
+int wx_rw_step(const double *e_in, double *e_out, const double *surf, const double *pbl, int nx, int ny, int nz,
+               double nu, void *stream) {
+  if (int rc = rw_check(e_in, e_out, surf, pbl, nx, ny, nz, nu)) return rc;
+  WX_HIP(wx::launch_rw_step(e_in, e_out, surf, pbl, nx, ny, nz, nu, static_cast<hipStream_t>(stream)));
+  return WX_OK;
+}
+
+int wx_rw_run(double *e0, double *e1, const double *surf, const double *pbl, int nx, int ny, int nz, double nu,
+              int nsteps, int *which, void *stream) {
+  if (!which) return fail(WX_E_INVAL, "which is NULL");
+  if (nsteps < 0) return fail(WX_E_INVAL, "nsteps must be >= 0");
+  if (int rc = rw_check(e0, e1, surf, pbl, nx, ny, nz, nu)) return rc;
+  double *cur = e0, *nxt = e1;
+  for (int n = 0; n < nsteps; ++n) {
+    WX_HIP(wx::launch_rw_step(cur, nxt, surf, pbl, nx, ny, nz, nu, static_cast<hipStream_t>(stream)));
+    double *t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  *which = cur == e0 ? 0 : 1;
+  return WX_OK;
+}
+
 int wx_copy_probe(void *dst, const void *src, size_t bytes, void *stream) {
   if (!dst || !src) return fail(WX_E_INVAL, "NULL pointer");
   if (bytes % 16 || !aligned16(dst) || !aligned16(src)) return fail(WX_E_INVAL, "copy needs 16-byte multiples");

@@ -34,7 +34,7 @@ EXPORTS = ("wx_create", "wx_destroy", "wx_last_error", "wx_workspace_bytes", "wx
            "wx_mlp_init", "wx_mlp_refresh", "wx_mlp_norm_scratch_bytes", "wx_mlp_fit_norm",
            "wx_mlp_normalize", "wx_mlp_work_bytes", "wx_mlp_forward_backward", "wx_mlp_adam",
            "wx_mlp_train_step", "wx_mlp_infer_work_bytes", "wx_mlp_infer",
-           "wx_surrogate_work_bytes")
+           "wx_surrogate_work_bytes", "wx_rw_step", "wx_rw_run")
 
 # surrogate network shapes and blob sections (include/wx.h)
 MLP_NZ, MLP_NIN, MLP_KIN, MLP_NHID, MLP_NOUT, MLP_NOUTP = 58, 294, 320, 512, 116, 128
@@ -124,6 +124,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.wx_mlp_infer_work_bytes.argtypes = [ctypes.c_int]
     lib.wx_mlp_infer.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp]
     lib.wx_surrogate_work_bytes.argtypes = [sp]
+    dbl, i32 = ctypes.c_double, ctypes.c_int
+    lib.wx_rw_step.argtypes = [vp, vp, vp, vp, i32, i32, i32, dbl, vp]
+    lib.wx_rw_run.argtypes = [vp, vp, vp, vp, i32, i32, i32, dbl, i32, ctypes.POINTER(i32), vp]
     size_returning = {"wx_workspace_bytes", "wx_mlp_bytes", "wx_mlp_norm_scratch_bytes",
                       "wx_mlp_work_bytes", "wx_mlp_infer_work_bytes", "wx_surrogate_work_bytes"}
     for name in EXPORTS[4:]:
@@ -510,3 +513,50 @@ class Mlp:
         _check(self.lib.wx_mlp_infer(self.blob.data_ptr(), self._infer_work.data_ptr(), x.data_ptr(), n,
                                      y.data_ptr(), _stream_ptr(stream)), "wx_mlp_infer")
         return y
+
+
+class ReducedApp:
+    """The paper's reduced weather application on the GPU (FP64, device buffers owned here).
+
+    ``e`` is the field [nz][ny+2][nx+2] (i fastest, one-cell ring), ``surf``
+    and ``pbl`` the [ny+2][nx+2] surface and boundary-layer values; ``run``
+    advances it with the printed physics-then-diffusion step and pointer swap.
+    """
+
+    def __init__(self, e, surf, pbl, nu: float, device: str = "cuda:0"):
+        torch = _torch()
+        self.lib = load_library()
+        self.nz, nyp, nxp = e.shape
+        self.ny, self.nx = nyp - 2, nxp - 2
+        self.nu = float(nu)
+        dev = torch.device(device)
+        self.buf = [torch.as_tensor(np.ascontiguousarray(e, dtype=np.float64)).to(dev),
+                    torch.empty(tuple(e.shape), dtype=torch.float64, device=dev)]
+        self.surf = torch.as_tensor(np.ascontiguousarray(surf, dtype=np.float64)).to(dev)
+        self.pbl = torch.as_tensor(np.ascontiguousarray(pbl, dtype=np.float64)).to(dev)
+        self.cur = 0
+
+    def run(self, nsteps: int, stream=None) -> None:
+        which = ctypes.c_int(0)
+        _check(self.lib.wx_rw_run(self.buf[self.cur].data_ptr(), self.buf[1 - self.cur].data_ptr(),
+                                  self.surf.data_ptr(), self.pbl.data_ptr(), self.nx, self.ny, self.nz,
+                                  self.nu, int(nsteps), ctypes.byref(which), _stream_ptr(stream)),
+               "wx_rw_run")
+        self.cur = self.cur if which.value == 0 else 1 - self.cur
+
+    def step_into(self, stream=None) -> None:
+        """One step through wx_rw_step (the single-step entry point)."""
+        _check(self.lib.wx_rw_step(self.buf[self.cur].data_ptr(), self.buf[1 - self.cur].data_ptr(),
+                                   self.surf.data_ptr(), self.pbl.data_ptr(), self.nx, self.ny, self.nz,
+                                   self.nu, _stream_ptr(stream)), "wx_rw_step")
+        self.cur = 1 - self.cur
+
+    @property
+    def field(self):
+        return self.buf[self.cur]
+
+    def download(self) -> np.ndarray:
+        torch = _torch()
+        torch.cuda.synchronize(self.buf[0].device)
+        return self.field.cpu().numpy()
+

@@ -160,3 +160,24 @@ def test_judge_rate_range(lib):
     assert lib.wx_set_param(p, 10, 4294967295.0) == wx.WX_OK
     lib.wx_destroy(p)
 
+
+
+def test_reduced_app_validates_before_any_launch(lib):
+    inval = wx.WX_E_INVAL
+    a, b, s, p = 4096, 8192, 12288, 16384       # fake aligned addresses, never dereferenced
+    assert lib.wx_rw_step(a, a, s, p, 4, 4, 4, 0.1, None) == inval           # same array twice
+    assert lib.wx_rw_step(a, b, s, p, 4, 4, 1, 0.1, None) == inval           # nz < 2
+    assert lib.wx_rw_step(a, b, s, p, 0, 4, 4, 0.1, None) == inval           # nx < 1
+    assert lib.wx_rw_step(a, b, s, p, 4, 0, 4, 0.1, None) == inval           # ny < 1
+    assert lib.wx_rw_step(a + 4, b, s, p, 4, 4, 4, 0.1, None) == inval       # misaligned
+    assert lib.wx_rw_step(None, b, s, p, 4, 4, 4, 0.1, None) == inval
+    assert lib.wx_rw_step(a, b, s, None, 4, 4, 4, 0.1, None) == inval
+    assert lib.wx_rw_step(a, b, s, p, 4, 4, 4, float("nan"), None) == inval
+    assert lib.wx_rw_step(a, b, s, p, 30000, 30000, 2, 0.1, None) == inval   # more than 2^29 cells
+    which = ctypes.c_int(7)
+    assert lib.wx_rw_run(a, b, s, p, 4, 4, 4, 0.1, -1, ctypes.byref(which), None) == inval
+    assert lib.wx_rw_run(a, b, s, p, 4, 4, 4, 0.1, 1, None, None) == inval
+    assert lib.wx_rw_run(a, b, s, p, 4, 4, 1, 0.1, 1, ctypes.byref(which), None) == inval
+    # zero steps launch nothing and leave the result in the first array
+    assert lib.wx_rw_run(a, b, s, p, 4, 4, 4, 0.1, 0, ctypes.byref(which), None) == wx.WX_OK
+    assert which.value == 0
