@@ -14,7 +14,10 @@ against FP64 after 100 steps on the one-GPU share 400 x 320 x 58.  Unless
 the line also carries the learned-physics leg: the MLP surrogate trained on
 2,048,000 columns of 400 x 320 x 58 states, its held-out tendency RMSE, and
 surrogate and judged steps on the same grid timed against plain steps, with
-the MFMA roofline of the inference GEMMs.
+the MFMA roofline of the inference GEMMs.  Unless --no-reduced it also
+carries the paper's reduced weather application (FP64 diffusion + column
+physics) at the paper's three benchmark shapes, next to the paper's K20x
+times.
 
     python bench.py [--gpus 1] [--steps 200] [--warmup 5] [--config full]
 """
@@ -246,6 +249,70 @@ def surrogate_leg(args, host_inp, stream):
     return out
 
 
+# the paper's reduced-application timings on a Tesla K20x (FP64, 100 time
+# steps, 32 x 16 blocks, host-device copies included; table "Block Size
+# Impact on Execution Time" and the appendix on the measurement setup): context
+PAPER_RW_K20X_S = {(128, 128, 128): 0.10, (256, 256, 256): 0.55, (256, 256, 512): 2.16}
+
+
+def reduced_app_leg(stream, steps: int = 100):
+    """The paper's reduced weather application (FP64) at its three benchmark shapes."""
+    import torch
+
+    from oracle import reduced as rw     # initial state and boundary values only
+    from paper_1802_05839_amd import wx
+
+    res = {}
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    for (nx, ny, nz), k20x_s in PAPER_RW_K20X_S.items():
+        e = rw.box_init(nx, ny, nz)
+        surf, pbl = rw.boundary_fields(nx, ny)
+        app = wx.ReducedApp(e, surf, pbl, rw.NU_DEFAULT)
+        app.run(10, stream)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        app.run(steps, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        # the same run with the field copied in from pinned host memory and
+        # back out, as the paper's GPU times include the copies
+        host = torch.from_numpy(e).pin_memory()
+        back = torch.empty_like(host).pin_memory()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        app.buf[0].copy_(host, non_blocking=True)
+        app.cur = 0
+        app.run(steps, stream)
+        back.copy_(app.field, non_blocking=True)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_copies = ev0.elapsed_time(ev1)
+        cells = nx * ny * nz
+        stored = (nx + 2) * (ny + 2) * nz
+        gbs = 16 * stored * steps / (ms / 1e3) / 1e9
+        res[f"{nx}x{ny}x{nz}"] = {"ms_per_100_steps": round(ms * 100 / steps, 3),
+                                  "Mcell_steps_per_s": round(cells * steps / (ms / 1e3) / 1e6, 1),
+                                  "algorithmic_GBs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                                  "ms_per_100_steps_with_copies": round(ms_copies * 100 / steps, 3),
+                                  "paper_k20x_s_per_100_steps": k20x_s,
+                                  "speedup_vs_paper_k20x_with_copies": round(k20x_s * 1e3 / (ms_copies * 100 / steps), 1)}
+        del app
+        log(f"reduced app {nx}x{ny}x{nz}: {res[f'{nx}x{ny}x{nz}']}")
+    # the FP64 oracle for one step at 128^3 on the host, for scale
+    e = rw.box_init(128, 128, 128)
+    surf, pbl = rw.boundary_fields(128, 128)
+    t0 = time.perf_counter()
+    rw.step(e, surf, pbl)
+    res["oracle_ms_per_step_128"] = round((time.perf_counter() - t0) * 1e3, 1)
+    res["note"] = ("FP64, the printed physics-then-diffusion step fused into one kernel (16 algorithmic B per "
+                   "stored cell), bit-identical to the oracle; 'with_copies' adds the host-to-device copy of the "
+                   "initial field and the copy back from pinned memory, as the paper's K20x times do; those are "
+                   "another machine's numbers, context rather than a target")
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,6 +325,7 @@ def main() -> int:
     ap.add_argument("--no-share-error", action="store_true")
     ap.add_argument("--train-epochs", type=int, default=120)
     ap.add_argument("--coupled-steps", type=int, default=500)
+    ap.add_argument("--no-reduced", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -355,6 +423,8 @@ def main() -> int:
     }
     if not args.no_surrogate and nz == 58:
         out["surrogate"] = surrogate_leg(args, inp, stream)
+    if not args.no_reduced:
+        out["reduced_app"] = reduced_app_leg(stream)
     if not args.no_share_error:
         log("FP32 against FP64 on the one-GPU share")
         out["fp32_error_share"] = share_error()
