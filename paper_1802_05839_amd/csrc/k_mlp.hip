@@ -59,7 +59,7 @@ __device__ __forceinline__ void load_tile(uint16_t *lds, const uint16_t *g, int 
 }
 
 // Epilogue kinds
-enum { EP_F32 = 0, EP_BIAS_F32 = 1, EP_BIAS_RELU_BF16 = 2, EP_PARTIAL_F32 = 4 };
+enum { EP_F32 = 0, EP_BIAS_F32 = 1, EP_BIAS_RELU_BF16 = 2, EP_PARTIAL_F32 = 4, EP_MASK_F32_BF16 = 5 };
 
 struct GemmArgs {
   const uint16_t *A, *B;
@@ -71,6 +71,8 @@ struct GemmArgs {
   void *C;                     // output
   int ldc;
   size_t split_stride;         // EP_PARTIAL_F32: elements between split slices
+  const uint16_t *mask;        // EP_MASK_F32_BF16: BF16 activation, C's layout
+  uint16_t *C2;                // EP_MASK_F32_BF16: BF16 copy of the output
 };
 
 template <bool AK, bool BK_, int EP>
@@ -124,19 +126,16 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
     } else if (EP == EP_BIAS_RELU_BF16) {
       v += a.bias[n];
       static_cast<uint16_t *>(a.C)[(size_t)m * a.ldc + n] = f2bf(v > 0.f ? v : 0.f);
+    } else if (EP == EP_MASK_F32_BF16) {
+      // hidden-layer gradient: (upstream @ W) * (h > 0), FP32 and its BF16 operand
+      const size_t o = (size_t)m * a.ldc + n;
+      const float g = bf2f(a.mask[o]) > 0.f ? v : 0.f;
+      static_cast<float *>(a.C)[o] = g;
+      a.C2[o] = f2bf(g);
     } else {
       static_cast<float *>(a.C)[blockIdx.z * a.split_stride + (size_t)m * a.ldc + n] = v;
     }
   }
-}
-
-// Sum nsplit partial slices in order: out[i] = sum_s part[s][i].
-__global__ void k_sum_splits(const float *part, int nsplit, size_t stride, float *out, size_t n) {
-  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float s = 0.f;
-  for (int p = 0; p < nsplit; ++p) s += part[p * stride + i];
-  out[i] = s;
 }
 
 // Loss and output gradient: d = 2 (y - t) / (B * nout) on the first nout
@@ -163,23 +162,13 @@ __global__ void k_loss(const float *y, const float *t, const int *rows, int batc
   if (n == 0) row_loss[m] = sh[0];
 }
 
-// Hidden-layer gradient: g = (upstream @ W) * (h > 0) in place (FP32) and its
-// BF16 GEMM operand.
-__global__ void k_mask_round(float *a, const uint16_t *mask, size_t n, uint16_t *out) {
-  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float g = bf2f(mask[i]) > 0.f ? a[i] : 0.f;
-  a[i] = g;
-  out[i] = f2bf(g);
-}
-
-// Column sums of up to four [rows][lda] FP32 matrices in one launch.  Block b
+// Column sums of up to four [rows][lda] FP32 matrices (one block's share).  Block b
 // covers 16 columns of one matrix; thread (quad q, group g) sums columns
 // 16b + 4q .. 16b + 4q + 3 over rows g, g + 64, ... in order (float4 loads
 // when the matrix allows), then the 64 group sums are folded in a fixed tree.
-__global__ void __launch_bounds__(256) k_colsum_multi(ColsumArgs a) {
+__device__ __forceinline__ void colsum_block(const ColsumArgs &a, int b) {
   __shared__ float sh[64][17];
-  int b = blockIdx.x, jb = 0;
+  int jb = 0;
   while (jb + 1 < a.njobs && b >= a.job[jb].blocks) {
     b -= a.job[jb].blocks;
     ++jb;
@@ -219,6 +208,25 @@ __global__ void __launch_bounds__(256) k_colsum_multi(ColsumArgs a) {
     __syncthreads();
   }
   if (threadIdx.x < 16 && b * 16 + col < J.cols) J.out[b * 16 + col] = sh[0][col];
+}
+
+// Weight gradients as ordered sums of split-K slices (first blocks), then the
+// bias-gradient and loss column sums (remaining blocks).
+__global__ void __launch_bounds__(256) k_grad_finish(GradFinishArgs a) {
+  int b = blockIdx.x;
+  for (int j = 0; j < a.nsj; ++j) {
+    const SplitJob &J = a.sj[j];
+    if (b < J.blocks) {
+      const int i = b * 256 + threadIdx.x;
+      if (i >= J.n) return;
+      float s = 0.f;
+      for (int p = 0; p < J.nsplit; ++p) s += J.part[p * J.stride + i];
+      J.out[i] = s;
+      return;
+    }
+    b -= J.blocks;
+  }
+  colsum_block(a.cs, b);
 }
 
 // Adam over the six parameter tensors in one launch (element i of the
@@ -281,6 +289,7 @@ hipError_t launch_gemm(const GemmSpec &g, hipStream_t s) {
   a.k_split = (a.k_split + GBK - 1) / GBK * GBK;
   a.rows_a = g.rows_a; a.bias = g.bias;
   a.C = g.C; a.ldc = g.ldc; a.split_stride = g.split_stride;
+  a.mask = g.mask; a.C2 = g.C2;
   const int splits = g.splits > 1 ? (g.K + a.k_split - 1) / a.k_split : 1;
   dim3 grid((g.N + GBN - 1) / GBN, (g.M + GBM - 1) / GBM, splits);
 #define WX_G(AK, BK, EP) hipLaunchKernelGGL((k_gemm<AK, BK, EP>), grid, dim3(256), 0, s, a)
@@ -298,6 +307,10 @@ hipError_t launch_gemm(const GemmSpec &g, hipStream_t s) {
       if (key != 3) return hipErrorInvalidValue;
       WX_G(true, true, EP_F32);
       break;
+    case GEMM_MASK_F32_BF16:
+      if (key != 3 || !g.mask || !g.C2) return hipErrorInvalidValue;
+      WX_G(true, true, EP_MASK_F32_BF16);
+      break;
     case GEMM_PARTIAL_F32:
       if (key != 0) return hipErrorInvalidValue;
       WX_G(false, false, EP_PARTIAL_F32);
@@ -309,33 +322,24 @@ hipError_t launch_gemm(const GemmSpec &g, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_sum_splits(const float *part, int nsplit, size_t stride, float *out, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_splits, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, part, nsplit, stride, out, n);
-  return hipGetLastError();
-}
-
 hipError_t launch_loss(const float *y, const float *t, const int *rows, int batch, int nout, int ldy,
                        float *d32, uint16_t *d16, float *row_loss, hipStream_t s) {
   hipLaunchKernelGGL(k_loss, dim3(batch), dim3(128), 0, s, y, t, rows, batch, nout, ldy, d32, d16, row_loss);
   return hipGetLastError();
 }
 
-hipError_t launch_colsum_multi(const ColsumArgs &a, hipStream_t s) {
+hipError_t launch_grad_finish(const GradFinishArgs &a, hipStream_t s) {
   int blocks = 0;
-  for (int j = 0; j < a.njobs; ++j) blocks += a.job[j].blocks;
+  for (int j = 0; j < a.nsj; ++j) blocks += a.sj[j].blocks;
+  for (int j = 0; j < a.cs.njobs; ++j) blocks += a.cs.job[j].blocks;
   if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_colsum_multi, dim3(blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_grad_finish, dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_adam_multi(const AdamArgs &a, hipStream_t s) {
   const size_t n = a.seg[5].start + a.seg[5].n;
   hipLaunchKernelGGL(k_adam_multi, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_mask_round(float *a, const uint16_t *mask, size_t n, uint16_t *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_mask_round, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, a, mask, n, out);
   return hipGetLastError();
 }
 

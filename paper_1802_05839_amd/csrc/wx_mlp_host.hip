@@ -85,7 +85,8 @@ bool al16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 // Training workspace for a batch of B rows.
 struct Work {
   uint16_t *xb, *h1, *h2, *d3b, *g2b, *g1b;
-  float *y, *d3f, *g2f, *g1f, *row_loss, *part;
+  float *y, *d3f, *g2f, *g1f, *row_loss;
+  float *part3, *part2, *part1;            // split-K slices of dW3, dW2, dW1
   size_t total;
   static constexpr int kSplitRows = 256;   // batch rows per dW split
 };
@@ -111,7 +112,9 @@ Work work_layout(void *base, int B) {
   w.g1f = reinterpret_cast<float *>(take(size_t(B) * MLP_NHID * 4));
   w.row_loss = reinterpret_cast<float *>(take(size_t(B) * 4));
   const size_t splits = (size_t(B) + Work::kSplitRows - 1) / Work::kSplitRows;
-  w.part = reinterpret_cast<float *>(take(splits * MLP_NHID * MLP_NHID * 4));
+  w.part3 = reinterpret_cast<float *>(take(splits * MLP_NOUTP * MLP_NHID * 4));
+  w.part2 = reinterpret_cast<float *>(take(splits * MLP_NHID * MLP_NHID * 4));
+  w.part1 = reinterpret_cast<float *>(take(splits * MLP_NHID * MLP_KIN * 4));
   w.total = off;
   return w;
 }
@@ -139,10 +142,10 @@ int forward_layers(const void *blob, const uint16_t *x, int n, uint16_t *h1, uin
   return WX_OK;
 }
 
-// dW[n][k] = sum_m d[m][n] act[m][k] over the batch: split-K partials, then an
-// ordered sum.
+// dW[n][k] = sum_m d[m][n] act[m][k] over the batch as split-K partial slices;
+// *job describes their ordered sum into out (run by launch_grad_finish).
 int weight_grad(const uint16_t *d, int ldd, int nout, const uint16_t *act, int lda, int kin, int B, float *part,
-                float *out, hipStream_t st) {
+                float *out, SplitJob *job, hipStream_t st) {
   GemmSpec g{};
   g.a_kcontig = g.b_kcontig = false;
   g.A = d; g.lda = ldd; g.B = act; g.ldb = lda;
@@ -153,18 +156,21 @@ int weight_grad(const uint16_t *d, int ldd, int nout, const uint16_t *act, int l
   MLP_HIP(launch_gemm(g, st));
   const int k_split = ((B + g.splits - 1) / g.splits + 31) / 32 * 32;
   const int nsplit = (B + k_split - 1) / k_split;
-  MLP_HIP(launch_sum_splits(part, nsplit, g.split_stride, out, g.split_stride, st));
+  const int n = nout * kin;
+  *job = {part, nsplit, g.split_stride, out, n, (n + 255) / 256};
   return WX_OK;
 }
 
-// dX[m][k] = sum_n d[m][n] W[n][k], with W given transposed as [k][n].
-int input_grad(const uint16_t *d, int ldd, int nred, const uint16_t *wt, int kout, int B, float *out,
-               hipStream_t st) {
+// Hidden-layer gradient: g = (sum_n d[m][n] W[n][k]) * (h[m][k] > 0), with W
+// given transposed as [k][n]; FP32 into out and its BF16 operand into out16.
+int input_grad(const uint16_t *d, int ldd, int nred, const uint16_t *wt, int kout, int B, const uint16_t *h,
+               float *out, uint16_t *out16, hipStream_t st) {
   GemmSpec g{};
   g.a_kcontig = g.b_kcontig = true;
   g.A = d; g.lda = ldd; g.B = wt; g.ldb = nred;
   g.M = B; g.N = kout; g.K = nred; g.splits = 1;
-  g.C = out; g.ldc = kout; g.epilogue = GEMM_F32;
+  g.C = out; g.ldc = kout; g.epilogue = GEMM_MASK_F32_BF16;
+  g.mask = h; g.C2 = out16;
   MLP_HIP(launch_gemm(g, st));
   return WX_OK;
 }
@@ -255,34 +261,37 @@ int wx_mlp_forward_backward(void *blob, void *work, const void *x, const float *
   MLP_HIP(launch_gather_rows(static_cast<const uint16_t *>(x), rows, B, w.xb, st));
   if (int rc = forward_layers(blob, w.xb, B, w.h1, w.h2, w.y, st)) return rc;
   MLP_HIP(launch_loss(w.y, y, rows, B, MLP_NOUT, MLP_NOUTP, w.d3f, w.d3b, w.row_loss, st));
+  GradFinishArgs gf{};
+  gf.nsj = 3;
   // output layer
-  if (int rc = weight_grad(w.d3b, MLP_NOUTP, MLP_NOUTP, w.h2, MLP_NHID, MLP_NHID, B, w.part,
-                           sec<float>(blob, WX_MLP_GRAD + 4), st))
+  if (int rc = weight_grad(w.d3b, MLP_NOUTP, MLP_NOUTP, w.h2, MLP_NHID, MLP_NHID, B, w.part3,
+                           sec<float>(blob, WX_MLP_GRAD + 4), &gf.sj[0], st))
     return rc;
-  // hidden layer 2
-  if (int rc = input_grad(w.d3b, MLP_NOUTP, MLP_NOUTP, sec<uint16_t>(blob, WX_MLP_W3T_BF16), MLP_NHID, B, w.g2f, st))
+  // hidden layer 2 (the ReLU mask and BF16 rounding in the GEMM's epilogue)
+  if (int rc = input_grad(w.d3b, MLP_NOUTP, MLP_NOUTP, sec<uint16_t>(blob, WX_MLP_W3T_BF16), MLP_NHID, B, w.h2,
+                          w.g2f, w.g2b, st))
     return rc;
-  MLP_HIP(launch_mask_round(w.g2f, w.h2, size_t(B) * MLP_NHID, w.g2b, st));
-  if (int rc = weight_grad(w.g2b, MLP_NHID, MLP_NHID, w.h1, MLP_NHID, MLP_NHID, B, w.part,
-                           sec<float>(blob, WX_MLP_GRAD + 2), st))
+  if (int rc = weight_grad(w.g2b, MLP_NHID, MLP_NHID, w.h1, MLP_NHID, MLP_NHID, B, w.part2,
+                           sec<float>(blob, WX_MLP_GRAD + 2), &gf.sj[1], st))
     return rc;
   // hidden layer 1
-  if (int rc = input_grad(w.g2b, MLP_NHID, MLP_NHID, sec<uint16_t>(blob, WX_MLP_W2T_BF16), MLP_NHID, B, w.g1f, st))
+  if (int rc = input_grad(w.g2b, MLP_NHID, MLP_NHID, sec<uint16_t>(blob, WX_MLP_W2T_BF16), MLP_NHID, B, w.h1,
+                          w.g1f, w.g1b, st))
     return rc;
-  MLP_HIP(launch_mask_round(w.g1f, w.h1, size_t(B) * MLP_NHID, w.g1b, st));
-  if (int rc = weight_grad(w.g1b, MLP_NHID, MLP_NHID, w.xb, MLP_KIN, MLP_KIN, B, w.part,
-                           sec<float>(blob, WX_MLP_GRAD + 0), st))
+  if (int rc = weight_grad(w.g1b, MLP_NHID, MLP_NHID, w.xb, MLP_KIN, MLP_KIN, B, w.part1,
+                           sec<float>(blob, WX_MLP_GRAD + 0), &gf.sj[2], st))
     return rc;
-  // bias gradients (column sums of the unrounded FP32 deltas) and the loss
-  // (sum of the per-row sums), one launch, fixed order
-  ColsumArgs cs{};
+  // one launch for the rest, fixed order: the weight gradients (ordered sums
+  // of their split-K slices), the bias gradients (column sums of the
+  // unrounded FP32 deltas) and the loss (sum of the per-row sums)
+  ColsumArgs &cs = gf.cs;
   cs.rows = B;
   cs.njobs = 4;
   cs.job[0] = {w.d3f, MLP_NOUTP, MLP_NOUTP, sec<float>(blob, WX_MLP_GRAD + 5), MLP_NOUTP / 16, 1};
   cs.job[1] = {w.g2f, MLP_NHID, MLP_NHID, sec<float>(blob, WX_MLP_GRAD + 3), MLP_NHID / 16, 1};
   cs.job[2] = {w.g1f, MLP_NHID, MLP_NHID, sec<float>(blob, WX_MLP_GRAD + 1), MLP_NHID / 16, 1};
   cs.job[3] = {w.row_loss, 1, 1, loss_sum, 1, 0};
-  MLP_HIP(launch_colsum_multi(cs, st));
+  MLP_HIP(launch_grad_finish(gf, st));
   return WX_OK;
 }
 

@@ -82,7 +82,8 @@ __device__ __forceinline__ void level_features(int k, const LevelVals &c, const 
   }
 }
 
-enum GemmEpilogue { GEMM_F32 = 0, GEMM_BIAS_F32 = 1, GEMM_BIAS_RELU_BF16 = 2, GEMM_PARTIAL_F32 = 3 };
+enum GemmEpilogue { GEMM_F32 = 0, GEMM_BIAS_F32 = 1, GEMM_BIAS_RELU_BF16 = 2, GEMM_PARTIAL_F32 = 3,
+                   GEMM_MASK_F32_BF16 = 4 };
 
 // C[m][n] = sum_k A(m,k) B(k,n).  a_kcontig: A is [M][lda] (k contiguous),
 // else [K][lda] (m contiguous); likewise B as [N][ldb] or [K][ldb].
@@ -98,15 +99,17 @@ struct GemmSpec {
   int ldc;
   size_t split_stride;
   int epilogue;
+  // GEMM_MASK_F32_BF16: C (FP32) and C2 (BF16) = acc where mask (BF16, same
+  // layout as C) is > 0, else 0
+  const uint16_t *mask;
+  uint16_t *C2;
 };
 
 hipError_t launch_gemm(const GemmSpec &g, hipStream_t s);
-hipError_t launch_sum_splits(const float *part, int nsplit, size_t stride, float *out, size_t n, hipStream_t s);
 hipError_t launch_loss(const float *y, const float *t, const int *rows, int batch, int nout, int ldy, float *d32,
                        uint16_t *d16, float *row_loss, hipStream_t s);
-hipError_t launch_mask_round(float *a, const uint16_t *mask, size_t n, uint16_t *out, hipStream_t s);
 
-// Column sums of up to four matrices in one launch (fixed order).
+// Column sums of up to four matrices (fixed order), run inside launch_grad_finish.
 struct ColsumJob {
   const float *a;   // [rows][lda]
   int cols, lda;
@@ -118,7 +121,22 @@ struct ColsumArgs {
   ColsumJob job[4];
   int njobs, rows;
 };
-hipError_t launch_colsum_multi(const ColsumArgs &a, hipStream_t s);
+
+// The end of the backward pass in one launch: the weight gradients as ordered
+// sums of their split-K partial slices, then the column sums of ColsumArgs.
+struct SplitJob {
+  const float *part;   // [nsplit][stride]
+  int nsplit;
+  size_t stride;
+  float *out;          // [n], n <= stride
+  int n, blocks;       // blocks = (n + 255) / 256
+};
+struct GradFinishArgs {
+  SplitJob sj[3];
+  int nsj;
+  ColsumArgs cs;
+};
+hipError_t launch_grad_finish(const GradFinishArgs &a, hipStream_t s);
 
 // Adam over the six parameter tensors in one launch.
 struct AdamSeg {
