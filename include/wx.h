@@ -342,6 +342,14 @@ int wx_rw_step(const double *e_in, double *e_out, const double *surf, const doub
  * result (0 when nsteps = 0). */
 int wx_rw_run(double *e0, double *e1, const double *surf, const double *pbl, int nx, int ny, int nz, double nu,
               int nsteps, int *which, void *stream);
+/* The same steps on the KIJ storage order (section "Performance Portable
+ * Storage Order": k fastest, then i, then j; element (i, j, k) at
+ * (j (nx+2) + i) nz + k), with one thread per column marching k, the direct
+ * GPU mapping of that order.  Results equal wx_rw_run's bit for bit (after
+ * the reordering); it exists to measure what the order costs on this GPU.
+ * Same arguments, requirements and errors as wx_rw_run. */
+int wx_rw_run_kij(double *e0, double *e1, const double *surf, const double *pbl, int nx, int ny, int nz, double nu,
+                  int nsteps, int *which, void *stream);
 
 #ifdef __cplusplus
 }

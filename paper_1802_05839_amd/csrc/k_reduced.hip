@@ -188,12 +188,68 @@ __global__ __launch_bounds__(RW_BX *RW_BY) void k_rw_step(RwArgs a) {
   }
 }
 
+// The same step on the KIJ storage order (k fastest, then i, then j: element
+// (i, j, k) at (j (nx+2) + i) nz + k), the order the paper's storage-order
+// table compares on CPU and GPU, with the direct GPU mapping of that order:
+// one thread per column (ring included), k marched inside the thread.  The
+// lanes of a wavefront touch addresses nz values apart, so no load
+// coalesces; this kernel exists to measure that cost.
+__global__ __launch_bounds__(RW_BX *RW_BY) void k_rw_step_kij(RwArgs a) {
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int i = blockIdx.x * RW_BX + threadIdx.x, j = blockIdx.y * RW_BY + threadIdx.y;
+  if (i > nx + 1 || j > ny + 1) return;
+  const unsigned sj2 = unsigned(nx + 2);                 // 2D stride of j
+  const unsigned si = unsigned(nz), sj = sj2 * unsigned(nz);
+  const unsigned ij = unsigned(i) + unsigned(j) * sj2;
+  const unsigned col = ij * si;
+  const double nu = a.nu;
+  if (i == 0 || i == nx + 1 || j == 0 || j == ny + 1) {
+    unsigned inner, opp, iji, ijo;                       // column offsets and 2D indices
+    if (i == 0 || i == nx + 1) {
+      iji = i == 0 ? ij + 1 : ij - 1;
+      ijo = i == 0 ? ij + unsigned(nx + 1) : ij - unsigned(nx + 1);
+    } else {
+      iji = j == 0 ? ij + sj2 : ij - sj2;
+      ijo = j == 0 ? ij + unsigned(ny + 1) * sj2 : ij - unsigned(ny + 1) * sj2;
+    }
+    inner = iji * si;
+    opp = ijo * si;
+    for (int k = 0; k < nz; ++k) {
+      const double c = phys(a, a.e[col + k], k, ij);
+      const double ni = phys(a, a.e[inner + k], k, iji);
+      const double no = phys(a, a.e[opp + k], k, ijo);
+      a.out[col + k] = c * a.c2 + nu * (ni + no);
+    }
+    return;
+  }
+  for (int k = 0; k < nz; ++k) {
+    const unsigned o = col + unsigned(k);
+    const double c = phys(a, a.e[o], k, ij);
+    double sum = phys(a, a.e[o - si], k, ij - 1) + phys(a, a.e[o + si], k, ij + 1);
+    sum = sum + phys(a, a.e[o - sj], k, ij - sj2);
+    sum = sum + phys(a, a.e[o + sj], k, ij + sj2);
+    double r;
+    if (k == 0) {
+      sum = sum + phys(a, a.e[o + 1], 1, ij);
+      r = c * a.c5 + nu * sum;
+    } else if (k == nz - 1) {
+      sum = sum + phys(a, a.e[o - 1], k - 1, ij);
+      r = c * a.c5 + nu * sum;
+    } else {
+      sum = sum + phys(a, a.e[o - 1], k - 1, ij);
+      sum = sum + phys(a, a.e[o + 1], k + 1, ij);
+      r = c * a.c6 + nu * sum;
+    }
+    a.out[o] = r;
+  }
+}
+
 }  // namespace
 
 int rw_chunk(int nz) { return nz < 16 ? nz : 16; }
 
 hipError_t launch_rw_step(const double *e, double *out, const double *surf, const double *pbl, int nx, int ny,
-                          int nz, double nu, hipStream_t s) {
+                          int nz, double nu, bool kij, hipStream_t s) {
   RwArgs a;
   a.e = e;
   a.out = out;
@@ -213,6 +269,11 @@ hipError_t launch_rw_step(const double *e, double *out, const double *surf, cons
   a.c2 = 1.0 - n2;
   a.nchunk = (nz + a.kchunk - 1) / a.kchunk;
   const int ring_cells = (2 * (ny + 2) + 2 * nx) * nz;
+  if (kij) {
+    const dim3 grid((nx + 2 + RW_BX - 1) / RW_BX, (ny + 2 + RW_BY - 1) / RW_BY);
+    hipLaunchKernelGGL(k_rw_step_kij, grid, dim3(RW_BX, RW_BY), 0, s, a);
+    return hipGetLastError();
+  }
   const int blocks = a.tiles_x * a.tiles_y * a.nchunk + (ring_cells + RW_BX * RW_BY - 1) / (RW_BX * RW_BY);
   hipLaunchKernelGGL(k_rw_step, dim3(blocks), dim3(RW_BX, RW_BY), 0, s, a);
   return hipGetLastError();

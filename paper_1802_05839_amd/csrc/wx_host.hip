@@ -764,24 +764,34 @@ static int rw_check(const void *a, const void *b, const double *surf, const doub
 int wx_rw_step(const double *e_in, double *e_out, const double *surf, const double *pbl, int nx, int ny, int nz,
                double nu, void *stream) {
   if (int rc = rw_check(e_in, e_out, surf, pbl, nx, ny, nz, nu)) return rc;
-  WX_HIP(wx::launch_rw_step(e_in, e_out, surf, pbl, nx, ny, nz, nu, static_cast<hipStream_t>(stream)));
+  WX_HIP(wx::launch_rw_step(e_in, e_out, surf, pbl, nx, ny, nz, nu, false, static_cast<hipStream_t>(stream)));
   return WX_OK;
 }
 
-int wx_rw_run(double *e0, double *e1, const double *surf, const double *pbl, int nx, int ny, int nz, double nu,
-              int nsteps, int *which, void *stream) {
+static int rw_run(double *e0, double *e1, const double *surf, const double *pbl, int nx, int ny, int nz, double nu,
+                  int nsteps, int *which, bool kij, void *stream) {
   if (!which) return fail(WX_E_INVAL, "which is NULL");
   if (nsteps < 0) return fail(WX_E_INVAL, "nsteps must be >= 0");
   if (int rc = rw_check(e0, e1, surf, pbl, nx, ny, nz, nu)) return rc;
   double *cur = e0, *nxt = e1;
   for (int n = 0; n < nsteps; ++n) {
-    WX_HIP(wx::launch_rw_step(cur, nxt, surf, pbl, nx, ny, nz, nu, static_cast<hipStream_t>(stream)));
+    WX_HIP(wx::launch_rw_step(cur, nxt, surf, pbl, nx, ny, nz, nu, kij, static_cast<hipStream_t>(stream)));
     double *t = cur;
     cur = nxt;
     nxt = t;
   }
   *which = cur == e0 ? 0 : 1;
   return WX_OK;
+}
+
+int wx_rw_run(double *e0, double *e1, const double *surf, const double *pbl, int nx, int ny, int nz, double nu,
+              int nsteps, int *which, void *stream) {
+  return rw_run(e0, e1, surf, pbl, nx, ny, nz, nu, nsteps, which, false, stream);
+}
+
+int wx_rw_run_kij(double *e0, double *e1, const double *surf, const double *pbl, int nx, int ny, int nz, double nu,
+                  int nsteps, int *which, void *stream) {
+  return rw_run(e0, e1, surf, pbl, nx, ny, nz, nu, nsteps, which, true, stream);
 }
 
 int wx_copy_probe(void *dst, const void *src, size_t bytes, void *stream) {

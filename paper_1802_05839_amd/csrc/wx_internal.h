@@ -106,7 +106,7 @@ hipError_t launch_fill_i32(int *p, int n, int value, hipStream_t s);
 constexpr int TEND_ROW = 128;      // row width of the row-major tendency layout
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 hipError_t launch_rw_step(const double *e, double *out, const double *surf, const double *pbl, int nx, int ny,
-                          int nz, double nu, hipStream_t s);
+                          int nz, double nu, bool kij, hipStream_t s);
 
 // RK3 stage tile: 64 columns in i (one wave per row) by 8 rows in j.
 constexpr int STAGE_BX = 64, STAGE_BY = 8;

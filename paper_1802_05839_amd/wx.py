@@ -34,7 +34,7 @@ EXPORTS = ("wx_create", "wx_destroy", "wx_last_error", "wx_workspace_bytes", "wx
            "wx_mlp_init", "wx_mlp_refresh", "wx_mlp_norm_scratch_bytes", "wx_mlp_fit_norm",
            "wx_mlp_normalize", "wx_mlp_work_bytes", "wx_mlp_forward_backward", "wx_mlp_adam",
            "wx_mlp_train_step", "wx_mlp_infer_work_bytes", "wx_mlp_infer",
-           "wx_surrogate_work_bytes", "wx_rw_step", "wx_rw_run")
+           "wx_surrogate_work_bytes", "wx_rw_step", "wx_rw_run", "wx_rw_run_kij")
 
 # surrogate network shapes and blob sections (include/wx.h)
 MLP_NZ, MLP_NIN, MLP_KIN, MLP_NHID, MLP_NOUT, MLP_NOUTP = 58, 294, 320, 512, 116, 128
@@ -127,6 +127,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     dbl, i32 = ctypes.c_double, ctypes.c_int
     lib.wx_rw_step.argtypes = [vp, vp, vp, vp, i32, i32, i32, dbl, vp]
     lib.wx_rw_run.argtypes = [vp, vp, vp, vp, i32, i32, i32, dbl, i32, ctypes.POINTER(i32), vp]
+    lib.wx_rw_run_kij.argtypes = [vp, vp, vp, vp, i32, i32, i32, dbl, i32, ctypes.POINTER(i32), vp]
     size_returning = {"wx_workspace_bytes", "wx_mlp_bytes", "wx_mlp_norm_scratch_bytes",
                       "wx_mlp_work_bytes", "wx_mlp_infer_work_bytes", "wx_surrogate_work_bytes"}
     for name in EXPORTS[4:]:
@@ -521,31 +522,38 @@ class ReducedApp:
     ``e`` is the field [nz][ny+2][nx+2] (i fastest, one-cell ring), ``surf``
     and ``pbl`` the [ny+2][nx+2] surface and boundary-layer values; ``run``
     advances it with the printed physics-then-diffusion step and pointer swap.
+    ``order="kij"`` keeps the field on the device in KIJ order ([ny+2][nx+2][nz])
+    and runs wx_rw_run_kij; upload and download reorder it.
     """
 
-    def __init__(self, e, surf, pbl, nu: float, device: str = "cuda:0"):
+    def __init__(self, e, surf, pbl, nu: float, device: str = "cuda:0", order: str = "ijk"):
         torch = _torch()
+        if order not in ("ijk", "kij"):
+            raise WxError(f"unknown storage order {order!r}")
         self.lib = load_library()
+        self.order = order
         self.nz, nyp, nxp = e.shape
         self.ny, self.nx = nyp - 2, nxp - 2
         self.nu = float(nu)
         dev = torch.device(device)
-        self.buf = [torch.as_tensor(np.ascontiguousarray(e, dtype=np.float64)).to(dev),
-                    torch.empty(tuple(e.shape), dtype=torch.float64, device=dev)]
+        host = np.ascontiguousarray(e if order == "ijk" else np.transpose(e, (1, 2, 0)), dtype=np.float64)
+        self.buf = [torch.as_tensor(host).to(dev), torch.empty(host.shape, dtype=torch.float64, device=dev)]
         self.surf = torch.as_tensor(np.ascontiguousarray(surf, dtype=np.float64)).to(dev)
         self.pbl = torch.as_tensor(np.ascontiguousarray(pbl, dtype=np.float64)).to(dev)
         self.cur = 0
 
     def run(self, nsteps: int, stream=None) -> None:
         which = ctypes.c_int(0)
-        _check(self.lib.wx_rw_run(self.buf[self.cur].data_ptr(), self.buf[1 - self.cur].data_ptr(),
-                                  self.surf.data_ptr(), self.pbl.data_ptr(), self.nx, self.ny, self.nz,
-                                  self.nu, int(nsteps), ctypes.byref(which), _stream_ptr(stream)),
-               "wx_rw_run")
+        fn = self.lib.wx_rw_run if self.order == "ijk" else self.lib.wx_rw_run_kij
+        _check(fn(self.buf[self.cur].data_ptr(), self.buf[1 - self.cur].data_ptr(),
+                  self.surf.data_ptr(), self.pbl.data_ptr(), self.nx, self.ny, self.nz,
+                  self.nu, int(nsteps), ctypes.byref(which), _stream_ptr(stream)), "wx_rw_run")
         self.cur = self.cur if which.value == 0 else 1 - self.cur
 
     def step_into(self, stream=None) -> None:
-        """One step through wx_rw_step (the single-step entry point)."""
+        """One step through wx_rw_step (the single-step entry point, IJK order)."""
+        if self.order != "ijk":
+            raise WxError("wx_rw_step takes the IJK order")
         _check(self.lib.wx_rw_step(self.buf[self.cur].data_ptr(), self.buf[1 - self.cur].data_ptr(),
                                    self.surf.data_ptr(), self.pbl.data_ptr(), self.nx, self.ny, self.nz,
                                    self.nu, _stream_ptr(stream)), "wx_rw_step")
@@ -556,7 +564,9 @@ class ReducedApp:
         return self.buf[self.cur]
 
     def download(self) -> np.ndarray:
+        """The field in the oracle's [nz][ny+2][nx+2] order."""
         torch = _torch()
         torch.cuda.synchronize(self.buf[0].device)
-        return self.field.cpu().numpy()
+        f = self.field.cpu().numpy()
+        return f if self.order == "ijk" else np.ascontiguousarray(np.transpose(f, (2, 0, 1)))
 

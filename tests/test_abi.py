@@ -181,3 +181,10 @@ def test_reduced_app_validates_before_any_launch(lib):
     # zero steps launch nothing and leave the result in the first array
     assert lib.wx_rw_run(a, b, s, p, 4, 4, 4, 0.1, 0, ctypes.byref(which), None) == wx.WX_OK
     assert which.value == 0
+    # the KIJ-order entry point validates the same way
+    assert lib.wx_rw_run_kij(a, a, s, p, 4, 4, 4, 0.1, 1, ctypes.byref(which), None) == inval
+    assert lib.wx_rw_run_kij(a, b, s, p, 4, 4, 1, 0.1, 1, ctypes.byref(which), None) == inval
+    assert lib.wx_rw_run_kij(a, b, s, p, 4, 4, 4, 0.1, -1, ctypes.byref(which), None) == inval
+    which.value = 7
+    assert lib.wx_rw_run_kij(a, b, s, p, 4, 4, 4, 0.1, 0, ctypes.byref(which), None) == wx.WX_OK
+    assert which.value == 0

@@ -89,3 +89,24 @@ def test_paper_largest_shape_sampled_columns():
         cp = pbl[j - h:j + h + 1, i - h:i + h + 1]
         ref = rw.simulate(crop, cs, cp, nsteps)
         np.testing.assert_array_equal(got[:, j, i], ref[:, h, h], err_msg=f"column ({i}, {j})")
+
+
+@pytest.mark.parametrize("nx,ny,nz,nsteps", [(5, 4, 2, 3), (70, 9, 17, 4), (1, 1, 3, 5)])
+def test_kij_order_bitwise(nx, ny, nz, nsteps):
+    _say(f"case: reduced app KIJ order {nx}x{ny}x{nz}, {nsteps} steps")
+    e, surf, pbl = _random_case(nx, ny, nz, seed=nx * 7 + nz)
+    app = wx.ReducedApp(e, surf, pbl, 0.1, order="kij")
+    app.run(nsteps)
+    np.testing.assert_array_equal(app.download(), rw.simulate(e, surf, pbl, nsteps, 0.1))
+
+
+def test_kij_order_equals_ijk_order_128_cubed():
+    _say("case: reduced app KIJ vs IJK order, 128^3 box, 10 steps")
+    n = 128
+    e = rw.box_init(n, n, n)
+    surf, pbl = rw.boundary_fields(n, n)
+    a = wx.ReducedApp(e, surf, pbl, rw.NU_DEFAULT)
+    b = wx.ReducedApp(e, surf, pbl, rw.NU_DEFAULT, order="kij")
+    a.run(10)
+    b.run(10)
+    np.testing.assert_array_equal(a.download(), b.download())
