@@ -138,7 +138,9 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
   if (a.fallback && *a.fallback) return;
   const bool rows_mode = a.rows_out != nullptr;
   const int nrows = rows_mode ? (a.n_list ? min(*a.n_list, a.cap) : a.cap) : a.ncols;
-  const int r0 = blockIdx.x * FT;
+  // tiles numbered so that each XCD works through a contiguous band: the
+  // row above a tile (its v(j-1) reads) was loaded by a tile on the same L2
+  const int r0 = xcd_remap(blockIdx.x, gridDim.x) * FT;
   if (r0 >= nrows) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nx = a.g.nx;
