@@ -103,7 +103,7 @@ def test_forward_matches_oracle(n):
     assert np.all(y[:, NOUT:] == 0)
 
 
-@pytest.mark.parametrize("batch", [300, 4096])
+@pytest.mark.parametrize("batch", [1, 257, 300, 4096])
 def test_gradients_match_oracle(batch):
     _say(f"case: gradients batch={batch}")
     torch = _torch()
