@@ -48,10 +48,14 @@ __device__ __forceinline__ void load_tile(uint16_t *lds, const uint16_t *g, int 
     }
     *reinterpret_cast<uint4 *>(lds + r * GLD + kk) = v;
   } else {
+    // rows_idx here indirects the k index (a batch gather of [K][ld] rows)
     const int kk = t >> 3, r = (t & 7) * 8;             // 32 k x 8 chunks of 8 rows
     const int gr = r0 + r, gk = k0 + kk;
     uint4 v = make_uint4(0, 0, 0, 0);
-    if (gk < nk && gr < nrows) v = *reinterpret_cast<const uint4 *>(g + (size_t)gk * ld + gr);
+    if (gk < nk && gr < nrows) {
+      const int krow = rows_idx ? rows_idx[gk] : gk;
+      v = *reinterpret_cast<const uint4 *>(g + (size_t)krow * ld + gr);
+    }
     const uint16_t *e = reinterpret_cast<const uint16_t *>(&v);
 #pragma unroll
     for (int q = 0; q < 8; ++q) lds[(r + q) * GLD + kk] = e[q];
@@ -66,7 +70,8 @@ struct GemmArgs {
   int lda, ldb;
   int M, N, K;                 // logical sizes (K = reduction length of this launch's split)
   int k_split;                 // K elements per split (grid.z splits)
-  const int *rows_a;           // optional row gather for A (KCONTIG only)
+  const int *rows_a;           // optional gather of A's rows (KCONTIG) or k rows (not KCONTIG)
+  const int *rows_b;           // optional gather of B's k rows (B not KCONTIG)
   const float *bias;           // [N]
   void *C;                     // output
   int ldc;
@@ -91,7 +96,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   const int nsteps = (ke - kb + GBK - 1) / GBK;
   if (nsteps > 0) {
     load_tile<AK>(sA[0], a.A, a.lda, m0, kb, a.M, ke, a.rows_a);
-    load_tile<BK_>(sB[0], a.B, a.ldb, n0, kb, a.N, ke, nullptr);
+    load_tile<BK_>(sB[0], a.B, a.ldb, n0, kb, a.N, ke, a.rows_b);
   }
   __syncthreads();
   // lane holds row (or column) lane % 32 of its operand at k = 8 (lane / 32)..+7
@@ -101,7 +106,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
     const int cur = s & 1;
     if (s + 1 < nsteps) {
       load_tile<AK>(sA[cur ^ 1], a.A, a.lda, m0, kb + (s + 1) * GBK, a.M, ke, a.rows_a);
-      load_tile<BK_>(sB[cur ^ 1], a.B, a.ldb, n0, kb + (s + 1) * GBK, a.N, ke, nullptr);
+      load_tile<BK_>(sB[cur ^ 1], a.B, a.ldb, n0, kb + (s + 1) * GBK, a.N, ke, a.rows_b);
     }
 #pragma unroll
     for (int kk = 0; kk < GBK; kk += 16) {
@@ -162,11 +167,29 @@ __global__ void k_loss(const float *y, const float *t, const int *rows, int batc
   if (n == 0) row_loss[m] = sh[0];
 }
 
+// One Adam update of element i of tensor S with gradient g; refreshes the
+// BF16 copies (row-major, transposed, fragment order) that exist.
+__device__ __forceinline__ void adam_elem(const AdamArgs &a, const AdamSeg &S, size_t i, float g) {
+  const float mi = 0.9f * S.m[i] + 0.1f * g;
+  const float vi = 0.999f * S.v[i] + 0.001f * g * g;
+  S.m[i] = mi;
+  S.v[i] = vi;
+  const float wi = S.w[i] - a.lr * (mi / a.bc1) / (sqrtf(vi / a.bc2) + 1e-8f);
+  S.w[i] = wi;
+  if (S.wb) {
+    const uint16_t h = f2bf(wi);
+    S.wb[i] = h;
+    const int r = int(i / S.cols), c = int(i % S.cols);
+    if (S.wbt) S.wbt[(size_t)c * S.rows + r] = h;
+    if (S.wbp) S.wbp[frag_index(r, c, S.cols)] = h;
+  }
+}
+
 // Column sums of up to four [rows][lda] FP32 matrices (one block's share).  Block b
 // covers 16 columns of one matrix; thread (quad q, group g) sums columns
 // 16b + 4q .. 16b + 4q + 3 over rows g, g + 64, ... in order (float4 loads
 // when the matrix allows), then the 64 group sums are folded in a fixed tree.
-__device__ __forceinline__ void colsum_block(const ColsumArgs &a, int b) {
+__device__ __forceinline__ void colsum_block(const ColsumArgs &a, int b, const AdamArgs *adam, const int *seg) {
   __shared__ float sh[64][17];
   int jb = 0;
   while (jb + 1 < a.njobs && b >= a.job[jb].blocks) {
@@ -207,11 +230,15 @@ __device__ __forceinline__ void colsum_block(const ColsumArgs &a, int b) {
     for (int gg = grp; gg < h; gg += 16) sh[gg][col] += sh[gg + h][col];
     __syncthreads();
   }
-  if (threadIdx.x < 16 && b * 16 + col < J.cols) J.out[b * 16 + col] = sh[0][col];
+  if (threadIdx.x < 16 && b * 16 + col < J.cols) {
+    J.out[b * 16 + col] = sh[0][col];
+    if (adam && seg[jb] >= 0) adam_elem(*adam, adam->seg[seg[jb]], size_t(b * 16 + col), sh[0][col]);
+  }
 }
 
 // Weight gradients as ordered sums of split-K slices (first blocks), then the
-// bias-gradient and loss column sums (remaining blocks).
+// bias-gradient and loss column sums (remaining blocks); with adam_on each
+// gradient element also takes its Adam update right where it is formed.
 __global__ void __launch_bounds__(256) k_grad_finish(GradFinishArgs a) {
   int b = blockIdx.x;
   for (int j = 0; j < a.nsj; ++j) {
@@ -222,11 +249,12 @@ __global__ void __launch_bounds__(256) k_grad_finish(GradFinishArgs a) {
       float s = 0.f;
       for (int p = 0; p < J.nsplit; ++p) s += J.part[p * J.stride + i];
       J.out[i] = s;
+      if (a.adam_on) adam_elem(a.adam, a.adam.seg[a.sj_seg[j]], size_t(i), s);
       return;
     }
     b -= J.blocks;
   }
-  colsum_block(a.cs, b);
+  colsum_block(a.cs, b, a.adam_on ? &a.adam : nullptr, a.cs_seg);
 }
 
 // Adam over the six parameter tensors in one launch (element i of the
@@ -238,20 +266,7 @@ __global__ void k_adam_multi(AdamArgs a) {
   const AdamSeg &S = a.seg[t];
   const size_t i = gi - S.start;
   if (i >= S.n) return;
-  const float g = S.g[i];
-  const float mi = 0.9f * S.m[i] + 0.1f * g;
-  const float vi = 0.999f * S.v[i] + 0.001f * g * g;
-  S.m[i] = mi;
-  S.v[i] = vi;
-  const float wi = S.w[i] - a.lr * (mi / a.bc1) / (sqrtf(vi / a.bc2) + 1e-8f);
-  S.w[i] = wi;
-  if (S.wb) {
-    const uint16_t h = f2bf(wi);
-    S.wb[i] = h;
-    const int r = int(i / S.cols), c = int(i % S.cols);
-    if (S.wbt) S.wbt[(size_t)c * S.rows + r] = h;
-    if (S.wbp) S.wbp[frag_index(r, c, S.cols)] = h;
-  }
+  adam_elem(a, S, i, S.g[i]);
 }
 
 // BF16 copies of FP32 weights (after initialisation or an upload).
@@ -287,7 +302,7 @@ hipError_t launch_gemm(const GemmSpec &g, hipStream_t s) {
   a.M = g.M; a.N = g.N; a.K = g.K;
   a.k_split = g.splits > 1 ? (g.K + g.splits - 1) / g.splits : g.K;
   a.k_split = (a.k_split + GBK - 1) / GBK * GBK;
-  a.rows_a = g.rows_a; a.bias = g.bias;
+  a.rows_a = g.rows_a; a.rows_b = g.rows_b; a.bias = g.bias;
   a.C = g.C; a.ldc = g.ldc; a.split_stride = g.split_stride;
   a.mask = g.mask; a.C2 = g.C2;
   const int splits = g.splits > 1 ? (g.K + a.k_split - 1) / a.k_split : 1;

@@ -157,13 +157,6 @@ __global__ void k_normalize(const float *xr, const float *yr, size_t n, const fl
       yo[r * MLP_NOUTP + o] = o < MLP_NOUT ? (yr[r * MLP_NOUTP + o] - ym[o]) / ys[o] : 0.f;
 }
 
-__global__ void k_gather_rows(const uint16_t *x, const int *rows, int batch, uint16_t *out) {
-  const int m = blockIdx.x;
-  const uint4 *src = reinterpret_cast<const uint4 *>(x + (size_t)rows[m] * MLP_KIN);
-  uint4 *dst = reinterpret_cast<uint4 *>(out + (size_t)m * MLP_KIN);
-  for (int q = threadIdx.x; q < MLP_KIN / 8; q += blockDim.x) dst[q] = src[q];
-}
-
 }  // namespace
 
 template <typename T>
@@ -207,11 +200,6 @@ hipError_t launch_normalize(const float *xr, const float *yr, size_t n, const fl
                             const float *ym, const float *ys, uint16_t *xo, float *yo, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_normalize, dim3(unsigned(n)), dim3(128), 0, s, xr, yr, n, xm, xis, ym, ys, xo, yo);
-  return hipGetLastError();
-}
-
-hipError_t launch_gather_rows(const uint16_t *x, const int *rows, int batch, uint16_t *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_rows, dim3(batch), dim3(64), 0, s, x, rows, batch, out);
   return hipGetLastError();
 }
 

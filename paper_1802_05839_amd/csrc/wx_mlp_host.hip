@@ -84,7 +84,7 @@ bool al16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 // Training workspace for a batch of B rows.
 struct Work {
-  uint16_t *xb, *h1, *h2, *d3b, *g2b, *g1b;
+  uint16_t *h1, *h2, *d3b, *g2b, *g1b;
   float *y, *d3f, *g2f, *g1f, *row_loss;
   float *part3, *part2, *part1;            // split-K slices of dW3, dW2, dW1
   size_t total;
@@ -100,7 +100,6 @@ Work work_layout(void *base, int B) {
     off += a256(bytes);
     return r;
   };
-  w.xb = reinterpret_cast<uint16_t *>(take(size_t(B) * MLP_KIN * 2));
   w.h1 = reinterpret_cast<uint16_t *>(take(size_t(B) * MLP_NHID * 2));
   w.h2 = reinterpret_cast<uint16_t *>(take(size_t(B) * MLP_NHID * 2));
   w.d3b = reinterpret_cast<uint16_t *>(take(size_t(B) * MLP_NOUTP * 2));
@@ -119,17 +118,19 @@ Work work_layout(void *base, int B) {
   return w;
 }
 
-int forward_layers(const void *blob, const uint16_t *x, int n, uint16_t *h1, uint16_t *h2, float *y,
+// The three layers for rows x[rows[m]] (or x[m] when rows is null), m < n.
+int forward_layers(const void *blob, const uint16_t *x, const int *rows, int n, uint16_t *h1, uint16_t *h2, float *y,
                    hipStream_t st) {
   GemmSpec g{};
   g.a_kcontig = g.b_kcontig = true;
   g.splits = 1;
   g.M = n;
-  // layer 1
-  g.A = x; g.lda = MLP_KIN; g.B = sec<uint16_t>(blob, WX_MLP_W1_BF16); g.ldb = MLP_KIN;
+  // layer 1 (gathering the batch rows on the way into LDS)
+  g.A = x; g.lda = MLP_KIN; g.rows_a = rows; g.B = sec<uint16_t>(blob, WX_MLP_W1_BF16); g.ldb = MLP_KIN;
   g.N = MLP_NHID; g.K = MLP_KIN; g.bias = sec<float>(blob, WX_MLP_B1); g.C = h1; g.ldc = MLP_NHID;
   g.epilogue = GEMM_BIAS_RELU_BF16;
   MLP_HIP(launch_gemm(g, st));
+  g.rows_a = nullptr;
   // layer 2
   g.A = h1; g.lda = MLP_NHID; g.B = sec<uint16_t>(blob, WX_MLP_W2_BF16); g.ldb = MLP_NHID;
   g.N = MLP_NHID; g.K = MLP_NHID; g.bias = sec<float>(blob, WX_MLP_B2); g.C = h2; g.ldc = MLP_NHID;
@@ -142,13 +143,14 @@ int forward_layers(const void *blob, const uint16_t *x, int n, uint16_t *h1, uin
   return WX_OK;
 }
 
-// dW[n][k] = sum_m d[m][n] act[m][k] over the batch as split-K partial slices;
-// *job describes their ordered sum into out (run by launch_grad_finish).
-int weight_grad(const uint16_t *d, int ldd, int nout, const uint16_t *act, int lda, int kin, int B, float *part,
-                float *out, SplitJob *job, hipStream_t st) {
+// dW[n][k] = sum_m d[m][n] act[act_rows[m]][k] over the batch (act row m when
+// act_rows is null) as split-K partial slices; *job describes their ordered
+// sum into out (run by launch_grad_finish).
+int weight_grad(const uint16_t *d, int ldd, int nout, const uint16_t *act, const int *act_rows, int lda, int kin,
+                int B, float *part, float *out, SplitJob *job, hipStream_t st) {
   GemmSpec g{};
   g.a_kcontig = g.b_kcontig = false;
-  g.A = d; g.lda = ldd; g.B = act; g.ldb = lda;
+  g.A = d; g.lda = ldd; g.B = act; g.ldb = lda; g.rows_b = act_rows;
   g.M = nout; g.N = kin; g.K = B;
   g.splits = (B + Work::kSplitRows - 1) / Work::kSplitRows;
   g.C = part; g.ldc = kin; g.split_stride = size_t(nout) * kin;
@@ -172,6 +174,83 @@ int input_grad(const uint16_t *d, int ldd, int nred, const uint16_t *wt, int kou
   g.C = out; g.ldc = kout; g.epilogue = GEMM_MASK_F32_BF16;
   g.mask = h; g.C2 = out16;
   MLP_HIP(launch_gemm(g, st));
+  return WX_OK;
+}
+
+// Adam step t with rate lr over the six parameter tensors of the blob (their
+// gradients, moments and BF16 copies).
+AdamArgs adam_args(void *blob, float lr, int t) {
+  uint16_t *wb[6] = {sec<uint16_t>(blob, WX_MLP_W1_BF16), nullptr, sec<uint16_t>(blob, WX_MLP_W2_BF16), nullptr,
+                     sec<uint16_t>(blob, WX_MLP_W3_BF16), nullptr};
+  uint16_t *wbt[6] = {nullptr, nullptr, sec<uint16_t>(blob, WX_MLP_W2T_BF16), nullptr,
+                      sec<uint16_t>(blob, WX_MLP_W3T_BF16), nullptr};
+  uint16_t *wbp[6] = {packed_weights(blob, 0), nullptr, packed_weights(blob, 1), nullptr, packed_weights(blob, 2),
+                      nullptr};
+  const int rows[6] = {MLP_NHID, 1, MLP_NHID, 1, MLP_NOUTP, 1};
+  const int cols[6] = {MLP_KIN, MLP_NHID, MLP_NHID, MLP_NHID, MLP_NHID, MLP_NOUTP};
+  AdamArgs aa{};
+  aa.lr = lr;
+  aa.bc1 = float(1.0 - std::pow(0.9, t));
+  aa.bc2 = float(1.0 - std::pow(0.999, t));
+  size_t start = 0;
+  for (int p = 0; p < 6; ++p) {
+    aa.seg[p] = {sec<float>(blob, p), sec<float>(blob, WX_MLP_GRAD + p), sec<float>(blob, WX_MLP_ADAM_M + p),
+                 sec<float>(blob, WX_MLP_ADAM_V + p), wb[p], wbt[p], wbp[p], start, kParamElems[p], rows[p], cols[p]};
+    start += kParamElems[p];
+  }
+  return aa;
+}
+
+// Forward, loss and backward for one batch; with adam non-null the finishing
+// launch also applies the Adam step to every parameter as its gradient forms.
+int forward_backward(void *blob, void *work, const void *x, const float *y, const int32_t *rows, int batch,
+                     float *loss_sum, const AdamArgs *adam, void *stream) {
+  if (!blob || !work || !x || !y || !rows || !loss_sum) return fail(WX_E_INVAL, "NULL argument");
+  if (batch < 1 || batch > 65536) return fail(WX_E_INVAL, "batch must be in 1..65536");
+  if (!al16(blob) || !al16(work) || !al16(x)) return fail(WX_E_INVAL, "blob, work and x must be 16-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Work w = work_layout(work, batch);
+  const int B = batch;
+  const uint16_t *xs = static_cast<const uint16_t *>(x);
+  if (int rc = forward_layers(blob, xs, rows, B, w.h1, w.h2, w.y, st)) return rc;
+  MLP_HIP(launch_loss(w.y, y, rows, B, MLP_NOUT, MLP_NOUTP, w.d3f, w.d3b, w.row_loss, st));
+  GradFinishArgs gf{};
+  gf.nsj = 3;
+  // output layer
+  if (int rc = weight_grad(w.d3b, MLP_NOUTP, MLP_NOUTP, w.h2, nullptr, MLP_NHID, MLP_NHID, B, w.part3,
+                           sec<float>(blob, WX_MLP_GRAD + 4), &gf.sj[0], st))
+    return rc;
+  // hidden layer 2 (the ReLU mask and BF16 rounding in the GEMM's epilogue)
+  if (int rc = input_grad(w.d3b, MLP_NOUTP, MLP_NOUTP, sec<uint16_t>(blob, WX_MLP_W3T_BF16), MLP_NHID, B, w.h2,
+                          w.g2f, w.g2b, st))
+    return rc;
+  if (int rc = weight_grad(w.g2b, MLP_NHID, MLP_NHID, w.h1, nullptr, MLP_NHID, MLP_NHID, B, w.part2,
+                           sec<float>(blob, WX_MLP_GRAD + 2), &gf.sj[1], st))
+    return rc;
+  // hidden layer 1
+  if (int rc = input_grad(w.g2b, MLP_NHID, MLP_NHID, sec<uint16_t>(blob, WX_MLP_W2T_BF16), MLP_NHID, B, w.h1,
+                          w.g1f, w.g1b, st))
+    return rc;
+  if (int rc = weight_grad(w.g1b, MLP_NHID, MLP_NHID, xs, rows, MLP_KIN, MLP_KIN, B, w.part1,
+                           sec<float>(blob, WX_MLP_GRAD + 0), &gf.sj[2], st))
+    return rc;
+  // one launch for the rest, fixed order: the weight gradients (ordered sums
+  // of their split-K slices), the bias gradients (column sums of the
+  // unrounded FP32 deltas) and the loss (sum of the per-row sums)
+  ColsumArgs &cs = gf.cs;
+  cs.rows = B;
+  cs.njobs = 4;
+  cs.job[0] = {w.d3f, MLP_NOUTP, MLP_NOUTP, sec<float>(blob, WX_MLP_GRAD + 5), MLP_NOUTP / 16, 1};
+  cs.job[1] = {w.g2f, MLP_NHID, MLP_NHID, sec<float>(blob, WX_MLP_GRAD + 3), MLP_NHID / 16, 1};
+  cs.job[2] = {w.g1f, MLP_NHID, MLP_NHID, sec<float>(blob, WX_MLP_GRAD + 1), MLP_NHID / 16, 1};
+  cs.job[3] = {w.row_loss, 1, 1, loss_sum, 1, 0};
+  if (adam) {
+    gf.adam = *adam;
+    gf.adam_on = 1;
+    gf.sj_seg[0] = 4; gf.sj_seg[1] = 2; gf.sj_seg[2] = 0;                    // dW3, dW2, dW1
+    gf.cs_seg[0] = 5; gf.cs_seg[1] = 3; gf.cs_seg[2] = 1; gf.cs_seg[3] = -1;  // db3, db2, db1, loss
+  }
+  MLP_HIP(launch_grad_finish(gf, st));
   return WX_OK;
 }
 
@@ -252,80 +331,23 @@ size_t wx_mlp_work_bytes(int batch) {
 
 int wx_mlp_forward_backward(void *blob, void *work, const void *x, const float *y, const int32_t *rows, int batch,
                             float *loss_sum, void *stream) {
-  if (!blob || !work || !x || !y || !rows || !loss_sum) return fail(WX_E_INVAL, "NULL argument");
-  if (batch < 1 || batch > 65536) return fail(WX_E_INVAL, "batch must be in 1..65536");
-  if (!al16(blob) || !al16(work) || !al16(x)) return fail(WX_E_INVAL, "blob, work and x must be 16-byte aligned");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const Work w = work_layout(work, batch);
-  const int B = batch;
-  MLP_HIP(launch_gather_rows(static_cast<const uint16_t *>(x), rows, B, w.xb, st));
-  if (int rc = forward_layers(blob, w.xb, B, w.h1, w.h2, w.y, st)) return rc;
-  MLP_HIP(launch_loss(w.y, y, rows, B, MLP_NOUT, MLP_NOUTP, w.d3f, w.d3b, w.row_loss, st));
-  GradFinishArgs gf{};
-  gf.nsj = 3;
-  // output layer
-  if (int rc = weight_grad(w.d3b, MLP_NOUTP, MLP_NOUTP, w.h2, MLP_NHID, MLP_NHID, B, w.part3,
-                           sec<float>(blob, WX_MLP_GRAD + 4), &gf.sj[0], st))
-    return rc;
-  // hidden layer 2 (the ReLU mask and BF16 rounding in the GEMM's epilogue)
-  if (int rc = input_grad(w.d3b, MLP_NOUTP, MLP_NOUTP, sec<uint16_t>(blob, WX_MLP_W3T_BF16), MLP_NHID, B, w.h2,
-                          w.g2f, w.g2b, st))
-    return rc;
-  if (int rc = weight_grad(w.g2b, MLP_NHID, MLP_NHID, w.h1, MLP_NHID, MLP_NHID, B, w.part2,
-                           sec<float>(blob, WX_MLP_GRAD + 2), &gf.sj[1], st))
-    return rc;
-  // hidden layer 1
-  if (int rc = input_grad(w.g2b, MLP_NHID, MLP_NHID, sec<uint16_t>(blob, WX_MLP_W2T_BF16), MLP_NHID, B, w.h1,
-                          w.g1f, w.g1b, st))
-    return rc;
-  if (int rc = weight_grad(w.g1b, MLP_NHID, MLP_NHID, w.xb, MLP_KIN, MLP_KIN, B, w.part1,
-                           sec<float>(blob, WX_MLP_GRAD + 0), &gf.sj[2], st))
-    return rc;
-  // one launch for the rest, fixed order: the weight gradients (ordered sums
-  // of their split-K slices), the bias gradients (column sums of the
-  // unrounded FP32 deltas) and the loss (sum of the per-row sums)
-  ColsumArgs &cs = gf.cs;
-  cs.rows = B;
-  cs.njobs = 4;
-  cs.job[0] = {w.d3f, MLP_NOUTP, MLP_NOUTP, sec<float>(blob, WX_MLP_GRAD + 5), MLP_NOUTP / 16, 1};
-  cs.job[1] = {w.g2f, MLP_NHID, MLP_NHID, sec<float>(blob, WX_MLP_GRAD + 3), MLP_NHID / 16, 1};
-  cs.job[2] = {w.g1f, MLP_NHID, MLP_NHID, sec<float>(blob, WX_MLP_GRAD + 1), MLP_NHID / 16, 1};
-  cs.job[3] = {w.row_loss, 1, 1, loss_sum, 1, 0};
-  MLP_HIP(launch_grad_finish(gf, st));
-  return WX_OK;
+  return forward_backward(blob, work, x, y, rows, batch, loss_sum, nullptr, stream);
 }
 
 int wx_mlp_adam(void *blob, float lr, int t, void *stream) {
   if (!blob || !al16(blob)) return fail(WX_E_INVAL, "blob is NULL or misaligned");
   if (t < 1 || !(lr >= 0.f)) return fail(WX_E_INVAL, "t must be >= 1 and lr >= 0");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const float bc1 = float(1.0 - std::pow(0.9, t)), bc2 = float(1.0 - std::pow(0.999, t));
-  uint16_t *wb[6] = {sec<uint16_t>(blob, WX_MLP_W1_BF16), nullptr, sec<uint16_t>(blob, WX_MLP_W2_BF16), nullptr,
-                     sec<uint16_t>(blob, WX_MLP_W3_BF16), nullptr};
-  uint16_t *wbt[6] = {nullptr, nullptr, sec<uint16_t>(blob, WX_MLP_W2T_BF16), nullptr,
-                      sec<uint16_t>(blob, WX_MLP_W3T_BF16), nullptr};
-  uint16_t *wbp[6] = {packed_weights(blob, 0), nullptr, packed_weights(blob, 1), nullptr, packed_weights(blob, 2),
-                      nullptr};
-  const int rows[6] = {MLP_NHID, 1, MLP_NHID, 1, MLP_NOUTP, 1};
-  const int cols[6] = {MLP_KIN, MLP_NHID, MLP_NHID, MLP_NHID, MLP_NHID, MLP_NOUTP};
-  AdamArgs aa{};
-  aa.lr = lr;
-  aa.bc1 = bc1;
-  aa.bc2 = bc2;
-  size_t start = 0;
-  for (int p = 0; p < 6; ++p) {
-    aa.seg[p] = {sec<float>(blob, p), sec<float>(blob, WX_MLP_GRAD + p), sec<float>(blob, WX_MLP_ADAM_M + p),
-                 sec<float>(blob, WX_MLP_ADAM_V + p), wb[p], wbt[p], wbp[p], start, kParamElems[p], rows[p], cols[p]};
-    start += kParamElems[p];
-  }
-  MLP_HIP(launch_adam_multi(aa, st));
+  MLP_HIP(launch_adam_multi(adam_args(blob, lr, t), static_cast<hipStream_t>(stream)));
   return WX_OK;
 }
 
 int wx_mlp_train_step(void *blob, void *work, const void *x, const float *y, const int32_t *rows, int batch, float lr,
                       int t, float *loss_sum, void *stream) {
-  if (int rc = wx_mlp_forward_backward(blob, work, x, y, rows, batch, loss_sum, stream)) return rc;
-  return wx_mlp_adam(blob, lr, t, stream);
+  if (!blob || !al16(blob)) return fail(WX_E_INVAL, "blob is NULL or misaligned");
+  if (t < 1 || !(lr >= 0.f)) return fail(WX_E_INVAL, "t must be >= 1 and lr >= 0");
+  // the Adam step runs inside the launch that forms the gradients
+  const AdamArgs aa = adam_args(blob, lr, t);
+  return forward_backward(blob, work, x, y, rows, batch, loss_sum, &aa, stream);
 }
 
 size_t wx_mlp_infer_work_bytes(int n) {
@@ -338,7 +360,7 @@ int wx_mlp_infer(const void *blob, void *work, const void *x, int n, float *y_ou
   if (!al16(blob) || !al16(work) || !al16(x)) return fail(WX_E_INVAL, "blob, work and x must be 16-byte aligned");
   uint16_t *h1 = static_cast<uint16_t *>(work);
   uint16_t *h2 = reinterpret_cast<uint16_t *>(static_cast<unsigned char *>(work) + a256(size_t(n) * MLP_NHID * 2));
-  return forward_layers(blob, static_cast<const uint16_t *>(x), n, h1, h2, y_out, static_cast<hipStream_t>(stream));
+  return forward_layers(blob, static_cast<const uint16_t *>(x), nullptr, n, h1, h2, y_out, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -94,6 +94,7 @@ struct GemmSpec {
   int M, N, K;
   int splits;                  // > 1: split K, write partial slices
   const int *rows_a;           // optional gather of A rows (a_kcontig only)
+  const int *rows_b;           // optional gather of B's k rows (!b_kcontig only)
   const float *bias;
   void *C;
   int ldc;
@@ -109,6 +110,20 @@ hipError_t launch_gemm(const GemmSpec &g, hipStream_t s);
 hipError_t launch_loss(const float *y, const float *t, const int *rows, int batch, int nout, int ldy, float *d32,
                        uint16_t *d16, float *row_loss, hipStream_t s);
 
+// Adam over the six parameter tensors in one launch.
+struct AdamSeg {
+  float *w;
+  const float *g;
+  float *m, *v;
+  uint16_t *wb, *wbt;   // BF16 copy and transpose (may be null)
+  uint16_t *wbp;        // BF16 copy in fragment order (may be null)
+  size_t start, n;      // range in the concatenation
+  int rows, cols;
+};
+struct AdamArgs {
+  AdamSeg seg[6];
+  float lr, bc1, bc2;
+};
 // Column sums of up to four matrices (fixed order), run inside launch_grad_finish.
 struct ColsumJob {
   const float *a;   // [rows][lda]
@@ -135,23 +150,15 @@ struct GradFinishArgs {
   SplitJob sj[3];
   int nsj;
   ColsumArgs cs;
+  // optional Adam step on each gradient element as it is formed: split job j
+  // updates tensor adam.seg[sj_seg[j]], column-sum job j tensor
+  // adam.seg[cs_seg[j]] (-1: no update, the loss)
+  AdamArgs adam;
+  int adam_on;
+  int sj_seg[3], cs_seg[4];
 };
 hipError_t launch_grad_finish(const GradFinishArgs &a, hipStream_t s);
 
-// Adam over the six parameter tensors in one launch.
-struct AdamSeg {
-  float *w;
-  const float *g;
-  float *m, *v;
-  uint16_t *wb, *wbt;   // BF16 copy and transpose (may be null)
-  uint16_t *wbp;        // BF16 copy in fragment order (may be null)
-  size_t start, n;      // range in the concatenation
-  int rows, cols;
-};
-struct AdamArgs {
-  AdamSeg seg[6];
-  float lr, bc1, bc2;
-};
 hipError_t launch_adam_multi(const AdamArgs &a, hipStream_t s);
 hipError_t launch_to_bf16(const float *w, size_t n, uint16_t *wb, uint16_t *wbt, uint16_t *wbp, int rows, int cols,
                           hipStream_t s);
@@ -197,7 +204,6 @@ hipError_t launch_fit_norm(const float *xr, const float *yr, size_t n, double *s
 size_t fit_norm_scratch_bytes(size_t n);
 hipError_t launch_normalize(const float *xr, const float *yr, size_t n, const float *xm, const float *xis,
                             const float *ym, const float *ys, uint16_t *xo, float *yo, hipStream_t s);
-hipError_t launch_gather_rows(const uint16_t *x, const int *rows, int batch, uint16_t *out, hipStream_t s);
 
 hipError_t launch_sample(int ncol, uint64_t seed, uint64_t t, unsigned rate, int *block_count, int *block_off,
                          int *n_list, int cap, int *list, hipStream_t s);

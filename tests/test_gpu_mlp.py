@@ -170,6 +170,29 @@ def test_adam_matches_oracle():
     _check_fragment_copies(m)
 
 
+def test_train_step_equals_forward_backward_then_adam():
+    # the train step applies Adam inside the launch that forms the gradients;
+    # it must equal the separate calls bit for bit, including the BF16 copies
+    _say("case: fused train step vs forward_backward + adam, 3 steps")
+    torch = _torch()
+    rng = np.random.default_rng(31)
+    nrows, batch = 1500, 300
+    x = _to_bf16_tensor(_bf16_rows(rng, nrows))
+    t = np.zeros((nrows, NOUTP), np.float32)
+    t[:, :NOUT] = rng.normal(0, 1, (nrows, NOUT))
+    y = torch.from_numpy(t).cuda()
+    a, b = wx.Mlp(), wx.Mlp()
+    a.init(2)
+    b.init(2)
+    for step in (1, 2, 3):
+        rows = torch.from_numpy(rng.permutation(nrows)[:batch].astype(np.int32)).cuda()
+        a.train_step(x, y, rows, 1e-3, step)
+        b.forward_backward(x, y, rows)
+        b.adam(1e-3, step)
+    torch.cuda.synchronize()
+    assert torch.equal(a.blob, b.blob)
+
+
 def _fragment_order(w):
     """[N][K] -> matrix-core fragment order: block (R, S) of 32 rows x 16 k,
     lane l = row % 32 + 32 * (k % 16 // 8) holding its 8 consecutive k."""
