@@ -20,13 +20,15 @@
 // reads (it is pointwise in each column apart from its own surface and
 // boundary-layer values), so a step reads the field once and writes it once:
 // 16 B per cell.  A 64 x 4 block of threads owns a tile of interior columns
-// (i fastest, coalesced 512-byte rows) and marches a chunk of levels,
-// carrying the vertical window k-1, k, k+1 in registers and loading the next
-// level's horizontal neighbours one level ahead; those come through L1/L2.
-// Tiles of one level chunk are numbered i-fastest and mapped XCD by XCD, so
-// the rows shared by j-neighbouring tiles meet in one L2.  The ring cells
-// (about 1% of a large grid) take extra blocks of the same launch, one cell
-// per thread, so no wavefront mixes the two rules.
+// (i fastest, coalesced rows) and marches a chunk of levels.  Each level's
+// 66 x 6 tile (the 64 x 4 cells and their one-cell rim) is loaded once with
+// coalesced reads, passed through the physics and kept in a 4-deep LDS ring,
+// so a cell's six neighbours and its vertical window are LDS reads, and the
+// loads of level k+2 are in flight while level k is computed (one barrier per
+// level).  Tiles of one level chunk are numbered i-fastest and mapped XCD by
+// XCD, so the rows shared by j-neighbouring tiles meet in one L2.  The ring
+// cells (about 1% of a large grid) take extra blocks of the same launch, one
+// cell per thread, so no wavefront mixes the two rules.
 #include "wx_internal.h"
 
 #pragma clang fp contract(off)
@@ -105,86 +107,72 @@ __global__ __launch_bounds__(RW_BX *RW_BY) void k_rw_step(RwArgs a) {
     return;
   }
 
-  // ---- interior columns: a 64 x 4 tile marching a chunk of levels
+  // ---- interior columns: a 64 x 4 tile marching a chunk of levels; each
+  // level's 66 x 6 plane tile (after physics) staged in a 4-deep LDS ring
+  __shared__ double sp[4][6][66];
   const int ntile = a.tiles_x * a.tiles_y;
   const int L = xcd_remap(blockIdx.x, nint);
   const int chunk = L / ntile, t = L % ntile;
-  const int i = 1 + (t % a.tiles_x) * RW_BX + threadIdx.x;
-  const int j = 1 + (t / a.tiles_x) * RW_BY + threadIdx.y;
-  if (i > nx || j > ny) return;
+  const int i0 = 1 + (t % a.tiles_x) * RW_BX, j0 = 1 + (t / a.tiles_x) * RW_BY;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * RW_BX + tx;
+  const int i = i0 + tx, j = j0 + ty;
+  const bool active = i <= nx && j <= ny;
   const int k0 = chunk * a.kchunk, k1 = min(nz, k0 + a.kchunk);
-  const unsigned ij = unsigned(i) + unsigned(j) * sj;
-  const unsigned iw = ij - 1, ie = ij + 1, is = ij - sj, in = ij + sj;
-
-  // the surface and boundary-layer values of the column and its four
-  // neighbours, read before the march: they are used on the bottom and top
-  // level, which the column's window (levels k0 - 1 .. k1) may reach from
-  // outside the chunk
-  double sc = 0.0, sw = 0.0, se = 0.0, ss = 0.0, sn = 0.0;
-  double bc = 0.0, bw = 0.0, be = 0.0, bs = 0.0, bn = 0.0;
-  if (k0 <= 1) {
-    sc = a.surf[ij]; sw = a.surf[iw]; se = a.surf[ie]; ss = a.surf[is]; sn = a.surf[in];
-  }
-  if (k1 >= nz - 1) {
-    bc = a.pbl[ij]; bw = a.pbl[iw]; be = a.pbl[ie]; bs = a.pbl[is]; bn = a.pbl[in];
-  }
-  // the column physics of level k on a value whose column has surface value
-  // sv and boundary-layer value bv (the same operations as phys)
-  auto ph = [&](double v, int k, double sv, double bv) {
-    double r = v + 0.1;
-    if (k == 0) {
-      const double lost = 0.01 * (r - sv);
-      r = r - lost;
-    }
-    if (k == nz - 1) {
-      const double lost = 0.01 * (r - bv);
-      r = r - lost;
-    }
-    return r;
-  };
-
-  // vertical window of this column: levels k-1 and k after physics, level
-  // k+1 raw; the raw horizontal neighbours of level k.  Every value is loaded
-  // one level before the level that uses it, and every iteration issues the
-  // same five loads (clamped to a valid level past the chunk), so the wait
-  // for the previous level's loads never drains the ones just issued.
   const double *__restrict__ E = a.e;
   double *__restrict__ OUT = a.out;
-  double pm = 0.0, pc = ph(E[unsigned(k0) * sk + ij], k0, sc, bc), pnr = 0.0;
-  if (k0 > 0) pm = ph(E[unsigned(k0 - 1) * sk + ij], k0 - 1, sc, bc);
-  if (k0 + 1 < nz) pnr = E[unsigned(k0 + 1) * sk + ij];
-  unsigned o = unsigned(k0) * sk;
-  double w = E[o + iw], e = E[o + ie], s = E[o + is], n = E[o + in];
-  for (int k = k0; k < k1; ++k) {
-    const unsigned o1 = k + 1 < k1 ? o + sk : o;
-    const unsigned o2 = k + 2 < nz ? o + 2 * sk : o;
-    const double w1 = E[o1 + iw], e1 = E[o1 + ie], s1 = E[o1 + is], n1 = E[o1 + in];
-    const double c2 = E[o2 + ij];
-    const double pn = k + 1 < nz ? ph(pnr, k + 1, sc, bc) : 0.0;
-    double sum = ph(w, k, sw, bw) + ph(e, k, se, be);
-    sum = sum + ph(s, k, ss, bs);
-    sum = sum + ph(n, k, sn, bn);
-    double r;
-    if (k == 0) {
-      sum = sum + pn;
-      r = pc * a.c5 + nu * sum;
-    } else if (k == nz - 1) {
-      sum = sum + pm;
-      r = pc * a.c5 + nu * sum;
-    } else {
-      sum = sum + pm;
-      sum = sum + pn;
-      r = pc * a.c6 + nu * sum;
+  // this thread's share of the plane tile: elements tid and tid + 256 of 396
+  unsigned goff[2];
+  bool gok[2];
+#pragma unroll
+  for (int n = 0; n < 2; ++n) {
+    const int e = tid + n * 256;
+    const int gi = i0 - 1 + e % 66, gj = j0 - 1 + e / 66;
+    gok[n] = e < 396 && gi <= nx + 1 && gj <= ny + 1;
+    goff[n] = gok[n] ? unsigned(gi) + unsigned(gj) * sj : 0u;
+  }
+  double pv[2];
+  auto fetch = [&](int k) {
+#pragma unroll
+    for (int n = 0; n < 2; ++n) pv[n] = gok[n] ? E[unsigned(k) * sk + goff[n]] : 0.0;
+  };
+  auto stash = [&](int k) {
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+      const int e = tid + n * 256;
+      if (e < 396) sp[k & 3][e / 66][e % 66] = gok[n] ? phys(a, pv[n], k, goff[n]) : 0.0;
     }
-    OUT[o + ij] = r;
-    pm = pc;
-    pc = pn;
-    pnr = c2;
-    w = w1;
-    e = e1;
-    s = s1;
-    n = n1;
-    o += sk;
+  };
+  for (int k = (k0 > 0 ? k0 - 1 : k0); k <= k0 + 1 && k < nz; ++k) {
+    fetch(k);
+    stash(k);
+  }
+  __syncthreads();
+  const int r = ty + 1, c = tx + 1;
+  for (int k = k0; k < k1; ++k) {
+    const bool more = k + 2 < nz && k + 2 <= k1;
+    if (more) fetch(k + 2);
+    if (active) {
+      const double (*P)[66] = sp[k & 3];
+      const double pc = P[r][c];
+      double sum = P[r][c - 1] + P[r][c + 1];
+      sum = sum + P[r - 1][c];
+      sum = sum + P[r + 1][c];
+      double res;
+      if (k == 0) {
+        sum = sum + sp[(k + 1) & 3][r][c];
+        res = pc * a.c5 + nu * sum;
+      } else if (k == nz - 1) {
+        sum = sum + sp[(k - 1) & 3][r][c];
+        res = pc * a.c5 + nu * sum;
+      } else {
+        sum = sum + sp[(k - 1) & 3][r][c];
+        sum = sum + sp[(k + 1) & 3][r][c];
+        res = pc * a.c6 + nu * sum;
+      }
+      OUT[unsigned(k) * sk + unsigned(i) + unsigned(j) * sj] = res;
+    }
+    if (more) stash(k + 2);
+    __syncthreads();
   }
 }
 
