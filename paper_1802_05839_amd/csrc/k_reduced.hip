@@ -19,9 +19,9 @@
 // GPU design: the physics is applied on the fly to every value the diffusion
 // reads (it is pointwise in each column apart from its own surface and
 // boundary-layer values), so a step reads the field once and writes it once:
-// 16 B per cell.  A 64 x 4 block of threads owns a tile of interior columns
+// 16 B per cell.  A 64 x 8 block of threads owns a tile of interior columns
 // (i fastest, coalesced rows) and marches a chunk of levels.  Each level's
-// 66 x 6 tile (the 64 x 4 cells and their one-cell rim) is loaded once with
+// 66 x 10 tile (the 64 x 8 cells and their one-cell rim) is loaded once with
 // coalesced reads, passed through the physics and kept in a 4-deep LDS ring,
 // so a cell's six neighbours and its vertical window are LDS reads, and the
 // loads of level k+2 are in flight while level k is computed (one barrier per
@@ -36,7 +36,10 @@
 namespace wx {
 namespace {
 
-constexpr int RW_BX = 64, RW_BY = 4;
+constexpr int RW_BX = 64, RW_BY = 8;
+constexpr int RW_TW = RW_BX + 2, RW_TH = RW_BY + 2, RW_TN = RW_TW * RW_TH;   // level tile with its rim
+constexpr int RW_NT = RW_BX * RW_BY, RW_NLOAD = (RW_TN + RW_NT - 1) / RW_NT;
+constexpr int KIJ_BX = 64, KIJ_BY = 4;   // the KIJ kernel's thread block (one thread per column)
 
 struct RwArgs {
   const double *e;
@@ -107,9 +110,9 @@ __global__ __launch_bounds__(RW_BX *RW_BY) void k_rw_step(RwArgs a) {
     return;
   }
 
-  // ---- interior columns: a 64 x 4 tile marching a chunk of levels; each
-  // level's 66 x 6 plane tile (after physics) staged in a 4-deep LDS ring
-  __shared__ double sp[4][6][66];
+  // ---- interior columns: a 64 x 8 tile marching a chunk of levels; each
+  // level's 66 x 10 plane tile (after physics) staged in a 4-deep LDS ring
+  __shared__ double sp[4][RW_TH][RW_TW];
   const int ntile = a.tiles_x * a.tiles_y;
   const int L = xcd_remap(blockIdx.x, nint);
   const int chunk = L / ntile, t = L % ntile;
@@ -120,26 +123,26 @@ __global__ __launch_bounds__(RW_BX *RW_BY) void k_rw_step(RwArgs a) {
   const int k0 = chunk * a.kchunk, k1 = min(nz, k0 + a.kchunk);
   const double *__restrict__ E = a.e;
   double *__restrict__ OUT = a.out;
-  // this thread's share of the plane tile: elements tid and tid + 256 of 396
-  unsigned goff[2];
-  bool gok[2];
+  // this thread's share of the plane tile: elements tid, tid + RW_NT, ...
+  unsigned goff[RW_NLOAD];
+  bool gok[RW_NLOAD];
 #pragma unroll
-  for (int n = 0; n < 2; ++n) {
-    const int e = tid + n * 256;
-    const int gi = i0 - 1 + e % 66, gj = j0 - 1 + e / 66;
-    gok[n] = e < 396 && gi <= nx + 1 && gj <= ny + 1;
+  for (int n = 0; n < RW_NLOAD; ++n) {
+    const int e = tid + n * RW_NT;
+    const int gi = i0 - 1 + e % RW_TW, gj = j0 - 1 + e / RW_TW;
+    gok[n] = e < RW_TN && gi <= nx + 1 && gj <= ny + 1;
     goff[n] = gok[n] ? unsigned(gi) + unsigned(gj) * sj : 0u;
   }
-  double pv[2];
+  double pv[RW_NLOAD];
   auto fetch = [&](int k) {
 #pragma unroll
-    for (int n = 0; n < 2; ++n) pv[n] = gok[n] ? E[unsigned(k) * sk + goff[n]] : 0.0;
+    for (int n = 0; n < RW_NLOAD; ++n) pv[n] = gok[n] ? E[unsigned(k) * sk + goff[n]] : 0.0;
   };
   auto stash = [&](int k) {
 #pragma unroll
-    for (int n = 0; n < 2; ++n) {
-      const int e = tid + n * 256;
-      if (e < 396) sp[k & 3][e / 66][e % 66] = gok[n] ? phys(a, pv[n], k, goff[n]) : 0.0;
+    for (int n = 0; n < RW_NLOAD; ++n) {
+      const int e = tid + n * RW_NT;
+      if (e < RW_TN) sp[k & 3][e / RW_TW][e % RW_TW] = gok[n] ? phys(a, pv[n], k, goff[n]) : 0.0;
     }
   };
   for (int k = (k0 > 0 ? k0 - 1 : k0); k <= k0 + 1 && k < nz; ++k) {
@@ -152,7 +155,7 @@ __global__ __launch_bounds__(RW_BX *RW_BY) void k_rw_step(RwArgs a) {
     const bool more = k + 2 < nz && k + 2 <= k1;
     if (more) fetch(k + 2);
     if (active) {
-      const double (*P)[66] = sp[k & 3];
+      const double (*P)[RW_TW] = sp[k & 3];
       const double pc = P[r][c];
       double sum = P[r][c - 1] + P[r][c + 1];
       sum = sum + P[r - 1][c];
@@ -182,9 +185,9 @@ __global__ __launch_bounds__(RW_BX *RW_BY) void k_rw_step(RwArgs a) {
 // one thread per column (ring included), k marched inside the thread.  The
 // lanes of a wavefront touch addresses nz values apart, so no load
 // coalesces; this kernel exists to measure that cost.
-__global__ __launch_bounds__(RW_BX *RW_BY) void k_rw_step_kij(RwArgs a) {
+__global__ __launch_bounds__(KIJ_BX *KIJ_BY) void k_rw_step_kij(RwArgs a) {
   const int nx = a.nx, ny = a.ny, nz = a.nz;
-  const int i = blockIdx.x * RW_BX + threadIdx.x, j = blockIdx.y * RW_BY + threadIdx.y;
+  const int i = blockIdx.x * KIJ_BX + threadIdx.x, j = blockIdx.y * KIJ_BY + threadIdx.y;
   if (i > nx + 1 || j > ny + 1) return;
   const unsigned sj2 = unsigned(nx + 2);                 // 2D stride of j
   const unsigned si = unsigned(nz), sj = sj2 * unsigned(nz);
@@ -258,8 +261,8 @@ hipError_t launch_rw_step(const double *e, double *out, const double *surf, cons
   a.nchunk = (nz + a.kchunk - 1) / a.kchunk;
   const int ring_cells = (2 * (ny + 2) + 2 * nx) * nz;
   if (kij) {
-    const dim3 grid((nx + 2 + RW_BX - 1) / RW_BX, (ny + 2 + RW_BY - 1) / RW_BY);
-    hipLaunchKernelGGL(k_rw_step_kij, grid, dim3(RW_BX, RW_BY), 0, s, a);
+    const dim3 grid((nx + 2 + KIJ_BX - 1) / KIJ_BX, (ny + 2 + KIJ_BY - 1) / KIJ_BY);
+    hipLaunchKernelGGL(k_rw_step_kij, grid, dim3(KIJ_BX, KIJ_BY), 0, s, a);
     return hipGetLastError();
   }
   const int blocks = a.tiles_x * a.tiles_y * a.nchunk + (ring_cells + RW_BX * RW_BY - 1) / (RW_BX * RW_BY);
