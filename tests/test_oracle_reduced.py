@@ -132,3 +132,64 @@ def test_step_is_physics_then_diffusion_and_rejects_flat_columns():
     np.testing.assert_array_equal(rw.step(e, surf, pbl, NU), rw.diffuse(rw.run_physics(e, surf, pbl), NU))
     with pytest.raises(ValueError):
         rw.diffuse(np.zeros(rw.shape(nx, ny, 1)), NU)
+
+
+def _diffuse_cellwise(e, nu):
+    """The diffusion rules cell by cell in plain Python (the printed loops'
+    order: interior levels, then the bottom and top levels, then the ring
+    rows, then the ring columns, each assignment overwriting earlier ones)."""
+    nz, nyp, nxp = e.shape
+    ny, nx = nyp - 2, nxp - 2
+    out = np.zeros_like(e)
+    for j in range(1, ny + 1):
+        for i in range(1, nx + 1):
+            for k in range(1, nz - 1):
+                s = e[k, j, i - 1] + e[k, j, i + 1]
+                s = s + e[k, j - 1, i]
+                s = s + e[k, j + 1, i]
+                s = s + e[k - 1, j, i]
+                s = s + e[k + 1, j, i]
+                out[k, j, i] = e[k, j, i] * (1.0 - 6.0 * nu) + nu * s
+    for j in range(1, ny + 1):
+        for i in range(1, nx + 1):
+            for k, kv in ((0, 1), (nz - 1, nz - 2)):
+                s = e[k, j, i - 1] + e[k, j, i + 1]
+                s = s + e[k, j - 1, i]
+                s = s + e[k, j + 1, i]
+                s = s + e[kv, j, i]
+                out[k, j, i] = e[k, j, i] * (1.0 - 5.0 * nu) + nu * s
+    for i in range(0, nx + 2):
+        for k in range(nz):
+            out[k, 0, i] = e[k, 0, i] * (1.0 - 2.0 * nu) + nu * (e[k, 1, i] + e[k, ny + 1, i])
+            out[k, ny + 1, i] = e[k, ny + 1, i] * (1.0 - 2.0 * nu) + nu * (e[k, ny, i] + e[k, 0, i])
+    for j in range(0, ny + 2):
+        for k in range(nz):
+            out[k, j, 0] = e[k, j, 0] * (1.0 - 2.0 * nu) + nu * (e[k, j, 1] + e[k, j, nx + 1])
+            out[k, j, nx + 1] = e[k, j, nx + 1] * (1.0 - 2.0 * nu) + nu * (e[k, j, nx] + e[k, j, 0])
+    return out
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(3, 2, 2), (4, 5, 3), (6, 3, 5)])
+def test_diffusion_equals_cell_by_cell_loops_bitwise(nx, ny, nz):
+    # brute force on tiny grids with random values and a non-dyadic nu: the
+    # vectorised oracle equals the cell-by-cell loops to the last bit
+    rng = np.random.default_rng(nx * 100 + ny * 10 + nz)
+    e = rng.uniform(-50.0, 400.0, rw.shape(nx, ny, nz))
+    np.testing.assert_array_equal(rw.diffuse(e, 0.137), _diffuse_cellwise(e, 0.137))
+
+
+def test_physics_equals_column_loops_bitwise():
+    rng = np.random.default_rng(3)
+    nx, ny, nz = 4, 3, 5
+    e = rng.uniform(0.0, 400.0, rw.shape(nx, ny, nz))
+    surf = rng.uniform(280.0, 340.0, (ny + 2, nx + 2))
+    pbl = rng.uniform(180.0, 240.0, (ny + 2, nx + 2))
+    want = e.copy()
+    for j in range(ny + 2):
+        for i in range(nx + 2):
+            col = want[:, j, i]
+            for k in range(nz):
+                col[k] = col[k] + 0.1
+            col[0] = col[0] - 0.01 * (col[0] - surf[j, i])
+            col[nz - 1] = col[nz - 1] - 0.01 * (col[nz - 1] - pbl[j, i])
+    np.testing.assert_array_equal(rw.run_physics(e, surf, pbl), want)
