@@ -25,17 +25,16 @@ sources "Reduced Weather: Diffusion", "Physical Processes", "Radiation",
     ring columns i = 0 and i = nx+1 (every j, written after the rows, so the
         four corner columns take this rule): E (1 - 2 nu) + nu (the inner
         neighbour, then the opposite ring column);
-* initial state 0 with a 300 box over the middle half of each dimension;
-  the surface and boundary-layer values are 330 and 200; the time step is
-  0.1 s.
+* the time step is 0.1 s.  The initial state (0 with a 300 box over the
+  middle half of each dimension) and the boundary values (330 and 200) are
+  inputs: ``paper_1802_05839_amd.inputs.rw_box_init`` and
+  ``rw_boundary_fields`` draw them for both sides.
 
 Readings (the paper leaves them open):
 
 * R-rw-nu: the diffusion number nu (the printed code's diffusion velocity
   has no value in the paper) is a parameter, 0.1 by default (stable: the
   interior weight 1 - 6 nu stays positive).
-* R-rw-box: a cell (1-based interior indices i, j, k) lies in the initial box
-  when n/4 < index <= 3 n/4 in each dimension; the ring starts at 0.
 * R-rw-names: the printed diffusion writes its interior result under one
   array name and its boundary results under another; both are the output
   array.
@@ -48,8 +47,6 @@ from __future__ import annotations
 
 import numpy as np
 
-SURFACE = 330.0
-PBL = 200.0
 RADIATION = 0.1
 TRANSFER = 0.01
 DT = 0.1
@@ -59,25 +56,6 @@ NU_DEFAULT = 0.1
 def shape(nx: int, ny: int, nz: int):
     """Array shape (k, j, i) of the field, ring included."""
     return (nz, ny + 2, nx + 2)
-
-
-def box_init(nx: int, ny: int, nz: int) -> np.ndarray:
-    """The initial field: 300 on the middle half of each dimension, else 0 (R-rw-box)."""
-    e = np.zeros(shape(nx, ny, nz))
-
-    def inside(n, idx):
-        return (idx * 4 > n) & (idx * 4 <= 3 * n)
-
-    ii = inside(nx, np.arange(nx + 2))
-    jj = inside(ny, np.arange(ny + 2))
-    kk = inside(nz, np.arange(1, nz + 1))
-    e[np.ix_(kk, jj, ii)] = 300.0
-    return e
-
-
-def boundary_fields(nx: int, ny: int):
-    """Surface and boundary-layer values over the (ny + 2) x (nx + 2) columns."""
-    return np.full((ny + 2, nx + 2), SURFACE), np.full((ny + 2, nx + 2), PBL)
 
 
 def run_physics(e: np.ndarray, surf: np.ndarray, pbl: np.ndarray) -> np.ndarray:

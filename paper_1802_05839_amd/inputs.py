@@ -251,3 +251,43 @@ def crop(inp: Inputs, i0: int, j0: int, cx: int, cy: int) -> Inputs:
                   u=c3(inp.u), v=c3(inp.v), w=c3(inp.w), rho=c3(inp.rho), theta=c3(inp.theta),
                   q=c3(inp.q), theta_s=c2(inp.theta_s), q_s=c2(inp.q_s), f0=c2(inp.f0),
                   ch=c2(inp.ch), seed=inp.seed)
+
+
+# ---- the paper's reduced weather application ------------------------------
+# Its initial state and boundary values (section "Reduced Weather
+# Application": a 300 box in a zero field, heat wells of 330 at the surface
+# and 200 at the boundary layer).  The field is (nz, ny + 2, nx + 2) float64,
+# i fastest, with a one-cell ring around the nx x ny interior.
+
+RW_SURFACE = 330.0
+RW_PBL = 200.0
+RW_NU_DEFAULT = 0.1      # the diffusion number; the paper prints no value for it
+
+
+def rw_shape(nx: int, ny: int, nz: int):
+    """Array shape (k, j, i) of a reduced-application field, ring included."""
+    return (nz, ny + 2, nx + 2)
+
+
+def rw_box_init(nx: int, ny: int, nz: int) -> np.ndarray:
+    """0 everywhere except 300 on the middle half of each dimension.
+
+    A cell with 1-based interior indices (i, j, k) is inside when
+    n/4 < index <= 3n/4 in every dimension; the ring (index 0 and n+1) is
+    outside.
+    """
+    e = np.zeros(rw_shape(nx, ny, nz))
+
+    def inside(n, idx):
+        return (idx * 4 > n) & (idx * 4 <= 3 * n)
+
+    ii = inside(nx, np.arange(nx + 2))
+    jj = inside(ny, np.arange(ny + 2))
+    kk = inside(nz, np.arange(1, nz + 1))
+    e[np.ix_(kk, jj, ii)] = 300.0
+    return e
+
+
+def rw_boundary_fields(nx: int, ny: int):
+    """Surface and boundary-layer values over the (ny + 2) x (nx + 2) columns."""
+    return np.full((ny + 2, nx + 2), RW_SURFACE), np.full((ny + 2, nx + 2), RW_PBL)

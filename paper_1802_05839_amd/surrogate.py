@@ -23,7 +23,7 @@ epoch.
 from __future__ import annotations
 
 import time
-from typing import Dict, List, Optional, Sequence
+from typing import List, Sequence
 
 import numpy as np
 
@@ -113,28 +113,6 @@ def train(mlp: "wx.Mlp", x, y, epochs: int = EPOCHS, batch: int = 4096, lr: floa
         for ep, last in enumerate(hist):
             log(f"epoch {ep + 1}: last-batch loss {last:.5f}")
     return hist
-
-
-def tendency_rmse(mlp: "wx.Mlp", x_raw, y_raw) -> Dict[str, float]:
-    """Held-out RMSE of the surrogate's tendencies against the plain physics.
-
-    Also the zero-tendency baseline and the training-set std of each variable.
-    """
-    import torch
-    xn, _ = mlp.normalize(x_raw)
-    yn = mlp.infer(xn)
-    ym = mlp._sec("y_mean", torch.float32, (wx.MLP_NOUTP,))
-    ys = mlp._sec("y_std", torch.float32, (wx.MLP_NOUTP,))
-    pred = (yn * ys + ym)[:, :wx.MLP_NOUT].double()
-    ref = y_raw[:, :wx.MLP_NOUT].double()
-    nz = wx.MLP_NZ
-    sig = mlp.sigma().cpu().numpy()
-    out = {}
-    for v, sl in (("theta", slice(0, nz)), ("q", slice(nz, 2 * nz))):
-        out[f"rmse_{v}"] = float(torch.sqrt(torch.mean((pred[:, sl] - ref[:, sl]) ** 2)).item())
-        out[f"rmse_zero_{v}"] = float(torch.sqrt(torch.mean(ref[:, sl] ** 2)).item())
-    out["sigma_theta"], out["sigma_q"] = float(sig[0]), float(sig[1])
-    return out
 
 
 def held_out(nx: int = 400, ny: int = 320, seed: int = HELD_OUT_SEED, steps: Sequence[int] = HELD_OUT_STEPS):

@@ -246,9 +246,11 @@ def test_features_and_targets_match_oracle():
                                  inp.f0, inp.ch, inp.dz, inp.dt)
     ty = omlp.targets(out.t_theta, out.t_q)
     assert np.all(yr[:, NOUT:] == 0)
+    # the FP32 stencil bar of the plain step's tendencies
     for blk in (slice(0, 58), slice(58, 116)):
         e = np.max(np.abs(yr[:, blk] - ty[:, blk])) / np.max(np.abs(ty[:, blk]))
-        assert e <= 1e-4, e
+        _say(f"target block {blk}: normalised max error {e:.3e}")
+        assert e <= 1e-5, e
 
 
 def test_fit_norm_and_normalize_match_oracle():
@@ -283,7 +285,9 @@ def test_fit_norm_and_normalize_match_oracle():
     want = omlp.bf16((x[:, :NIN] - ref.x_mean) / ref.x_std)
     # one BF16 step allowed where FP32 statistics move a value across a rounding
     # boundary; values that cancel to ~0 differ by the FP32 statistics' rounding
-    assert np.all(np.abs(xn[:, :NIN] - want) <= 2.0 ** -7 * np.abs(want) + 1e-5)
+    excess = float(np.max(np.abs(xn[:, :NIN] - want) - 2.0 ** -7 * np.abs(want)))
+    _say(f"normalised features: worst excess over one BF16 step {excess:.3e}")
+    assert excess <= 1e-5
     assert np.mean(xn[:, :NIN] == want) > 0.99
     np.testing.assert_allclose(yo.cpu().numpy()[:, :NOUT], (y[:, :NOUT] - ref.y_mean) / ref.y_std,
                                rtol=1e-5, atol=1e-5)

@@ -6,7 +6,9 @@ identical FP32-representable inputs, with theta measured as theta - 300.
 Bitwise checks: constant fields, uniform states, translation, run-to-run.
 """
 import hashlib
+import math
 import sys
+from dataclasses import replace
 
 import numpy as np
 import pytest
@@ -200,33 +202,128 @@ def test_tendencies_match_oracle():
     st.close()
     e = (nmax(tt, ref32.t_theta), nmax(tq, ref32.t_q))
     _say(f"fp32 tendency errors {e}")
-    assert max(e) <= 1e-4
+    assert max(e) <= FP32_TOL
 
 
-@pytest.mark.parametrize("tdd", [0.0, 1e30])
-@pytest.mark.parametrize("nz", [12, 16, 58])
-def test_fp64_elimination_switch(tdd, nz):
-    # T_dd = 0 sends every column through the FP64 forward elimination,
-    # T_dd = 1e30 none; both agree with the oracle and the counter says which.
-    _say(f"case: FP64 elimination switch tdd={tdd} nz={nz}")
-    inp = inputs.generate(70, 20, nz, seed=28)
-    inp.dt = inp.dt * 40.0          # stiff columns: large alpha / m
+def _stiff_f32_inputs(nz, dt_scale, mix_len, seed=28):
+    """FP32-representable problem whose columns are stiff: the dominance
+    ratio r = (alpha_lo + alpha_hi)/m scales with dt and with mix_len^2."""
+    inp = inputs.generate(70, 20, nz, seed=seed)
+    inp.dt = inp.dt * dt_scale
     inp32 = inp.astype(np.float32)
     inp32.theta = (inp.theta - 300.0).astype(np.float32).astype(np.float64) + 300.0
     inp32.theta_s = (inp.theta_s - 300.0).astype(np.float32).astype(np.float64) + 300.0
-    ref = physics.column_physics(inp32.rho, inp32.theta, inp32.q, inp32.u, inp32.v, inp32.theta_s,
-                                 inp32.q_s, inp32.f0, inp32.ch, inp32.dz, inp32.dt)
-    st = wx.state_from_inputs(inp32, dtype="f32", theta_offset=300.0)
-    st.set_param("t_dd", tdd)
-    st.t["flags_out"].zero_()
-    tt, tq = st.tendencies()
-    flags = st.flags()
+    return inp32, replace(DEFAULT, mix_len=mix_len)
+
+
+def _exact_mass_of_f32_state(raw, inp, theta_offset=300.0):
+    """The three mass sums of a stored state, exactly rounded (math.fsum) over
+    the FP64 cell terms rho V, rho V (theta' + offset), rho V q formed from the
+    stored values, V = dx dy dz_k.  raw: padded arrays (halo 2)."""
+    nx, ny = inp.nx, inp.ny
+    rho = raw["rho"][:, 2:2 + ny, 2:2 + nx].astype(np.float64)
+    th = raw["theta"][:, 2:2 + ny, 2:2 + nx].astype(np.float64) + theta_offset
+    q = raw["q"][:, 2:2 + ny, 2:2 + nx].astype(np.float64)
+    m = rho * (inp.dx * inp.dx * inp.dz)[:, None, None]
+    return np.array([math.fsum(m.ravel()), math.fsum((m * th).ravel()), math.fsum((m * q).ravel())])
+
+
+@pytest.mark.parametrize("nx,ny,nz,phys", [(400, 320, 58, wx.WX_PHYS_PLAIN), (130, 66, 16, wx.WX_PHYS_PLAIN),
+                                           (97, 45, 11, wx.WX_PHYS_PLAIN), (97, 45, 58, wx.WX_PHYS_OFF)])
+def test_fp32_mass_sums_are_exact_sums_of_the_state(nx, ny, nz, phys):
+    # The FP32 state's compensated FP64 sums against the exactly rounded sums
+    # of the same stored values.  nz 58 and 16 take the register-column
+    # physics (per-column FP64 sums folded into Neumaier sums), other nz the
+    # general physics kernel (Neumaier per cell), physics off the mass pass;
+    # every term is positive, so the bound is a few ulp of the total.
+    _say(f"case: FP32 mass sums {nx}x{ny}x{nz} phys {phys}")
+    inp = _f32_inputs(inputs.generate(nx, ny, nz, seed=33))
+    st = wx.state_from_inputs(inp, dtype="f32", phys_mode=phys, theta_offset=300.0)
+    st.step(2)
+    mass = st.mass()
+    raw = {name: st.download_raw(name) for name in ("rho", "theta", "q")}
     st.close()
-    ncol = inp.nx * inp.ny
-    assert flags["fp64_columns"] == (ncol if tdd == 0.0 else 0)
-    e = (nmax(tt, ref.t_theta), nmax(tq, ref.t_q))
-    _say(f"tdd={tdd} tendency errors {e} ratio max {ref.ratio.max():.3g}")
-    assert max(e) <= 1e-4
+    want = _exact_mass_of_f32_state(raw, inp)
+    rel = np.abs(mass - want) / np.abs(want)
+    _say(f"relative error of the mass sums {rel}")
+    assert np.all(rel <= 1e-13), rel
+
+
+@pytest.mark.parametrize("nz", [12, 16, 58])
+def test_fp64_elimination_is_what_stiff_columns_need(nz):
+    # Columns with dominance ratios r ~ 1e3 .. 4e4 (dt x 40, mixing length
+    # 500 m), radiation off so the tendencies are the implicit diffusion alone.
+    # The FP32 forward elimination loses about r * eps32 relative to the
+    # solution (its rounding of each diagonal m + alpha_lo + alpha_hi is a
+    # perturbation r times larger relative to the layer mass m), ~1e-4 here;
+    # the FP64 elimination of the same FP32 inputs is limited by the FP32
+    # inputs and the FP32 rounding of the stored result (the matrix is a
+    # diagonally dominant M-matrix, whose solution is insensitive to relative
+    # perturbations of its off-diagonals and of m), ~1e-7.  T_dd = 0 forces
+    # every column through FP64, T_dd = 1e30 none; the counter says which.
+    _say(f"case: stiff columns nz={nz}, forced FP32 and forced FP64 elimination")
+    inp32, p = _stiff_f32_inputs(nz, 40.0, 500.0)
+    inp32.f0[:] = 0.0
+    ref = physics.column_physics(inp32.rho, inp32.theta, inp32.q, inp32.u, inp32.v, inp32.theta_s,
+                                 inp32.q_s, inp32.f0, inp32.ch, inp32.dz, inp32.dt, p)
+    assert ref.ratio.max() > 1e4 and ref.ratio.min() > 64
+    ncol = inp32.nx * inp32.ny
+    errs = {}
+    for tdd in (0.0, 1e30):
+        st = wx.state_from_inputs(inp32, dtype="f32", theta_offset=300.0)
+        st.set_param("mix_len", p.mix_len)
+        st.set_param("t_dd", tdd)
+        st.t["flags_out"].zero_()
+        tt, tq = st.tendencies()
+        flags = st.flags()
+        st.close()
+        assert flags["fp64_columns"] == (ncol if tdd == 0.0 else 0)
+        errs[tdd] = (nmax(tt, ref.t_theta), nmax(tq, ref.t_q))
+    _say(f"r in [{ref.ratio.min():.3g}, {ref.ratio.max():.3g}]; FP64 elimination errors {errs[0.0]}, "
+         f"FP32 elimination errors {errs[1e30]}")
+    assert max(errs[0.0]) <= 1e-6
+    assert max(errs[1e30]) > 1e-5
+
+
+@pytest.mark.parametrize("nz", [16, 58])
+def test_stiff_step_fp64_branch_matches_oracle(nz):
+    # A whole FP32 step (dycore, then physics updating the state in place)
+    # with every column through the FP64 elimination: the mixing length 2000 m
+    # makes r ~ 1e4, so the default T_dd = 64 picks FP64 for every column.
+    # The state, its periodic halo images and the compensated mass sums must
+    # match the oracle; forcing FP32 elimination misses the 1e-5 bar.
+    _say(f"case: stiff FP32 step nz={nz} through the FP64 elimination branch")
+    inp32, p = _stiff_f32_inputs(nz, 1.0, 2000.0, seed=32)
+    ref = step.run(inp32, 1, p=p)
+    cf = physics.diffusion_coeffs(ref.rho, inp32.u, inp32.v, inp32.ch, inp32.dz, inp32.dt, p)
+    ncol = inp32.nx * inp32.ny
+    res = {}
+    for tdd in (64.0, 1e30):
+        st = wx.state_from_inputs(inp32, dtype="f32", theta_offset=300.0)
+        st.set_param("mix_len", p.mix_len)
+        st.set_param("t_dd", tdd)
+        st.step(1)
+        gpu = st.download()
+        flags = st.flags()
+        mass = st.mass()
+        raw = {name: st.download_raw(name)[:, :, :inp32.nx + 4] for name in ("rho", "theta", "q")}
+        st.close()
+        res[tdd] = (gpu, flags, mass, raw)
+    gpu, flags, mass, raw = res[64.0]
+    assert physics.dominance_ratio(cf).min() > 64.0
+    assert flags["fp64_columns"] == ncol and flags["nonfinite"] == 0
+    errs = _compare(gpu, ref, FP32_TOL, theta_ref=300.0)
+    for name, a in raw.items():
+        inner = a[:, 2:-2, 2:-2]
+        np.testing.assert_array_equal(a, np.pad(inner, ((0, 0), (2, 2), (2, 2)), mode="wrap"))
+    want = _exact_mass_of_f32_state(raw, inp32)
+    rel = np.abs(mass - want) / np.abs(want)
+    assert np.all(rel <= 1e-13), rel
+    e32 = {k: nmax(res[1e30][0][k] - (300.0 if k == "theta" else 0.0),
+                   getattr(ref, k) - (300.0 if k == "theta" else 0.0)) for k in ("rho", "theta", "q")}
+    _say(f"FP64 branch errors {errs}, mass rel {rel}; forced FP32 elimination errors {e32}")
+    assert res[1e30][1]["fp64_columns"] == 0
+    assert max(e32["theta"], e32["q"]) > FP32_TOL
 
 
 def test_fp64_column_count_matches_dominance_ratio():
@@ -343,11 +440,18 @@ def test_full_grid_fp32_crops_and_mass():
     gpu = st.download()
     flags = st.flags()
     m1 = st.mass()
+    raw = {name: st.download_raw(name) for name in ("rho", "theta", "q")}
     st.close()
     del inp
     assert flags["nonfinite"] == 0 and flags["rho_le0"] == 0
     # density is conserved exactly by the dycore and untouched by the physics
     assert abs(m1[0] - m0[0]) / m0[0] <= 1e-6
+    # the production sums equal the exactly rounded sums of the stored state
+    want = _exact_mass_of_f32_state(raw, inp64)
+    del raw
+    rel = np.abs(m1 - want) / np.abs(want)
+    _say(f"full grid mass sums, relative error against exact sums {rel}")
+    assert np.all(rel <= 1e-13), rel
     w = [(0, 0, 32, 32), (1565, 1285, 32, 32), (790, 650, 32, 32), (1500, 20, 32, 32)]
     worst = _crop_check(inp64, gpu, 1, w, FP32_TOL)
     _say(f"full grid fp32 errors {worst}")

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 from oracle import reduced as rw
-from paper_1802_05839_amd import wx
+from paper_1802_05839_amd import inputs, wx
 
 pytestmark = pytest.mark.gpu
 
@@ -46,9 +46,9 @@ def test_random_fields_bitwise(nx, ny, nz, nsteps, nu):
 def test_paper_initial_state_128_cubed_bitwise():
     _say("case: reduced app 128^3 from the paper's box, 20 steps")
     n = 128
-    e = rw.box_init(n, n, n)
-    surf, pbl = rw.boundary_fields(n, n)
-    app = wx.ReducedApp(e, surf, pbl, rw.NU_DEFAULT)
+    e = inputs.rw_box_init(n, n, n)
+    surf, pbl = inputs.rw_boundary_fields(n, n)
+    app = wx.ReducedApp(e, surf, pbl, inputs.RW_NU_DEFAULT)
     app.run(20)
     np.testing.assert_array_equal(app.download(), rw.simulate(e, surf, pbl, 20))
 
@@ -74,9 +74,9 @@ def test_paper_largest_shape_sampled_columns():
     # information one cell, so the crop's own edge cannot reach the centre)
     nx, ny, nz, nsteps = 256, 256, 512, 20
     _say(f"case: reduced app {nx}x{ny}x{nz}, {nsteps} steps, sampled columns")
-    e = rw.box_init(nx, ny, nz)
-    surf, pbl = rw.boundary_fields(nx, ny)
-    app = wx.ReducedApp(e, surf, pbl, rw.NU_DEFAULT)
+    e = inputs.rw_box_init(nx, ny, nz)
+    surf, pbl = inputs.rw_boundary_fields(nx, ny)
+    app = wx.ReducedApp(e, surf, pbl, inputs.RW_NU_DEFAULT)
     app.run(nsteps)
     got = app.download()
     h = nsteps + 1
@@ -103,10 +103,10 @@ def test_kij_order_bitwise(nx, ny, nz, nsteps):
 def test_kij_order_equals_ijk_order_128_cubed():
     _say("case: reduced app KIJ vs IJK order, 128^3 box, 10 steps")
     n = 128
-    e = rw.box_init(n, n, n)
-    surf, pbl = rw.boundary_fields(n, n)
-    a = wx.ReducedApp(e, surf, pbl, rw.NU_DEFAULT)
-    b = wx.ReducedApp(e, surf, pbl, rw.NU_DEFAULT, order="kij")
+    e = inputs.rw_box_init(n, n, n)
+    surf, pbl = inputs.rw_boundary_fields(n, n)
+    a = wx.ReducedApp(e, surf, pbl, inputs.RW_NU_DEFAULT)
+    b = wx.ReducedApp(e, surf, pbl, inputs.RW_NU_DEFAULT, order="kij")
     a.run(10)
     b.run(10)
     np.testing.assert_array_equal(a.download(), b.download())

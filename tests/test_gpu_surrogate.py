@@ -15,10 +15,19 @@ increments (state after the step minus state after the dycore):
   must agree to
   the forward-pass bar, 1e-3 Frobenius-relative, plus half an FP32 spacing of
   the stored state per value;
-* general winds: the FP32 dycore differs from the FP64 one by up to 1e-5,
-  which moves some normalised inputs across a BF16 rounding boundary (one
-  ulp, 2^-8 relative); the bar is 1e-2 Frobenius-relative (2.5 ulps).
+* general winds: the FP32 dycore differs from the FP64 one by about 1e-6
+  relative, which moves a normalised input across a BF16 rounding boundary
+  (one ulp, 2^-8 relative) with probability ~2e-6 / 2^-8 = 5e-4, i.e. about
+  0.15 of the 294 inputs of a column; one flip moves the column's outputs by
+  ~2^-8 / sqrt(294) = 2e-4 relative, and the hidden activations, rounded to
+  BF16 again, flip in turn with a similar share.  The measured
+  Frobenius-relative increment error is 2-3e-4; the bar is 1e-3.
+* the judge's pooled RMSE over the sampled columns moves by the same
+  relative amount as the network outputs it pools: bar 1e-3 relative.
 """
+
+INCR_TOL = 1e-3
+JUDGE_TOL = 1e-3
 import sys
 
 import numpy as np
@@ -177,7 +186,7 @@ def test_surrogate_step_matches_oracle():
     _say(f"surrogate step: rho {e_rho:.3e}, increments {e_inc}, state "
          f"{nmax(got['theta'] - 300, th - 300):.3e} {nmax(got['q'], q):.3e}")
     assert e_rho <= 1e-5
-    assert max(e_inc) <= 1e-2
+    assert max(e_inc) <= INCR_TOL
 
 
 def test_judged_step_matches_oracle_without_fallback():
@@ -199,9 +208,9 @@ def test_judged_step_matches_oracle_without_fallback():
     assert g_n == int(mask.sum()) and not g_fb and not fb
     # per-column exceedance against the same (never reached) bound
     assert g_ct == 0.0 and g_cq == 0.0
-    assert abs(g_rt - r_t) <= 1e-2 * r_t and abs(g_rq - r_q) <= 1e-2 * r_q
+    assert abs(g_rt - r_t) <= JUDGE_TOL * r_t and abs(g_rq - r_q) <= JUDGE_TOL * r_q
     assert e_rho <= 1e-5
-    assert max(e_inc) <= 1e-2
+    assert max(e_inc) <= INCR_TOL
     # sampled columns carry the plain physics: FP32 stencil bar on their increments
     nz = NZ
     cols = np.flatnonzero(mask)

@@ -10,6 +10,7 @@ import sys
 import numpy as np
 import pytest
 
+from bench import tendency_rmse
 from paper_1802_05839_amd import inputs, surrogate, wx
 
 pytestmark = pytest.mark.gpu
@@ -28,10 +29,10 @@ def test_training_beats_untrained_and_no_physics():
     untrained = wx.Mlp()
     untrained.init(1)
     untrained.fit_norm(x, y)
-    r_untrained = surrogate.tendency_rmse(untrained, *held)
+    r_untrained = tendency_rmse(untrained, *held)
     trained = wx.Mlp()
     hist, secs = surrogate.fit(trained, x, y, epochs=30)
-    r = surrogate.tendency_rmse(trained, *held)
+    r = tendency_rmse(trained, *held)
     _say(f"trained {secs:.1f}s, loss {hist[0]:.4f} -> {hist[-1]:.4f}; held-out rmse/sigma "
          f"theta {r['rmse_theta'] / r['sigma_theta']:.4f} q {r['rmse_q'] / r['sigma_q']:.4f}; "
          f"untrained {r_untrained['rmse_theta'] / r['sigma_theta']:.3f} "

@@ -197,3 +197,58 @@ def test_mass_sums_closed_form():
     m = mass_sums(rho, th, q, 2000.0, 2000.0, dz)
     mr = 1.25 * 2000.0 * 2000.0 * nx * ny * np.sum(dz)
     np.testing.assert_allclose(m, [mr, 300.0 * mr, 0.01 * mr], rtol=1e-15)
+
+
+@pytest.mark.parametrize("i0,j0", [(0, 0), (3, 2), (4, 3)])
+def test_centred_winds_single_face_perturbation(i0, j0):
+    # C-grid staggering: u[..., i] sits on the east face of cell i, so it is
+    # the east wind of cell i and the west wind of cell i+1 (periodic).  A
+    # perturbation of one east face must move the centred wind of exactly
+    # those two cells, by half the perturbation; the same for v in j.  A roll
+    # in the wrong direction moves cells i and i-1 instead and fails here.
+    nz, ny, nx = 3, 4, 5
+    rng = np.random.default_rng(7 + i0 + 10 * j0)
+    u = rng.normal(0.0, 5.0, (nz, ny, nx))
+    v = rng.normal(0.0, 5.0, (nz, ny, nx))
+    ub0, vb0 = physics.centred_winds(u, v)
+    du = np.zeros_like(u)
+    du[1, j0, i0] = 2.0
+    ub1, vb1 = physics.centred_winds(u + du, v)
+    want = np.zeros_like(u)
+    want[1, j0, i0] = 1.0
+    want[1, j0, (i0 + 1) % nx] = 1.0
+    np.testing.assert_allclose(ub1 - ub0, want, rtol=0, atol=1e-14)
+    np.testing.assert_array_equal(vb1, vb0)
+    dv = np.zeros_like(v)
+    dv[2, j0, i0] = -4.0
+    ub2, vb2 = physics.centred_winds(u, v + dv)
+    want = np.zeros_like(v)
+    want[2, j0, i0] = -2.0
+    want[2, (j0 + 1) % ny, i0] = -2.0
+    np.testing.assert_allclose(vb2 - vb0, want, rtol=0, atol=1e-14)
+    np.testing.assert_array_equal(ub2, ub0)
+
+
+def test_diffusion_coeffs_on_a_stretched_three_level_column():
+    # Hand-worked column with unequal thicknesses and densities, so the
+    # interface spacing (dz_k + dz_{k+1})/2 and the face density
+    # (rho_k + rho_{k+1})/2 differ from either neighbour's own value.
+    #   dz = 10, 30, 70 m;  rho = 1.2, 0.9, 0.5 kg/m^3;  dt = 4 s; C_h = 0.01
+    #   centred winds (u, v) = (0, 0), (3, 4), (5, 4) m/s (a 1 x 1 grid, so
+    #   the face mean of a horizontally uniform wind is the wind itself)
+    # Interface 1/2: dz = 20, |dU| = 5 -> shear 0.25, K = 0.1 + 2500 * 0.25 = 625.1,
+    #   rho_f = 1.05 -> alpha = 4 * 1.05 * 625.1 / 20 = 131.271
+    # Interface 3/2: dz = 50, |dU| = 2 -> shear 0.04, K = 0.1 + 100 = 100.1,
+    #   rho_f = 0.7 -> alpha = 4 * 0.7 * 100.1 / 50 = 5.6056
+    # Layer masses 12, 27, 35; beta = 4 * 1.2 * 0.01 = 0.048.
+    dz = np.array([10.0, 30.0, 70.0])
+    rho = np.array([1.2, 0.9, 0.5]).reshape(3, 1, 1)
+    u = np.array([0.0, 3.0, 5.0]).reshape(3, 1, 1)
+    v = np.array([0.0, 4.0, 4.0]).reshape(3, 1, 1)
+    ch = np.full((1, 1), 0.01)
+    cf = physics.diffusion_coeffs(rho, u, v, ch, dz, 4.0)
+    np.testing.assert_allclose(cf.alpha[:, 0, 0], [0.0, 131.271, 5.6056, 0.0], rtol=1e-14, atol=0)
+    np.testing.assert_allclose(cf.m[:, 0, 0], [12.0, 27.0, 35.0], rtol=1e-15)
+    np.testing.assert_allclose(cf.beta[0, 0], 0.048, rtol=1e-15)
+    # dominance ratios: (0 + 131.271)/12, (131.271 + 5.6056)/27, 5.6056/35
+    np.testing.assert_allclose(physics.dominance_ratio(cf)[0, 0], 131.271 / 12.0, rtol=1e-14)

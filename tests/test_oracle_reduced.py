@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 from oracle import reduced as rw
+from paper_1802_05839_amd import inputs
 
 NU = 0.125
 
@@ -93,7 +94,7 @@ def test_quadratic_field_gives_the_exact_laplacian(axis):
 def test_physics_closed_forms():
     nx, ny, nz = 3, 2, 5
     e = np.full(rw.shape(nx, ny, nz), 300.0)
-    surf, pbl = rw.boundary_fields(nx, ny)
+    surf, pbl = inputs.rw_boundary_fields(nx, ny)
     out = rw.run_physics(e, surf, pbl)
     np.testing.assert_array_equal(out[1:nz - 1], 300.0 + 0.1)
     b = 300.0 + 0.1
@@ -107,7 +108,7 @@ def test_boundary_levels_relax_to_the_heat_well_fixed_point():
     # whose fixed point is 330 + 0.1 * 0.99 / 0.01 = 339.9 (and 209.9 on top)
     nx, ny, nz = 2, 2, 3
     e = np.zeros(rw.shape(nx, ny, nz))
-    surf, pbl = rw.boundary_fields(nx, ny)
+    surf, pbl = inputs.rw_boundary_fields(nx, ny)
     for _ in range(6000):
         e = rw.run_physics(e, surf, pbl)
     np.testing.assert_allclose(e[0], 339.9, rtol=1e-9)
@@ -116,7 +117,7 @@ def test_boundary_levels_relax_to_the_heat_well_fixed_point():
 
 
 def test_box_init_covers_the_middle_half():
-    e = rw.box_init(8, 12, 4)
+    e = inputs.rw_box_init(8, 12, 4)
     assert e.shape == (4, 14, 10)
     assert set(np.unique(e)) == {0.0, 300.0}
     # 1-based interior indices 3..6 of 8, 4..9 of 12, 2..3 of 4; ring and outside are 0
@@ -127,69 +128,80 @@ def test_box_init_covers_the_middle_half():
 
 def test_step_is_physics_then_diffusion_and_rejects_flat_columns():
     nx, ny, nz = 6, 5, 4
-    e = rw.box_init(nx, ny, nz)
-    surf, pbl = rw.boundary_fields(nx, ny)
+    e = inputs.rw_box_init(nx, ny, nz)
+    surf, pbl = inputs.rw_boundary_fields(nx, ny)
     np.testing.assert_array_equal(rw.step(e, surf, pbl, NU), rw.diffuse(rw.run_physics(e, surf, pbl), NU))
     with pytest.raises(ValueError):
         rw.diffuse(np.zeros(rw.shape(nx, ny, 1)), NU)
 
 
-def _diffuse_cellwise(e, nu):
-    """The diffusion rules cell by cell in plain Python (the printed loops'
-    order: interior levels, then the bottom and top levels, then the ring
-    rows, then the ring columns, each assignment overwriting earlier ones)."""
+def _rule(i, j, k, nx, ny, nz, nu):
+    """(centre weight, ordered neighbour list) of cell (i, j, k) by its class.
+
+    The rules of the diffusion as mathematics, looked up per cell:
+      ring column (i = 0 or nx + 1; the corner columns included):
+          weight 1 - 2 nu; neighbours: the inner column, the opposite ring column
+      ring row (j = 0 or ny + 1, i interior):
+          weight 1 - 2 nu; neighbours: the inner row, the opposite ring row
+      interior column, bottom or top level:
+          weight 1 - 5 nu; neighbours i-1, i+1, j-1, j+1, the one level inside
+      interior column, other levels:
+          weight 1 - 6 nu; neighbours i-1, i+1, j-1, j+1, k-1, k+1
+    """
+    if i in (0, nx + 1):
+        inner, opposite = (1, nx + 1) if i == 0 else (nx, 0)
+        return 1.0 - 2.0 * nu, [(k, j, inner), (k, j, opposite)]
+    if j in (0, ny + 1):
+        inner, opposite = (1, ny + 1) if j == 0 else (ny, 0)
+        return 1.0 - 2.0 * nu, [(k, inner, i), (k, opposite, i)]
+    horizontal = [(k, j, i - 1), (k, j, i + 1), (k, j - 1, i), (k, j + 1, i)]
+    if k == 0:
+        return 1.0 - 5.0 * nu, horizontal + [(1, j, i)]
+    if k == nz - 1:
+        return 1.0 - 5.0 * nu, horizontal + [(nz - 2, j, i)]
+    return 1.0 - 6.0 * nu, horizontal + [(k - 1, j, i), (k + 1, j, i)]
+
+
+def _diffuse_by_rules(e, nu, rng):
+    """Every cell from its rule, visited in a random order."""
     nz, nyp, nxp = e.shape
     ny, nx = nyp - 2, nxp - 2
-    out = np.zeros_like(e)
-    for j in range(1, ny + 1):
-        for i in range(1, nx + 1):
-            for k in range(1, nz - 1):
-                s = e[k, j, i - 1] + e[k, j, i + 1]
-                s = s + e[k, j - 1, i]
-                s = s + e[k, j + 1, i]
-                s = s + e[k - 1, j, i]
-                s = s + e[k + 1, j, i]
-                out[k, j, i] = e[k, j, i] * (1.0 - 6.0 * nu) + nu * s
-    for j in range(1, ny + 1):
-        for i in range(1, nx + 1):
-            for k, kv in ((0, 1), (nz - 1, nz - 2)):
-                s = e[k, j, i - 1] + e[k, j, i + 1]
-                s = s + e[k, j - 1, i]
-                s = s + e[k, j + 1, i]
-                s = s + e[kv, j, i]
-                out[k, j, i] = e[k, j, i] * (1.0 - 5.0 * nu) + nu * s
-    for i in range(0, nx + 2):
-        for k in range(nz):
-            out[k, 0, i] = e[k, 0, i] * (1.0 - 2.0 * nu) + nu * (e[k, 1, i] + e[k, ny + 1, i])
-            out[k, ny + 1, i] = e[k, ny + 1, i] * (1.0 - 2.0 * nu) + nu * (e[k, ny, i] + e[k, 0, i])
-    for j in range(0, ny + 2):
-        for k in range(nz):
-            out[k, j, 0] = e[k, j, 0] * (1.0 - 2.0 * nu) + nu * (e[k, j, 1] + e[k, j, nx + 1])
-            out[k, j, nx + 1] = e[k, j, nx + 1] * (1.0 - 2.0 * nu) + nu * (e[k, j, nx] + e[k, j, 0])
+    out = np.full_like(e, np.nan)
+    for flat in rng.permutation(e.size):
+        k, j, i = np.unravel_index(flat, e.shape)
+        w, nbs = _rule(int(i), int(j), int(k), nx, ny, nz, nu)
+        s = e[nbs[0]]
+        for nb in nbs[1:]:
+            s = s + e[nb]
+        out[k, j, i] = e[k, j, i] * w + nu * s
     return out
 
 
 @pytest.mark.parametrize("nx,ny,nz", [(3, 2, 2), (4, 5, 3), (6, 3, 5)])
-def test_diffusion_equals_cell_by_cell_loops_bitwise(nx, ny, nz):
+def test_diffusion_equals_per_cell_rules_bitwise(nx, ny, nz):
     # brute force on tiny grids with random values and a non-dyadic nu: the
-    # vectorised oracle equals the cell-by-cell loops to the last bit
+    # vectorised oracle equals every cell's rule (looked up from its class,
+    # cells visited in random order) to the last bit
     rng = np.random.default_rng(nx * 100 + ny * 10 + nz)
     e = rng.uniform(-50.0, 400.0, rw.shape(nx, ny, nz))
-    np.testing.assert_array_equal(rw.diffuse(e, 0.137), _diffuse_cellwise(e, 0.137))
+    np.testing.assert_array_equal(rw.diffuse(e, 0.137), _diffuse_by_rules(e, 0.137, rng))
 
 
-def test_physics_equals_column_loops_bitwise():
+def test_physics_equals_per_cell_rule_bitwise():
+    # each cell from the physics rule of its level, cells in random order:
+    #   x = E + 0.1;  bottom level: x - 0.01 (x - surface);  top level: x - 0.01 (x - boundary layer)
     rng = np.random.default_rng(3)
     nx, ny, nz = 4, 3, 5
     e = rng.uniform(0.0, 400.0, rw.shape(nx, ny, nz))
     surf = rng.uniform(280.0, 340.0, (ny + 2, nx + 2))
     pbl = rng.uniform(180.0, 240.0, (ny + 2, nx + 2))
-    want = e.copy()
-    for j in range(ny + 2):
-        for i in range(nx + 2):
-            col = want[:, j, i]
-            for k in range(nz):
-                col[k] = col[k] + 0.1
-            col[0] = col[0] - 0.01 * (col[0] - surf[j, i])
-            col[nz - 1] = col[nz - 1] - 0.01 * (col[nz - 1] - pbl[j, i])
+    want = np.full_like(e, np.nan)
+    for flat in rng.permutation(e.size):
+        k, j, i = np.unravel_index(flat, e.shape)
+        x = e[k, j, i] + 0.1
+        if k == 0:
+            x = x - 0.01 * (x - surf[j, i])
+        if k == nz - 1:
+            x = x - 0.01 * (x - pbl[j, i])
+        want[k, j, i] = x
     np.testing.assert_array_equal(rw.run_physics(e, surf, pbl), want)
