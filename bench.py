@@ -385,6 +385,106 @@ def reduced_app_leg(stream, steps: int = 100):
     return res
 
 
+def ablation_leg(host_inp, stream, steps: int = 10):
+    """Stage-kernel tile shapes and physics-kernel variants on the benchmark
+    grid (the MI355X analogue of the paper's block-size table): average launch
+    time of each stage and of the physics per variant, from wx_profile_step
+    (HIP events on the launch stream).  Every variant gives the same bytes."""
+    from paper_1802_05839_amd import wx
+
+    ncells = host_inp.nx * host_inp.ny * host_inp.nz
+    out = {"grid": f"{host_inp.nx}x{host_inp.ny}x{host_inp.nz} FP32", "steps_profiled": steps, "stage_tiles": {},
+           "physics_kernels": {}}
+    shapes = {0: "64x8", 1: "64x4", 2: "64x12", 3: "32x16", 4: "128x4", 5: "64x8 shared faces"}
+    st = wx.state_from_inputs(host_inp, dtype="f32", theta_offset=300.0)
+    for tile, name in shapes.items():
+        st.set_param("stage_tile", tile)
+        st.step(1)
+        prof = st.profile(steps, stream).tolist()
+        d1, d2, d3 = prof[1:4]
+        gbs = sum(VALUES_STAGE.values()) * 4 * ncells / ((d1 + d2 + d3) / 1e3) / 1e9
+        out["stage_tiles"][name] = {"stage1_ms": round(d1, 4), "stage2_ms": round(d2, 4), "stage3_ms": round(d3, 4),
+                                    "algorithmic_GBs": round(gbs, 1)}
+        log(f"stage tile {name}: {out['stage_tiles'][name]}")
+    st.set_param("stage_tile", 0)
+    for var, name in ((0, "column in registers, 1 wave/SIMD"), (1, "column re-read, 2 waves/SIMD")):
+        st.set_param("phys_kernel", var)
+        st.step(1)
+        d = st.profile(steps, stream).tolist()[4]
+        out["physics_kernels"][name] = {"ms": round(d, 4),
+                                        "algorithmic_GBs": round(VALUES_PHYSICS * 4 * ncells / (d / 1e3) / 1e9, 1)}
+        log(f"physics kernel {name}: {out['physics_kernels'][name]}")
+    st.close()
+    return out
+
+
+def rw_block_leg(stream, steps: int = 100):
+    """The reduced application's thread-block sweep at the paper's three
+    shapes (its table "Block Size Impact on Execution Time" compares the
+    compiler's default 128 x 1 with 32 x 16)."""
+    import torch
+
+    from paper_1802_05839_amd import inputs, wx
+
+    res = {}
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    for (nx, ny, nz) in PAPER_RW_K20X_S:
+        e = inputs.rw_box_init(nx, ny, nz)
+        surf, pbl = inputs.rw_boundary_fields(nx, ny)
+        row = {}
+        for blk in ((64, 8), (32, 16), (128, 1), (64, 4), (128, 4)):
+            app = wx.ReducedApp(e, surf, pbl, inputs.RW_NU_DEFAULT, block=blk)
+            app.run(5, stream)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            app.run(steps, stream)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            row[f"{blk[0]}x{blk[1]}"] = round(ev0.elapsed_time(ev1) * 100 / steps, 3)
+            del app
+        res[f"{nx}x{ny}x{nz}"] = {"ms_per_100_steps": row}
+        log(f"reduced app blocks {nx}x{ny}x{nz}: {row}")
+    res["paper_k20x_s_per_100_steps"] = {"automatic (128x1)": [0.095, 0.63, 2.99], "32x16": [0.10, 0.55, 2.16]}
+    return res
+
+
+# HEVI short step: algorithmic values per cell.  The first stage reads u, v,
+# w, b, pi and writes its pi; the second reads the same five and the first
+# stage's pi and writes u, v, w, b, pi.
+VALUES_HEVI = 6 + 11
+
+
+def hevi_leg(nx: int, ny: int, nz: int, stream, steps: int = 50):
+    """Fast-mode (HEVI) short steps at the benchmark grid, FP32: time per short
+    step and the HBM roofline of its two launches."""
+    import torch
+
+    from paper_1802_05839_amd import inputs, wx
+
+    f = inputs.hevi_fields(nx, ny, nz, seed=2).astype(np.float32)
+    hv = wx.Hevi(f, inputs.HEVI_TAU_DEFAULT, dtype="f32")
+    del f
+    hv.run(4, stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    hv.run(steps, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    ncells = nx * ny * nz
+    gbs = VALUES_HEVI * 4 * ncells / (ms / 1e3) / 1e9
+    del hv
+    return {"workload": f"HEVI short step {nx}x{ny}x{nz} FP32 (two stages, vertical tridiagonal solve per column)",
+            "steps": steps, "ms_per_short_step": round(ms, 4),
+            "Mcell_steps_per_s": round(ncells / (ms / 1e3) / 1e6, 1),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "algorithmic_bytes_per_cell": VALUES_HEVI * 4}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -398,6 +498,10 @@ def main() -> int:
     ap.add_argument("--train-epochs", type=int, default=120)
     ap.add_argument("--coupled-steps", type=int, default=500)
     ap.add_argument("--no-reduced", action="store_true")
+    ap.add_argument("--no-hevi", action="store_true")
+    ap.add_argument("--ablation", action="store_true",
+                    help="also sweep the stage-kernel tiles, the physics kernels and the reduced application's "
+                         "thread blocks")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -493,6 +597,14 @@ def main() -> int:
         "flags": flags,
         "mass": [float(x) for x in mass],
     }
+    if not args.no_hevi:
+        log("HEVI fast-mode short steps")
+        out["hevi"] = hevi_leg(nx, ny, nz, stream)
+        log(f"hevi: {out['hevi']}")
+    if args.ablation:
+        out["ablation"] = ablation_leg(inp, stream)
+        if not args.no_reduced:
+            out["ablation"]["reduced_app_blocks"] = rw_block_leg(stream)
     if not args.no_surrogate and nz == 58:
         out["surrogate"] = surrogate_leg(args, inp, stream)
     if not args.no_reduced:

@@ -90,7 +90,16 @@ typedef enum wx_param {
                                 fixed once the surrogate workspace is sized [100] */
   WX_PARAM_STEP = 11,        /* index t of the next step (sample hash), integer
                                 >= 0; wx_step advances it by nsteps [0]          */
-  WX_PARAM_COUNT = 12
+  WX_PARAM_PHYS_KERNEL = 12, /* kernel of the FP32 physics at nz 16 and 58, same
+                                arithmetic: 0 column kept in registers (one wave
+                                per SIMD), 1 column read again on the way down
+                                (two waves per SIMD) [0]                         */
+  WX_PARAM_STAGE_TILE = 13,  /* tile of the RK3 stage kernel (columns x rows), same
+                                results bit for bit: 0 64x8, 1 64x4, 2 64x12,
+                                3 32x16, 4 128x4, 5 64x8 with each face value,
+                                mass flux and Laplacian formed once per tile
+                                in LDS instead of once per adjacent cell [0]     */
+  WX_PARAM_COUNT = 14
 } wx_param;
 
 /* Flags written by wx_step / wx_mass into flags_out[WX_NFLAGS] (cleared at the
@@ -342,6 +351,14 @@ int wx_rw_step(const double *e_in, double *e_out, const double *surf, const doub
  * result (0 when nsteps = 0). */
 int wx_rw_run(double *e0, double *e1, const double *surf, const double *pbl, int nx, int ny, int nz, double nu,
               int nsteps, int *which, void *stream);
+/* wx_rw_run with a chosen thread-block shape block_x x block_y (the paper's
+ * table "Block Size Impact on Execution Time" compares its compiler's
+ * default 128 x 1 with 32 x 16): one of 64x8 (wx_rw_run's), 32x16, 128x1,
+ * 64x4, 128x4, else WX_E_UNSUPPORTED.  Every shape does the same arithmetic
+ * per cell, so results equal wx_rw_run's bit for bit.  Same arguments,
+ * requirements and errors as wx_rw_run otherwise. */
+int wx_rw_run_block(double *e0, double *e1, const double *surf, const double *pbl, int nx, int ny, int nz, double nu,
+                    int nsteps, int *which, int block_x, int block_y, void *stream);
 /* The same steps on the KIJ storage order (section "Performance Portable
  * Storage Order": k fastest, then i, then j; element (i, j, k) at
  * (j (nx+2) + i) nz + k), with one thread per column marching k, the direct
@@ -350,6 +367,69 @@ int wx_rw_run(double *e0, double *e1, const double *surf, const double *pbl, int
  * Same arguments, requirements and errors as wx_rw_run. */
 int wx_rw_run_kij(double *e0, double *e1, const double *surf, const double *pbl, int nx, int ny, int nz, double nu,
                   int nsteps, int *which, void *stream);
+
+/* ======================================================================
+ * Fast modes: HEVI short steps of the linear acoustic-gravity system.
+ *
+ * Section "The ASUCA Weather Prediction Model" splits sound and gravity
+ * waves from the Runge-Kutta long step: they advance in shorter steps of a
+ * second-order Runge-Kutta scheme, horizontally explicit and vertically
+ * implicit (HEVI); section "Hybrid ASUCA Strong Scaling GPU Results" names
+ * them as the costliest module.  The paper prints no equations; this library
+ * reads them as the linearised system about a resting state with kinematic
+ * pressure pi and buoyancy b,
+ *   du/dt = -dpi/dx, dv/dt = -dpi/dy, dw/dt = -dpi/dz + b, db/dt = -N^2 w,
+ *   dpi/dt = -c^2 (du/dx + dv/dy + dw/dz),
+ * on the dycore's C-grid (u on east faces, v on north faces, pi at cell
+ * centres, w and b on the nz + 1 level faces with w = b = 0 at the ground
+ * and lid; vertical differences over dz_k at cells and (dz_{k-1} + dz_k)/2 at
+ * faces).  A short step of length tau is two stages from its start X, with
+ * h = tau/2 and then h = tau, each taking the previous stage's pi in the
+ * horizontal and treating the vertical terms with the trapezoidal rule:
+ *   u' = u - h dpi_prev/dx,  v' = v - h dpi_prev/dy,  D = du'/dx + dv'/dy,
+ *   (1 + h^2 N^2/4) wm - (h^2 c^2/4) d/dz(dwm/dz)
+ *        = w + (h/2)(-dpi/dz + b) + (h^2 c^2/4) dD/dz   (a tridiagonal solve
+ *          per column over the interior faces),
+ *   w' = 2 wm - w,  b' = b - h N^2 wm,  pi' = pi - h c^2 (D + dwm/dz).
+ *
+ * Layout: cell fields (u, v, pi) exactly like wx_state's cell fields (i
+ * fastest, 2-cell halo in i and j, stride_j = roundup(nx + 4, 64)); face
+ * fields (w, b) have nz + 1 planes of the same shape.  All device buffers
+ * belong to the caller.
+ * ====================================================================== */
+
+typedef struct wx_hevi_grid {
+  int32_t nx, ny, nz, dtype;     /* nx, ny >= 4, 2 <= nz <= 1024; WX_F32 / WX_F64     */
+  int64_t stride_j, stride_k;    /* elements, as for wx_state                       */
+  int64_t origin;                /* element offset of interior (0,0,0)              */
+  int64_t cell_elems;            /* elements of one cell field (nz planes)          */
+  int64_t face_elems;            /* elements of one face field (nz + 1 planes)      */
+  double dx;                     /* horizontal spacing [m], dy == dx                */
+  double tau;                    /* short step [s]                                  */
+  double c_sound, n_bv;          /* sound speed [m/s] > 0, buoyancy frequency [1/s] */
+} wx_hevi_grid;
+
+/* Fill *g for the given grid and constants (host only).  WX_E_INVAL on bad
+ * sizes or non-finite / non-positive dx, tau, c (N >= 0). */
+int wx_hevi_grid_init(wx_hevi_grid *g, int nx, int ny, int nz, int dtype, double dx, double tau, double c_sound,
+                      double n_bv);
+
+/* Device workspace wx_hevi_run needs: the two stages' coefficient tables,
+ * the first stage's pi and parked right-hand side, and a second copy of the
+ * five fields for the ping-pong between steps.  0 for a bad grid. */
+size_t wx_hevi_workspace_bytes(const wx_hevi_grid *g);
+
+/* Advance (u, v, w, b, pi) by nsteps >= 0 short steps of length g->tau on
+ * `stream`, in place (after the last step the fields are in the caller's
+ * buffers; the halo rings of u, v and pi are filled at entry and kept
+ * current).  dz: host array of nz level thicknesses > 0 (k = 0 at the
+ * ground).  Two kernel launches per step (the first stage writes only its
+ * pi).  The call uploads the small coefficient tables from host memory and
+ * synchronizes `stream` once for that upload, before any launch; the steps
+ * themselves are asynchronous.  WX_E_INVAL on NULL or
+ * misaligned pointers, bad dz or nsteps < 0, before any device work. */
+int wx_hevi_run(const wx_hevi_grid *g, const double *dz, void *u, void *v, void *w, void *b, void *pi,
+                void *workspace, int nsteps, void *stream);
 
 #ifdef __cplusplus
 }

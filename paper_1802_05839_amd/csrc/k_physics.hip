@@ -270,9 +270,15 @@ __device__ __forceinline__ void block_finish(const PhysArgs<float> *ap, double *
 // hoisting further and running out of registers.  Columns whose dominance
 // ratio exceeds T_dd redo the elimination in FP64 (runtime loop, global
 // scratch).
-template <int NZ, int MODE>
-__global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
-  constexpr int PF = 8;
+//
+// KEEP = false is the variant that does not keep the column in registers: the
+// downward pass reads rho, theta, q again (the same block read them a moment
+// earlier, so they come from the caches, not HBM) through a prefetch ring of
+// its own.  That halves the registers, so two waves share each SIMD and one
+// wave's loads overlap the other's arithmetic.
+template <int NZ, int MODE, bool KEEP>
+__global__ __launch_bounds__(256, KEEP ? 1 : 2) void k_physics_f32(PhysArgs<float> a) {
+  constexpr int PF = KEEP ? 8 : 4;     // levels prefetched ahead (two waves per SIMD need half)
   extern __shared__ float s_c[];          // [NZ][256]
   // the per-level constants, staged once per block: read through LDS they
   // never wait behind the kernel's own global stores (on this target the
@@ -303,26 +309,29 @@ __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
 
     // ---- upward pass: build row k from a one-level look-ahead, eliminate
     float pr[PF], pt[PF], pq[PF], pu[PF], pe[PF], pv[PF], pn[PF];  // prefetch ring, levels k+1 .. k+PF
+    // west and south face winds through shifted (uniform) base pointers, so
+    // that all seven loads of a level share one vector offset
+    const float *uw = plane(a.u, -1), *vs = plane(a.v, -(long long)sj);
     auto fetch_up = [&](int lev, int slot) {
       const unsigned g = g0 + unsigned(lev) * sk;
       pr[slot] = ldg(a.rho, g);
       pt[slot] = ldg(a.th, g);
       pq[slot] = ldg(a.q, g);
-      pu[slot] = ldg(a.u, g - 1);
+      pu[slot] = ldg(uw, g);
       pe[slot] = ldg(a.u, g);
-      pv[slot] = ldg(a.v, g - sj);
+      pv[slot] = ldg(vs, g);
       pn[slot] = ldg(a.v, g);
     };
     float r0 = ldg(a.rho, g0), t0 = ldg(a.th, g0), q0 = ldg(a.q, g0);
-    float ub0 = (ldg(a.u, g0 - 1) + ldg(a.u, g0)) * 0.5f;
-    float vb0 = (ldg(a.v, g0 - sj) + ldg(a.v, g0)) * 0.5f;
+    float ub0 = (ldg(uw, g0) + ldg(a.u, g0)) * 0.5f;
+    float vb0 = (ldg(vs, g0) + ldg(a.v, g0)) * 0.5f;
 #pragma unroll
     for (int l = 1; l <= PF; ++l)
       if (l < NZ) fetch_up(l, l % PF);
     const float beta = dt * r0 * ldg(a.ch, unsigned(col));
     const float ths = ldg(a.th_s, unsigned(col)), qs = ldg(a.q_s, unsigned(col));
     float dtr[NZ], dqr[NZ];
-    float colr[NZ], colt[NZ], colq[NZ];   // the column itself, kept for the downward pass
+    float colr[KEEP ? NZ : 1], colt[KEEP ? NZ : 1], colq[KEEP ? NZ : 1];   // the column itself (KEEP)
     float alo = 0.f, tm1 = t0, qm1 = q0, cpv = 0.f, dtp = 0.f, dqp = 0.f, rmax = 0.f;
 #pragma unroll
     for (int k = 0; k < NZ; ++k) {
@@ -340,9 +349,11 @@ __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
         const float kz = kmin + l2 * (__builtin_amdgcn_sqrtf(du * du + dv * dv) * rdzi);
         ahi = dt * ((r0 + r1) * 0.5f) * kz * rdzi;
       }
-      colr[k] = r0;
-      colt[k] = t0;
-      colq[k] = q0;
+      if (KEEP) {
+        colr[k] = r0;
+        colt[k] = t0;
+        colq[k] = q0;
+      }
       const float m = r0 * s_dz[k];
       float diag = m + alo + ahi;
       float rt = ahi * (t1 - t0) - alo * (t0 - tm1);
@@ -390,9 +401,37 @@ __global__ __launch_bounds__(256) void k_physics_f32(PhysArgs<float> a) {
       // the column's 58 mass terms are summed in plain FP64 (relative error
       // at most 57 ulp) and enter the compensated sums once per column
       double cm = 0.0, cmt = 0.0, cmq = 0.0;
+      // KEEP = false: ring of the next PF levels below (slot of level k is (NZ-1-k) % PF)
+      float dr[KEEP ? 1 : PF], dtt[KEEP ? 1 : PF], dqq_[KEEP ? 1 : PF];
+      if (!KEEP) {
+#pragma unroll
+        for (int l = 0; l < PF; ++l)
+          if (NZ - 1 - l >= 0) {
+            const unsigned g = gd + unsigned(NZ - 1 - l) * sk;
+            dr[l] = ldg(a.rho, g);
+            dtt[l] = ldg(a.th, g);
+            dqq_[l] = ldg(a.q, g);
+          }
+      }
 #pragma unroll
       for (int k = NZ - 1; k >= 0; --k) {
-        const float r = colr[k], t = colt[k], q = colq[k];
+        float r, t, q;
+        if (KEEP) {
+          r = colr[k];
+          t = colt[k];
+          q = colq[k];
+        } else {
+          const int sl = (NZ - 1 - k) % PF;
+          r = dr[sl];
+          t = dtt[sl];
+          q = dqq_[sl];
+          if (k - PF >= 0) {
+            const unsigned g = gd + unsigned(k - PF) * sk;
+            dr[sl] = ldg(a.rho, g);
+            dtt[sl] = ldg(a.th, g);
+            dqq_[sl] = ldg(a.q, g);
+          }
+        }
         const float ck = s_c[k * 256 + tid];
         const float dth = dtr[k] - ck * dtn;
         const float dqq = dqr[k] - ck * dqn;
@@ -603,16 +642,27 @@ hipError_t launch_physics(const PhysArgs<T> &a, hipStream_t s) {
   if constexpr (sizeof(T) == 4) {
     const int nb = phys_reg_blocks(a.g.nx, a.g.ny);
     const dim3 blk(64, 4);
+    const bool keep = a.variant != PHYS_VARIANT_REREAD;
     if (a.g.nz == 58) {
       const size_t lds = 58 * 256 * sizeof(float);
-      if (a.mode == 0) hipLaunchKernelGGL((k_physics_f32<58, 0>), dim3(nb), blk, lds, s, a);
-      else hipLaunchKernelGGL((k_physics_f32<58, 1>), dim3(nb), blk, lds, s, a);
+      if (keep) {
+        if (a.mode == 0) hipLaunchKernelGGL((k_physics_f32<58, 0, true>), dim3(nb), blk, lds, s, a);
+        else hipLaunchKernelGGL((k_physics_f32<58, 1, true>), dim3(nb), blk, lds, s, a);
+      } else {
+        if (a.mode == 0) hipLaunchKernelGGL((k_physics_f32<58, 0, false>), dim3(nb), blk, lds, s, a);
+        else hipLaunchKernelGGL((k_physics_f32<58, 1, false>), dim3(nb), blk, lds, s, a);
+      }
       return hipGetLastError();
     }
     if (a.g.nz == 16) {
       const size_t lds = 16 * 256 * sizeof(float);
-      if (a.mode == 0) hipLaunchKernelGGL((k_physics_f32<16, 0>), dim3(nb), blk, lds, s, a);
-      else hipLaunchKernelGGL((k_physics_f32<16, 1>), dim3(nb), blk, lds, s, a);
+      if (keep) {
+        if (a.mode == 0) hipLaunchKernelGGL((k_physics_f32<16, 0, true>), dim3(nb), blk, lds, s, a);
+        else hipLaunchKernelGGL((k_physics_f32<16, 1, true>), dim3(nb), blk, lds, s, a);
+      } else {
+        if (a.mode == 0) hipLaunchKernelGGL((k_physics_f32<16, 0, false>), dim3(nb), blk, lds, s, a);
+        else hipLaunchKernelGGL((k_physics_f32<16, 1, false>), dim3(nb), blk, lds, s, a);
+      }
       return hipGetLastError();
     }
   }

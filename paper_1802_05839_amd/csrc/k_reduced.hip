@@ -36,9 +36,6 @@
 namespace wx {
 namespace {
 
-constexpr int RW_BX = 64, RW_BY = 8;
-constexpr int RW_TW = RW_BX + 2, RW_TH = RW_BY + 2, RW_TN = RW_TW * RW_TH;   // level tile with its rim
-constexpr int RW_NT = RW_BX * RW_BY, RW_NLOAD = (RW_TN + RW_NT - 1) / RW_NT;
 constexpr int KIJ_BX = 64, KIJ_BY = 4;   // the KIJ kernel's thread block (one thread per column)
 
 struct RwArgs {
@@ -78,7 +75,13 @@ __device__ __forceinline__ void ring_column(int c, int nx, int ny, int &i, int &
   }
 }
 
+// RW_BX x RW_BY thread block: 64 x 8 in production; the paper's 32 x 16 and
+// its compiler's default 128 x 1, and 64 x 4, 128 x 4 are the block-size
+// ablation (same arithmetic per cell, so the same bits).
+template <int RW_BX, int RW_BY>
 __global__ __launch_bounds__(RW_BX *RW_BY) void k_rw_step(RwArgs a) {
+  constexpr int RW_TW = RW_BX + 2, RW_TH = RW_BY + 2, RW_TN = RW_TW * RW_TH;   // level tile with its rim
+  constexpr int RW_NT = RW_BX * RW_BY, RW_NLOAD = (RW_TN + RW_NT - 1) / RW_NT;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const unsigned sj = unsigned(nx + 2), sk = sj * unsigned(ny + 2);
   const double nu = a.nu;
@@ -110,8 +113,8 @@ __global__ __launch_bounds__(RW_BX *RW_BY) void k_rw_step(RwArgs a) {
     return;
   }
 
-  // ---- interior columns: a 64 x 8 tile marching a chunk of levels; each
-  // level's 66 x 10 plane tile (after physics) staged in a 4-deep LDS ring
+  // ---- interior columns: a tile marching a chunk of levels; each level's
+  // plane tile with its one-cell rim (after physics) staged in a 4-deep LDS ring
   __shared__ double sp[4][RW_TH][RW_TW];
   const int ntile = a.tiles_x * a.tiles_y;
   const int L = xcd_remap(blockIdx.x, nint);
@@ -239,8 +242,22 @@ __global__ __launch_bounds__(KIJ_BX *KIJ_BY) void k_rw_step_kij(RwArgs a) {
 
 int rw_chunk(int nz) { return nz < 16 ? nz : 16; }
 
+template <int BX, int BY>
+void launch_rw_shape(RwArgs a, hipStream_t s) {
+  a.tiles_x = (a.nx + BX - 1) / BX;
+  a.tiles_y = (a.ny + BY - 1) / BY;
+  const int ring_cells = (2 * (a.ny + 2) + 2 * a.nx) * a.nz;
+  const int blocks = a.tiles_x * a.tiles_y * a.nchunk + (ring_cells + BX * BY - 1) / (BX * BY);
+  hipLaunchKernelGGL((k_rw_step<BX, BY>), dim3(blocks), dim3(BX, BY), 0, s, a);
+}
+
+bool rw_block_supported(int bx, int by) {
+  return (bx == 64 && by == 8) || (bx == 32 && by == 16) || (bx == 128 && by == 1) || (bx == 64 && by == 4) ||
+         (bx == 128 && by == 4);
+}
+
 hipError_t launch_rw_step(const double *e, double *out, const double *surf, const double *pbl, int nx, int ny,
-                          int nz, double nu, bool kij, hipStream_t s) {
+                          int nz, double nu, bool kij, hipStream_t s, int bx, int by) {
   RwArgs a;
   a.e = e;
   a.out = out;
@@ -250,8 +267,7 @@ hipError_t launch_rw_step(const double *e, double *out, const double *surf, cons
   a.ny = ny;
   a.nz = nz;
   a.kchunk = rw_chunk(nz);
-  a.tiles_x = (nx + RW_BX - 1) / RW_BX;
-  a.tiles_y = (ny + RW_BY - 1) / RW_BY;
+  a.tiles_x = a.tiles_y = 0;
   a.nu = nu;
   // the weights as the printed program forms them: 1 - (n nu), two roundings
   const double n6 = 6.0 * nu, n5 = 5.0 * nu, n2 = 2.0 * nu;
@@ -259,14 +275,17 @@ hipError_t launch_rw_step(const double *e, double *out, const double *surf, cons
   a.c5 = 1.0 - n5;
   a.c2 = 1.0 - n2;
   a.nchunk = (nz + a.kchunk - 1) / a.kchunk;
-  const int ring_cells = (2 * (ny + 2) + 2 * nx) * nz;
   if (kij) {
     const dim3 grid((nx + 2 + KIJ_BX - 1) / KIJ_BX, (ny + 2 + KIJ_BY - 1) / KIJ_BY);
     hipLaunchKernelGGL(k_rw_step_kij, grid, dim3(KIJ_BX, KIJ_BY), 0, s, a);
     return hipGetLastError();
   }
-  const int blocks = a.tiles_x * a.tiles_y * a.nchunk + (ring_cells + RW_BX * RW_BY - 1) / (RW_BX * RW_BY);
-  hipLaunchKernelGGL(k_rw_step, dim3(blocks), dim3(RW_BX, RW_BY), 0, s, a);
+  if (bx == 64 && by == 8) launch_rw_shape<64, 8>(a, s);
+  else if (bx == 32 && by == 16) launch_rw_shape<32, 16>(a, s);
+  else if (bx == 128 && by == 1) launch_rw_shape<128, 1>(a, s);
+  else if (bx == 64 && by == 4) launch_rw_shape<64, 4>(a, s);
+  else if (bx == 128 && by == 4) launch_rw_shape<128, 4>(a, s);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

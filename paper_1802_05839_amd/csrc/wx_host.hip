@@ -36,7 +36,7 @@ int fail(int code, const char *fmt, ...) {
 
 // Default constants (the readings; see wx_param in wx.h).
 const double kDefaults[WX_PARAM_COUNT] = {1.0 / 256.0, 0.1, 50.0, 0.02, 1004.0, 64.0, 0.0, 1.0,
-                                          0.0,         0.05, 100.0, 0.0};
+                                          0.0,         0.05, 100.0, 0.0, 0.0, 0.0};
 
 struct Impl {
   std::vector<double> dz;
@@ -284,10 +284,11 @@ struct Plan {
     a.h = h;
     a.rdx = T(1.0 / s->dx);
     a.k4 = T(im->param[WX_PARAM_GAMMA4] * std::pow(s->dx, 4) / s->dt);
-    a.nbx = wx::stage_tiles_x(s->nx);
-    a.nblocks = a.nbx * wx::stage_tiles_y(s->ny);
+    const int tile = int(im->param[WX_PARAM_STAGE_TILE]);
+    a.nbx = wx::stage_tiles_x(s->nx, tile);
+    a.nblocks = a.nbx * wx::stage_tiles_y(s->ny, tile);
     WX_TRY(tm.begin(n));
-    WX_HIP(wx::launch_stage<T>(a, n, st));
+    WX_HIP(wx::launch_stage<T>(a, n, tile, st));
     return tm.end();
   }
 
@@ -325,6 +326,7 @@ struct Plan {
     a.n_list = nullptr;
     a.list_cap = 0;
     a.run_if = nullptr;
+    a.variant = int(im->param[WX_PARAM_PHYS_KERNEL]);
     return a;
   }
 
@@ -573,6 +575,10 @@ int wx_set_param(wx_state *s, int param, double value) {
   if ((param == WX_PARAM_MASS_EVERY || param == WX_PARAM_JUDGE_SEED || param == WX_PARAM_JUDGE_RATE ||
        param == WX_PARAM_STEP) && value != std::floor(value))
     return fail(WX_E_INVAL, "param %d must be an integer", param);
+  if (param == WX_PARAM_PHYS_KERNEL && value != 0.0 && value != 1.0)
+    return fail(WX_E_INVAL, "physics kernel must be 0 or 1");
+  if (param == WX_PARAM_STAGE_TILE && (value != std::floor(value) || value >= wx::STAGE_TILE_VARIANTS))
+    return fail(WX_E_INVAL, "stage tile must be an integer in 0..%d", wx::STAGE_TILE_VARIANTS - 1);
   if (param == WX_PARAM_JUDGE_SEED && value >= 4294967296.0) return fail(WX_E_INVAL, "judge seed must be < 2^32");
   if (param == WX_PARAM_JUDGE_RATE && (value < 1 || value > 4294967295.0))
     return fail(WX_E_INVAL, "judge rate must be in 1..2^32-1");
@@ -769,13 +775,15 @@ int wx_rw_step(const double *e_in, double *e_out, const double *surf, const doub
 }
 
 static int rw_run(double *e0, double *e1, const double *surf, const double *pbl, int nx, int ny, int nz, double nu,
-                  int nsteps, int *which, bool kij, void *stream) {
+                  int nsteps, int *which, bool kij, void *stream, int bx = 64, int by = 8) {
   if (!which) return fail(WX_E_INVAL, "which is NULL");
   if (nsteps < 0) return fail(WX_E_INVAL, "nsteps must be >= 0");
   if (int rc = rw_check(e0, e1, surf, pbl, nx, ny, nz, nu)) return rc;
+  if (!kij && !wx::rw_block_supported(bx, by))
+    return fail(WX_E_UNSUPPORTED, "block %d x %d is not one of 64x8, 32x16, 128x1, 64x4, 128x4", bx, by);
   double *cur = e0, *nxt = e1;
   for (int n = 0; n < nsteps; ++n) {
-    WX_HIP(wx::launch_rw_step(cur, nxt, surf, pbl, nx, ny, nz, nu, kij, static_cast<hipStream_t>(stream)));
+    WX_HIP(wx::launch_rw_step(cur, nxt, surf, pbl, nx, ny, nz, nu, kij, static_cast<hipStream_t>(stream), bx, by));
     double *t = cur;
     cur = nxt;
     nxt = t;
@@ -787,6 +795,11 @@ static int rw_run(double *e0, double *e1, const double *surf, const double *pbl,
 int wx_rw_run(double *e0, double *e1, const double *surf, const double *pbl, int nx, int ny, int nz, double nu,
               int nsteps, int *which, void *stream) {
   return rw_run(e0, e1, surf, pbl, nx, ny, nz, nu, nsteps, which, false, stream);
+}
+
+int wx_rw_run_block(double *e0, double *e1, const double *surf, const double *pbl, int nx, int ny, int nz, double nu,
+                    int nsteps, int *which, int block_x, int block_y, void *stream) {
+  return rw_run(e0, e1, surf, pbl, nx, ny, nz, nu, nsteps, which, false, stream, block_x, block_y);
 }
 
 int wx_rw_run_kij(double *e0, double *e1, const double *surf, const double *pbl, int nx, int ny, int nz, double nu,

@@ -30,6 +30,16 @@ __device__ __forceinline__ T &ref(T *base, unsigned idx) {
   return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + idx * unsigned(sizeof(T)));
 }
 
+// Address of element `d` (a uniform displacement, possibly negative) from p.
+// Kernels keep every uniform part of an address (level * stride_k, -1, -sj,
+// ...) in the scalar base pointer and only the per-thread part in the 32-bit
+// vector offset, so each load is `global_load v, v_off, s[base]` with a
+// per-thread offset that never changes inside the k loop.
+template <typename T>
+__device__ __forceinline__ T *plane(T *p, long long d) {
+  return p + d;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs; map dispatch index b
 // of n so that XCD x works on the contiguous logical range [x*q + min(x, r),
 // ...), and tiles that share halo rows share one L2.
@@ -78,7 +88,13 @@ struct PhysArgs {
   const int *n_list;
   int list_cap;
   const int *run_if;               // when set, the launch does nothing unless *run_if != 0
+  int variant;                     // FP32 nz 16/58 kernel: PHYS_VARIANT_*
 };
+
+// Variants of the FP32 register-column physics kernel (nz 16 and 58).
+constexpr int PHYS_VARIANT_KEEP = 0;     // column kept in registers, one wave per SIMD
+constexpr int PHYS_VARIANT_REREAD = 1;   // column read again on the way down, two waves per SIMD
+
 
 template <typename T>
 struct MassArgs {
@@ -90,13 +106,36 @@ struct MassArgs {
   double theta_off;
 };
 
+// Per-level coefficients of the HEVI vertical solve for one stage length h:
+// face f (between cells f-1 and f, f >= 1): spacing dzf and 1/dzf, coupling
+// lo = (h^2 c^2 / 4) / (dzf dz_{f-1}), the Thomas factors inv = 1/(diag +
+// lo c'_{f-1}) and c' = -hi inv; cell f: dz and 1/dz.
+template <typename T>
+struct HeviCoef {
+  T dzf, rdzf, lo, inv, cp, dz, rdz, pad;
+};
+
+template <typename T>
+struct HeviArgs {
+  const T *u, *v, *w, *b, *pi;     // stage base (the short step's start)
+  const T *pp;                     // pi of the previous stage (horizontal gradient)
+  T *u_o, *v_o, *w_o, *b_o, *pi_o; // outputs (u, v, w, b only in the second stage)
+  T *e_o;                          // face field parking the eliminated right-hand side
+  const HeviCoef<T> *coef;         // [nz]
+  Geom g;
+  T h, h2, a4, hc2, hn2, dx, rdx;  // h, h/2, h^2 c^2/4, h c^2, h N^2, dx, 1/dx
+};
+
+template <typename T>
+hipError_t launch_hevi_stage(const HeviArgs<T> &a, bool full, hipStream_t s);
+
 constexpr int PHYS_BX = 64;        // columns per physics block (one wave)
 constexpr int PHYS_LDS_NZ_MAX = 80;
 
 template <typename T>
 hipError_t launch_halo(T *const *fields, int nf, int nplanes, const Geom &g, hipStream_t s);
 template <typename T>
-hipError_t launch_stage(const StageArgs<T> &a, int stage, hipStream_t s);
+hipError_t launch_stage(const StageArgs<T> &a, int stage, int tile, hipStream_t s);
 template <typename T>
 hipError_t launch_physics(const PhysArgs<T> &a, hipStream_t s);
 template <typename T>
@@ -106,12 +145,30 @@ hipError_t launch_fill_i32(int *p, int n, int value, hipStream_t s);
 constexpr int TEND_ROW = 128;      // row width of the row-major tendency layout
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 hipError_t launch_rw_step(const double *e, double *out, const double *surf, const double *pbl, int nx, int ny,
-                          int nz, double nu, bool kij, hipStream_t s);
+                          int nz, double nu, bool kij, hipStream_t s, int bx = 64, int by = 8);
+bool rw_block_supported(int bx, int by);
 
-// RK3 stage tile: 64 columns in i (one wave per row) by 8 rows in j.
-constexpr int STAGE_BX = 64, STAGE_BY = 8;
-inline int stage_tiles_x(int nx) { return (nx + STAGE_BX - 1) / STAGE_BX; }
-inline int stage_tiles_y(int ny) { return (ny + STAGE_BY - 1) / STAGE_BY; }
+// RK3 stage tile shapes (columns in i x rows in j).  0 is the production
+// 64 x 8 (one wave per row); 1-4 are the block-shape ablation.
+struct StageShape {
+  int bx, by;
+};
+// 5 is the 64 x 8 kernel that forms each face and Laplacian once per tile.
+constexpr int STAGE_TILE_VARIANTS = 6;
+constexpr int STAGE_TILE_SHARED = 5;
+inline StageShape stage_shape(int tile) {
+  switch (tile) {
+    case 0: return {64, 8};
+    case 1: return {64, 4};
+    case 2: return {64, 12};
+    case 3: return {32, 16};
+    case 4: return {128, 4};
+    case 5: return {64, 8};
+    default: return {0, 0};
+  }
+}
+inline int stage_tiles_x(int nx, int tile) { return (nx + stage_shape(tile).bx - 1) / stage_shape(tile).bx; }
+inline int stage_tiles_y(int ny, int tile) { return (ny + stage_shape(tile).by - 1) / stage_shape(tile).by; }
 inline int phys_blocks(int nx, int ny) { return ((nx + PHYS_BX - 1) / PHYS_BX) * ny; }
 inline int phys_reg_blocks(int nx, int ny) { return ((nx + 63) / 64) * ((ny + 3) / 4); }
 // physics kernel variant for a state: register-resident columns for FP32 and these level counts

@@ -291,3 +291,53 @@ def rw_box_init(nx: int, ny: int, nz: int) -> np.ndarray:
 def rw_boundary_fields(nx: int, ny: int):
     """Surface and boundary-layer values over the (ny + 2) x (nx + 2) columns."""
     return np.full((ny + 2, nx + 2), RW_SURFACE), np.full((ny + 2, nx + 2), RW_PBL)
+
+
+# ---- fast modes (HEVI short steps) ----------------------------------------
+# Perturbation fields of the linear acoustic-gravity system about a resting
+# state: u, v at east / north faces and pi at cell centres (nz, ny, nx); w and
+# b on the nz + 1 level faces, zero at the ground and lid.  White noise plus a
+# smooth large-scale part, so that both the grid-scale and the long waves are
+# present:  u, v ~ N(0, 1) m/s + 2 m/s modes;  w ~ N(0, 0.05) m/s;
+# b ~ N(0, 0.005) m/s^2;  pi ~ N(0, 5) m^2/s^2 + a 20 m^2/s^2 mode.  Stream ids
+# 11-15.  The short step defaults to 2 s, a horizontal sound Courant number
+# c tau / dx = 0.34 at 2 km.
+
+HEVI_TAU_DEFAULT = 2.0
+HEVI_C_SOUND = 340.0
+HEVI_N_BV = 0.01
+
+
+@dataclasses.dataclass
+class FastFields:
+    u: np.ndarray
+    v: np.ndarray
+    w: np.ndarray
+    b: np.ndarray
+    pi: np.ndarray
+    dz: np.ndarray
+    dx: float
+
+    def astype(self, dtype) -> "FastFields":
+        """Values rounded to ``dtype`` (stored back as float64)."""
+        c = lambda a: a.astype(dtype).astype(np.float64)  # noqa: E731
+        return FastFields(c(self.u), c(self.v), c(self.w), c(self.b), c(self.pi), self.dz.copy(), self.dx)
+
+
+def hevi_fields(nx: int, ny: int, nz: int, seed: int = 0, dx: float = DX_DEFAULT,
+                dz: Optional[np.ndarray] = None) -> FastFields:
+    dz = stretched_dz(nz) if dz is None else np.asarray(dz, dtype=np.float64)
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    ph = _rng(seed, 15).uniform(0.0, 2.0 * np.pi, 3)
+    mode = np.sin(2.0 * np.pi * x[None, :] + ph[0]) * np.cos(2.0 * np.pi * y[:, None] + ph[1])
+    zc = level_centres(dz)
+    vert = np.cos(np.pi * zc / (np.sum(dz)))[:, None, None]
+    u = _rng(seed, 11).normal(0.0, 1.0, (nz, ny, nx)) + 2.0 * vert * mode[None]
+    v = _rng(seed, 12).normal(0.0, 1.0, (nz, ny, nx)) - 2.0 * vert * mode[None]
+    w = np.zeros((nz + 1, ny, nx))
+    w[1:nz] = _rng(seed, 13).normal(0.0, 0.05, (nz - 1, ny, nx))
+    b = np.zeros((nz + 1, ny, nx))
+    b[1:nz] = _rng(seed, 14).normal(0.0, 0.005, (nz - 1, ny, nx))
+    pi = _rng(seed, 15).normal(0.0, 5.0, (nz, ny, nx)) + 20.0 * vert * mode[None]
+    return FastFields(u, v, w, b, pi, dz, dx)

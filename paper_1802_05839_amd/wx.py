@@ -24,7 +24,7 @@ PROFILE_CLASSES = ("halo", "stage1", "stage2", "stage3", "physics", "mass_final"
                    "surrogate", "sampled_apply")
 PARAMS = {"gamma4": 0, "k_min": 1, "mix_len": 2, "kappa_q": 3, "cp": 4, "t_dd": 5,
           "theta_offset": 6, "mass_every": 7, "judge_seed": 8, "judge_rel": 9, "judge_rate": 10,
-          "step": 11}
+          "step": 11, "phys_kernel": 12, "stage_tile": 13}
 FLAG_NAMES = ("nonfinite", "rho_le0", "fp64_columns", "fallback_steps")
 HALO = 2
 
@@ -34,7 +34,8 @@ EXPORTS = ("wx_create", "wx_destroy", "wx_last_error", "wx_workspace_bytes", "wx
            "wx_mlp_init", "wx_mlp_refresh", "wx_mlp_norm_scratch_bytes", "wx_mlp_fit_norm",
            "wx_mlp_normalize", "wx_mlp_work_bytes", "wx_mlp_forward_backward", "wx_mlp_adam",
            "wx_mlp_train_step", "wx_mlp_infer_work_bytes", "wx_mlp_infer",
-           "wx_surrogate_work_bytes", "wx_rw_step", "wx_rw_run", "wx_rw_run_kij")
+           "wx_surrogate_work_bytes", "wx_rw_step", "wx_rw_run", "wx_rw_run_kij",
+           "wx_rw_run_block", "wx_hevi_grid_init", "wx_hevi_workspace_bytes", "wx_hevi_run")
 
 # surrogate network shapes and blob sections (include/wx.h)
 MLP_NZ, MLP_NIN, MLP_KIN, MLP_NHID, MLP_NOUT, MLP_NOUTP = 58, 294, 320, 512, 116, 128
@@ -73,6 +74,16 @@ class _State(ctypes.Structure):
 
 class _Tend(ctypes.Structure):
     _fields_ = [("dtheta", ctypes.c_void_p), ("dq", ctypes.c_void_p)]
+
+
+class _HeviGrid(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("stride_j", ctypes.c_int64), ("stride_k", ctypes.c_int64), ("origin", ctypes.c_int64),
+        ("cell_elems", ctypes.c_int64), ("face_elems", ctypes.c_int64),
+        ("dx", ctypes.c_double), ("tau", ctypes.c_double), ("c_sound", ctypes.c_double),
+        ("n_bv", ctypes.c_double),
+    ]
 
 
 _lib = None
@@ -128,8 +139,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.wx_rw_step.argtypes = [vp, vp, vp, vp, i32, i32, i32, dbl, vp]
     lib.wx_rw_run.argtypes = [vp, vp, vp, vp, i32, i32, i32, dbl, i32, ctypes.POINTER(i32), vp]
     lib.wx_rw_run_kij.argtypes = [vp, vp, vp, vp, i32, i32, i32, dbl, i32, ctypes.POINTER(i32), vp]
+    lib.wx_rw_run_block.argtypes = [vp, vp, vp, vp, i32, i32, i32, dbl, i32, ctypes.POINTER(i32), i32, i32, vp]
+    hg = ctypes.POINTER(_HeviGrid)
+    lib.wx_hevi_grid_init.argtypes = [hg, i32, i32, i32, i32, dbl, dbl, dbl, dbl]
+    lib.wx_hevi_workspace_bytes.argtypes = [hg]
+    lib.wx_hevi_run.argtypes = [hg, ctypes.POINTER(dbl), vp, vp, vp, vp, vp, vp, i32, vp]
     size_returning = {"wx_workspace_bytes", "wx_mlp_bytes", "wx_mlp_norm_scratch_bytes",
-                      "wx_mlp_work_bytes", "wx_mlp_infer_work_bytes", "wx_surrogate_work_bytes"}
+                      "wx_mlp_work_bytes", "wx_mlp_infer_work_bytes", "wx_surrogate_work_bytes",
+                      "wx_hevi_workspace_bytes"}
     for name in EXPORTS[4:]:
         if name in size_returning:
             getattr(lib, name).restype = ctypes.c_size_t
@@ -526,12 +543,16 @@ class ReducedApp:
     and runs wx_rw_run_kij; upload and download reorder it.
     """
 
-    def __init__(self, e, surf, pbl, nu: float, device: str = "cuda:0", order: str = "ijk"):
+    def __init__(self, e, surf, pbl, nu: float, device: str = "cuda:0", order: str = "ijk",
+                 block=None):
         torch = _torch()
         if order not in ("ijk", "kij"):
             raise WxError(f"unknown storage order {order!r}")
+        if block is not None and order != "ijk":
+            raise WxError("the thread-block shape applies to the IJK order")
         self.lib = load_library()
         self.order = order
+        self.block = None if block is None else (int(block[0]), int(block[1]))
         self.nz, nyp, nxp = e.shape
         self.ny, self.nx = nyp - 2, nxp - 2
         self.nu = float(nu)
@@ -544,10 +565,15 @@ class ReducedApp:
 
     def run(self, nsteps: int, stream=None) -> None:
         which = ctypes.c_int(0)
-        fn = self.lib.wx_rw_run if self.order == "ijk" else self.lib.wx_rw_run_kij
-        _check(fn(self.buf[self.cur].data_ptr(), self.buf[1 - self.cur].data_ptr(),
-                  self.surf.data_ptr(), self.pbl.data_ptr(), self.nx, self.ny, self.nz,
-                  self.nu, int(nsteps), ctypes.byref(which), _stream_ptr(stream)), "wx_rw_run")
+        args = (self.buf[self.cur].data_ptr(), self.buf[1 - self.cur].data_ptr(),
+                self.surf.data_ptr(), self.pbl.data_ptr(), self.nx, self.ny, self.nz,
+                self.nu, int(nsteps), ctypes.byref(which))
+        if self.block is not None:
+            _check(self.lib.wx_rw_run_block(*args, self.block[0], self.block[1], _stream_ptr(stream)),
+                   "wx_rw_run_block")
+        else:
+            fn = self.lib.wx_rw_run if self.order == "ijk" else self.lib.wx_rw_run_kij
+            _check(fn(*args, _stream_ptr(stream)), "wx_rw_run")
         self.cur = self.cur if which.value == 0 else 1 - self.cur
 
     def step_into(self, stream=None) -> None:
@@ -570,3 +596,62 @@ class ReducedApp:
         f = self.field.cpu().numpy()
         return f if self.order == "ijk" else np.ascontiguousarray(np.transpose(f, (2, 0, 1)))
 
+
+
+class Hevi:
+    """Fast-mode (HEVI) fields on the GPU, advanced by wx_hevi_run (buffers owned here).
+
+    ``f`` is an ``inputs.FastFields`` (u, v, pi of shape (nz, ny, nx); w, b of
+    shape (nz + 1, ny, nx)); ``run`` advances it by short steps of ``tau``.
+    """
+
+    CELL = ("u", "v", "pi")
+    FACE = ("w", "b")
+
+    def __init__(self, f, tau: float, dtype: str = "f64", c_sound: float = 340.0, n_bv: float = 0.01,
+                 device: str = "cuda:0"):
+        torch = _torch()
+        self.lib = load_library()
+        nz, ny, nx = f.pi.shape
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.g = _HeviGrid()
+        _check(self.lib.wx_hevi_grid_init(ctypes.byref(self.g), nx, ny, nz, WX_F32 if dtype == "f32" else WX_F64,
+                                          float(f.dx), float(tau), float(c_sound), float(n_bv)),
+               "wx_hevi_grid_init")
+        self.dz = np.ascontiguousarray(f.dz, dtype=np.float64)
+        self.sj = int(self.g.stride_j)
+        self.tdt = torch.float32 if dtype == "f32" else torch.float64
+        self.np_dtype = np.float32 if dtype == "f32" else np.float64
+        self.device = torch.device(device)
+        self.t = {}
+        for name in self.CELL:
+            self.t[name] = torch.zeros(int(self.g.cell_elems), dtype=self.tdt, device=self.device)
+        for name in self.FACE:
+            self.t[name] = torch.zeros(int(self.g.face_elems), dtype=self.tdt, device=self.device)
+        self.ws = torch.zeros(int(self.lib.wx_hevi_workspace_bytes(ctypes.byref(self.g))), dtype=torch.uint8,
+                              device=self.device)
+        for name in self.CELL + self.FACE:
+            self.interior(name).copy_(torch.from_numpy(np.ascontiguousarray(getattr(f, name),
+                                                                            dtype=self.np_dtype)))
+
+    def interior(self, name: str):
+        planes = self.nz + 1 if name in self.FACE else self.nz
+        return self.t[name].view(planes, self.ny + 2 * HALO, self.sj)[:, HALO:HALO + self.ny, HALO:HALO + self.nx]
+
+    def run(self, nsteps: int, stream=None) -> None:
+        t = self.t
+        _check(self.lib.wx_hevi_run(ctypes.byref(self.g), self.dz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    t["u"].data_ptr(), t["v"].data_ptr(), t["w"].data_ptr(), t["b"].data_ptr(),
+                                    t["pi"].data_ptr(), self.ws.data_ptr(), int(nsteps), _stream_ptr(stream)),
+               "wx_hevi_run")
+
+    def download(self) -> Dict[str, np.ndarray]:
+        torch = _torch()
+        torch.cuda.synchronize(self.device)
+        return {name: self.interior(name).cpu().numpy().astype(np.float64) for name in self.CELL + self.FACE}
+
+    def download_raw(self, name: str) -> np.ndarray:
+        torch = _torch()
+        torch.cuda.synchronize(self.device)
+        planes = self.nz + 1 if name in self.FACE else self.nz
+        return self.t[name].view(planes, self.ny + 2 * HALO, self.sj).cpu().numpy()

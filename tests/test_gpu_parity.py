@@ -455,3 +455,73 @@ def test_full_grid_fp32_crops_and_mass():
     w = [(0, 0, 32, 32), (1565, 1285, 32, 32), (790, 650, 32, 32), (1500, 20, 32, 32)]
     worst = _crop_check(inp64, gpu, 1, w, FP32_TOL)
     _say(f"full grid fp32 errors {worst}")
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3, 4])
+def test_stage_tile_shapes_bitwise(tile):
+    # the stage kernel's tile-shape ablation: each cell's arithmetic does not
+    # depend on the tile, so every shape gives the production tile's bytes
+    # (ragged tiles in i and j, FP32 and FP64)
+    for dtype, (nx, ny, nz) in (("f32", (150, 37, 12)), ("f64", (67, 29, 7))):
+        _say(f"case: stage tile {tile} vs tile 0, {nx}x{ny}x{nz} {dtype}")
+        inp = inputs.generate(nx, ny, nz, seed=40 + tile)
+        outs = []
+        for t in (0, tile):
+            st = wx.state_from_inputs(inp, dtype=dtype)
+            st.set_param("stage_tile", t)
+            st.step(2)
+            outs.append({n: st.download_raw(n) for n in ("rho", "theta", "q")})
+            outs[-1]["mass"] = st.mass_raw()
+            st.close()
+        for n in ("rho", "theta", "q", "mass"):
+            np.testing.assert_array_equal(outs[0][n], outs[1][n])
+
+
+@pytest.mark.parametrize("nz", [16, 58])
+def test_physics_kernel_variants_bitwise(nz):
+    # the physics kernel that reads the column again on the way down (two
+    # waves per SIMD) does the same arithmetic as the one that keeps it in
+    # registers: same state, mass sums, counters and tendencies
+    _say(f"case: physics kernel variants nz={nz}")
+    inp = _f32_inputs(inputs.generate(130, 21, nz, seed=44))
+    res = []
+    for v in (0, 1):
+        st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
+        st.set_param("phys_kernel", v)
+        tt, tq = st.tendencies()
+        st.step(2)
+        res.append(({n: st.download_raw(n) for n in ("rho", "theta", "q")}, st.mass_raw(), st.flags(), tt, tq))
+        st.close()
+    for n in ("rho", "theta", "q"):
+        np.testing.assert_array_equal(res[0][0][n], res[1][0][n])
+    np.testing.assert_array_equal(res[0][1], res[1][1])
+    assert res[0][2] == res[1][2]
+    np.testing.assert_array_equal(res[0][3], res[1][3])
+    np.testing.assert_array_equal(res[0][4], res[1][4])
+
+
+def test_shared_face_stage_kernel_matches_oracle():
+    # the variant that forms each face, mass flux and Laplacian once per tile
+    # in LDS: the same formulas, but a value read back from LDS is rounded
+    # where the per-cell kernel could fuse its last multiply into the next
+    # add, so it agrees with the oracle at the usual bars rather than with
+    # the per-cell kernel bit for bit; it is reproducible run to run
+    _say("case: shared-face stage kernel, FP64 3 steps ragged, FP32 1 step")
+    inp = inputs.generate(67, 37, 7, seed=45)
+    st = wx.state_from_inputs(inp, dtype="f64")
+    st.set_param("stage_tile", 5)
+    st.step(3)
+    gpu = st.download()
+    st.close()
+    _compare(gpu, _oracle(inp, 3), FP64_TOL)
+    inp32 = _f32_inputs(inputs.generate(150, 37, 12, seed=46))
+    outs = []
+    for _ in range(2):
+        st = wx.state_from_inputs(inp32, dtype="f32", theta_offset=300.0)
+        st.set_param("stage_tile", 5)
+        st.step(1)
+        outs.append((st.download(), st.download_raw("theta")))
+        st.close()
+    errs = _compare(outs[0][0], _oracle(inp32, 1), FP32_TOL, theta_ref=300.0)
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    _say(f"shared-face fp32 errors {errs}")

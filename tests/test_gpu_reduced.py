@@ -110,3 +110,23 @@ def test_kij_order_equals_ijk_order_128_cubed():
     a.run(10)
     b.run(10)
     np.testing.assert_array_equal(a.download(), b.download())
+
+
+@pytest.mark.parametrize("block", [(32, 16), (128, 1), (64, 4), (128, 4)])
+def test_block_shapes_bitwise(block):
+    # the block-size ablation: every shape does the printed arithmetic per
+    # cell, so each equals the oracle bit for bit (ragged tiles in i and j,
+    # two level chunks)
+    _say(f"case: reduced app block {block[0]}x{block[1]}, 70x37x20, 4 steps")
+    e, surf, pbl = _random_case(70, 37, 20, seed=77)
+    app = wx.ReducedApp(e, surf, pbl, 0.1, block=block)
+    app.run(4)
+    np.testing.assert_array_equal(app.download(), rw.simulate(e, surf, pbl, 4, 0.1))
+
+
+def test_unsupported_block_shape_is_rejected():
+    _say("case: reduced app unsupported block shape")
+    e, surf, pbl = _random_case(8, 8, 4, seed=78)
+    app = wx.ReducedApp(e, surf, pbl, 0.1, block=(16, 16))
+    with pytest.raises(wx.WxError, match="not one of"):
+        app.run(1)
