@@ -197,6 +197,24 @@ int wx_physics(wx_state *s, wx_tend *t, int mode);
  * on s->stream; fixed reduction order, so bitwise reproducible. */
 int wx_mass(wx_state *s);
 
+/* Largest ceil(nx/64)*ny that wx_mass_noalloc accepts (its block partials
+ * live in a fixed device array of 6 doubles per block). */
+#define WX_MASS_NOALLOC_MAX_PARTS 40960
+
+/* wx_mass for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and summation order as wx_mass, so bitwise the same mass_out, but
+ * the block partials and level volumes live in a static per-device array of
+ * 8 KiB + WX_MASS_NOALLOC_MAX_PARTS * 48 B (1.9 MiB) that the library keeps
+ * until the process ends; s->workspace is neither needed nor touched.  Needs
+ * rho, theta, q, mass_out and flags_out; grids with ceil(nx/64)*ny above
+ * WX_MASS_NOALLOC_MAX_PARTS (and nz above 1024) are rejected with WX_E_INVAL
+ * before any device work.  Calls no hipMalloc/hipFree.  Every call on one
+ * GPU shares that array: calls that overlap in time on one GPU (two streams,
+ * two host threads) race and must be serialized by the caller.  Runs on
+ * s->stream; adds fault counts to flags_out like wx_mass. */
+int wx_mass_noalloc(wx_state *s);
+
 /* Timing instrument: run nsteps steps like wx_step with a HIP event around
  * every kernel launch (same stream), synchronize, and write the average
  * duration in ms of each launch class to ms_out[0..n_out): 0 halo fill,

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -486,6 +487,75 @@ int run_steps(wx_state *s, int nsteps, hipStream_t st, Timer &tm) {
 
 }  // namespace
 
+// ---- mass sums without any allocation ----------------------------------
+//
+// The block partials and the per-level cell volumes of wx_mass_noalloc live in
+// this file-scope device array instead of the caller's workspace.  Its device
+// address is looked up once per device (hipGetSymbolAddress with that device
+// current) and only that address is handed to kernels.
+namespace {
+
+constexpr int kNoallocMaxNz = 1024;
+constexpr int kNoallocMaxParts = WX_MASS_NOALLOC_MAX_PARTS;
+constexpr int kNoallocMaxDevices = 64;
+__device__ __align__(256) double scratch[kNoallocMaxNz + size_t(kNoallocMaxParts) * 6];
+
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kNoallocMaxDevices] = {nullptr};
+
+// Volumes dx*dy*dz_k for up to 256 levels per launch, passed by value so that
+// no host buffer or copy is involved.
+struct VolChunk {
+  double v[256];
+};
+__global__ void k_put_vol(double *dst, VolChunk c, int n) {
+  const int t = threadIdx.x;
+  if (t < n) dst[t] = c.v[t];
+}
+
+int scratch_ptr(double **out) {
+  int dev = 0;
+  WX_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoallocMaxDevices) return fail(WX_E_UNSUPPORTED, "device index %d >= %d", dev, kNoallocMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    WX_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(WX_E_HIP, "hipGetSymbolAddress returned NULL for the static scratch");
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return WX_OK;
+}
+
+template <typename T>
+int mass_noalloc(wx_state *s, hipStream_t st, double *ws) {
+  double *vol = ws;
+  double *parts = ws + kNoallocMaxNz;
+  const std::vector<double> &dz = impl_of(s)->dz;
+  for (int k0 = 0; k0 < s->nz; k0 += 256) {
+    VolChunk c;
+    const int n = std::min(256, s->nz - k0);
+    for (int k = 0; k < n; ++k) c.v[k] = s->dx * s->dx * dz[k0 + k];
+    hipLaunchKernelGGL(k_put_vol, dim3(1), dim3(256), 0, st, vol + k0, c, n);
+    WX_HIP(hipGetLastError());
+  }
+  wx::MassArgs<T> a;
+  a.rho = static_cast<const T *>(s->rho);
+  a.th = static_cast<const T *>(s->theta);
+  a.q = static_cast<const T *>(s->q);
+  a.vol = vol;
+  a.partials = parts;
+  a.flags = s->flags_out;
+  a.g = geom(s);
+  a.theta_off = impl_of(s)->param[WX_PARAM_THETA_OFFSET];
+  WX_HIP(wx::launch_mass<T>(a, st));
+  WX_HIP(wx::launch_mass_final(parts, wx::phys_blocks(s->nx, s->ny), s->mass_out, st));
+  return WX_OK;
+}
+
+}  // namespace
+
 namespace wx {
 int set_error(int code, const char *msg) {
   g_err = msg;
@@ -805,6 +875,26 @@ int wx_rw_run_block(double *e0, double *e1, const double *surf, const double *pb
 int wx_rw_run_kij(double *e0, double *e1, const double *surf, const double *pbl, int nx, int ny, int nz, double nu,
                   int nsteps, int *which, void *stream) {
   return rw_run(e0, e1, surf, pbl, nx, ny, nz, nu, nsteps, which, true, stream);
+}
+
+int wx_mass_noalloc(wx_state *s) {
+  if (!s || !s->impl) return fail(WX_E_INVAL, "state is NULL");
+  const long long nparts = wx::phys_blocks(s->nx, s->ny);
+  if (nparts > kNoallocMaxParts)
+    return fail(WX_E_INVAL, "grid %d x %d needs %lld mass partials; wx_mass_noalloc holds at most %d "
+                "(ceil(nx/64)*ny <= %d)", s->nx, s->ny, nparts, kNoallocMaxParts, kNoallocMaxParts);
+  if (s->dtype != WX_F32 && s->dtype != WX_F64) return fail(WX_E_INVAL, "dtype %d is not WX_F32/WX_F64", s->dtype);
+  const void *req[] = {s->rho, s->theta, s->q, s->mass_out, s->flags_out};
+  const char *names[] = {"rho", "theta", "q", "mass_out", "flags_out"};
+  for (int n = 0; n < 5; ++n) {
+    if (!req[n]) return fail(WX_E_STATE, "state pointer '%s' is NULL", names[n]);
+    if (!aligned16(req[n])) return fail(WX_E_INVAL, "state pointer '%s' is not 16-byte aligned", names[n]);
+  }
+  double *ws = nullptr;
+  WX_TRY(scratch_ptr(&ws));
+  hipStream_t st = static_cast<hipStream_t>(s->stream);
+  if (s->dtype == WX_F32) return mass_noalloc<float>(s, st, ws);
+  return mass_noalloc<double>(s, st, ws);
 }
 
 int wx_copy_probe(void *dst, const void *src, size_t bytes, void *stream) {

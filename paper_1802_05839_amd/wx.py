@@ -34,7 +34,7 @@ EXPORTS = ("wx_create", "wx_destroy", "wx_last_error", "wx_workspace_bytes", "wx
            "wx_mlp_init", "wx_mlp_refresh", "wx_mlp_norm_scratch_bytes", "wx_mlp_fit_norm",
            "wx_mlp_normalize", "wx_mlp_work_bytes", "wx_mlp_forward_backward", "wx_mlp_adam",
            "wx_mlp_train_step", "wx_mlp_infer_work_bytes", "wx_mlp_infer",
-           "wx_surrogate_work_bytes", "wx_rw_step", "wx_rw_run", "wx_rw_run_kij",
+           "wx_surrogate_work_bytes", "wx_rw_step", "wx_rw_run", "wx_rw_run_kij", "wx_mass_noalloc",
            "wx_rw_run_block", "wx_hevi_grid_init", "wx_hevi_workspace_bytes", "wx_hevi_run")
 
 # surrogate network shapes and blob sections (include/wx.h)
@@ -113,6 +113,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.wx_step.argtypes = [sp, ctypes.c_int, ctypes.c_void_p]
     lib.wx_physics.argtypes = [sp, ctypes.POINTER(_Tend), ctypes.c_int]
     lib.wx_mass.argtypes = [sp]
+    lib.wx_mass_noalloc.argtypes = [sp]
     lib.wx_profile_step.argtypes = [sp, ctypes.c_int, ctypes.c_void_p,
                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     lib.wx_copy_probe.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
@@ -332,6 +333,12 @@ class State:
         torch.cuda.synchronize(self.device)
         m = self.t["mass_out"].cpu().numpy()
         return np.array([m[0] + m[1], m[2] + m[3], m[4] + m[5]])
+
+    def mass_noalloc(self, stream=None) -> None:
+        """Run wx_mass_noalloc (the same sums into mass_out, partials in the
+        library's static device array; the workspace is not used)."""
+        self._p.contents.stream = _stream_ptr(stream)
+        _check(self.lib.wx_mass_noalloc(self._p), "wx_mass_noalloc")
 
     def mass_raw(self) -> np.ndarray:
         torch = _torch()

@@ -188,3 +188,14 @@ def test_reduced_app_validates_before_any_launch(lib):
     which.value = 7
     assert lib.wx_rw_run_kij(a, b, s, p, 4, 4, 4, 0.1, 0, ctypes.byref(which), None) == wx.WX_OK
     assert which.value == 0
+
+
+def test_mass_noalloc_rejects_grids_beyond_its_static_array(lib):
+    # ceil(64/64) * 40961 partial blocks > WX_MASS_NOALLOC_MAX_PARTS: rejected on
+    # the host before any pointer is looked at or any device call is made
+    p = lib.wx_create(64, 40961, 3, 2.0, 100.0, _dz(3))
+    assert p
+    assert lib.wx_mass_noalloc(p) == wx.WX_E_INVAL
+    assert b"at most 40960" in lib.wx_last_error()
+    lib.wx_destroy(p)
+    assert lib.wx_mass_noalloc(None) == wx.WX_E_INVAL
