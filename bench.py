@@ -407,7 +407,8 @@ def ablation_leg(host_inp, stream, steps: int = 10):
                                     "algorithmic_GBs": round(gbs, 1)}
         log(f"stage tile {name}: {out['stage_tiles'][name]}")
     st.set_param("stage_tile", 0)
-    for var, name in ((0, "column in registers, 1 wave/SIMD"), (1, "column re-read, 2 waves/SIMD")):
+    for var, name in ((0, "column in registers, 1 wave/SIMD"), (1, "column re-read, 2 waves/SIMD"),
+                      (2, "wave per column, lane scans")):
         st.set_param("phys_kernel", var)
         st.step(1)
         d = st.profile(steps, stream).tolist()[4]
@@ -457,32 +458,34 @@ VALUES_HEVI = 6 + 11
 
 def hevi_leg(nx: int, ny: int, nz: int, stream, steps: int = 50):
     """Fast-mode (HEVI) short steps at the benchmark grid, FP32: time per short
-    step and the HBM roofline of its two launches."""
+    step and the HBM roofline of its two launches, for the register kernel
+    (the default) and the one that parks the column in its outputs."""
     import torch
 
     from paper_1802_05839_amd import inputs, wx
 
     f = inputs.hevi_fields(nx, ny, nz, seed=2).astype(np.float32)
-    hv = wx.Hevi(f, inputs.HEVI_TAU_DEFAULT, dtype="f32")
-    del f
-    hv.run(4, stream)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    hv.run(steps, stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / steps
     ncells = nx * ny * nz
-    gbs = VALUES_HEVI * 4 * ncells / (ms / 1e3) / 1e9
-    del hv
+    out = {}
+    for kernel, name in ((0, "registers"), (1, "parked")):
+        hv = wx.Hevi(f, inputs.HEVI_TAU_DEFAULT, dtype="f32", kernel=kernel)
+        hv.run(4, stream)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        hv.run(steps, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        gbs = VALUES_HEVI * 4 * ncells / (ms / 1e3) / 1e9
+        del hv
+        out[name] = {"ms_per_short_step": round(ms, 4), "Mcell_steps_per_s": round(ncells / (ms / 1e3) / 1e6, 1),
+                     "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+    del f
     return {"workload": f"HEVI short step {nx}x{ny}x{nz} FP32 (two stages, vertical tridiagonal solve per column)",
-            "steps": steps, "ms_per_short_step": round(ms, 4),
-            "Mcell_steps_per_s": round(ncells / (ms / 1e3) / 1e6, 1),
-            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(gbs / HBM_PEAK_GBS, 4),
-                         "algorithmic_bytes_per_cell": VALUES_HEVI * 4}}
+            "steps": steps, "algorithmic_bytes_per_cell": VALUES_HEVI * 4, **out}
 
 
 def main() -> int:

@@ -65,8 +65,10 @@ typedef enum wx_phys_mode {
   WX_PHYS_OFF = 0,        /* dycore only                                        */
   WX_PHYS_PLAIN = 1,      /* dycore, then implicit diffusion + radiation        */
   WX_PHYS_SURROGATE = 2,  /* dycore, then the learned surrogate on every column */
-  WX_PHYS_JUDGED = 3      /* dycore, surrogate, plain physics on sampled columns
+  WX_PHYS_JUDGED = 3,     /* dycore, surrogate, plain physics on sampled columns
                              as judge, whole-step fallback to the plain physics  */
+  WX_PHYS_DATASET = 4     /* wx_physics only: raw feature rows and plain-physics
+                             tendency labels of every column (as wx_dataset)    */
 } wx_phys_mode;
 
 /* Tunable constants (readings of the paper; defaults in brackets). */
@@ -90,10 +92,15 @@ typedef enum wx_param {
                                 fixed once the surrogate workspace is sized [100] */
   WX_PARAM_STEP = 11,        /* index t of the next step (sample hash), integer
                                 >= 0; wx_step advances it by nsteps [0]          */
-  WX_PARAM_PHYS_KERNEL = 12, /* kernel of the FP32 physics at nz 16 and 58, same
-                                arithmetic: 0 column kept in registers (one wave
-                                per SIMD), 1 column read again on the way down
-                                (two waves per SIMD) [0]                         */
+  WX_PARAM_PHYS_KERNEL = 12, /* kernel of the FP32 plain physics: 0 thread per
+                                column, column kept in registers (one wave per
+                                SIMD; nz 16 and 58); 1 the same, column read
+                                again on the way down (two waves per SIMD);
+                                0 and 1 give the same bits; 2 wave per column,
+                                the k-recurrences (elimination, back
+                                substitution, optical depth) as scans over the
+                                lanes (nz <= 64; same arithmetic in another
+                                order: equal within rounding) [0]                */
   WX_PARAM_STAGE_TILE = 13,  /* tile of the RK3 stage kernel (columns x rows), same
                                 results bit for bit: 0 64x8, 1 64x4, 2 64x12,
                                 3 32x16, 4 128x4, 5 64x8 with each face value,
@@ -146,6 +153,8 @@ typedef struct wx_state {
 typedef struct wx_tend {
   void *dtheta;            /* nx*ny*nz of the state's dtype: d(theta)/dt [K/s]    */
   void *dq;                /* nx*ny*nz: d(q)/dt [1/s]                             */
+  void *features;          /* WX_PHYS_DATASET: [nx*ny][320] FP32 raw feature rows */
+  float *labels;           /* WX_PHYS_DATASET: [nx*ny][128] FP32 tendency labels  */
 } wx_tend;
 
 /* Create a state for an nx x ny x nz grid (nx, ny >= 4, 3 <= nz <= 1024),
@@ -188,9 +197,17 @@ int wx_halo(wx_state *s, void *stream);
 int wx_step(wx_state *s, int nsteps, void *stream);
 
 /* Physics tendencies of the current state on s->stream, state unchanged.
- * mode must be WX_PHYS_PLAIN: t->dtheta = delta_theta/dt + H, t->dq = delta_q/dt
- * of one implicit-diffusion + radiation step of length dt.  Requires a current
- * halo on u and v (wx_halo or wx_step). */
+ * Requires a current halo on u and v (wx_halo or wx_step).
+ *   WX_PHYS_PLAIN: t->dtheta = delta_theta/dt + H, t->dq = delta_q/dt of one
+ *     implicit-diffusion + radiation step of length dt (any dtype, any nz);
+ *   WX_PHYS_SURROGATE: the learned surrogate's tendencies of every column
+ *     (FP32 state, nz 58, s->mlp and s->surrogate_work set);
+ *   WX_PHYS_JUDGED: the surrogate's tendencies judged on the columns sampled
+ *     for step index WX_PARAM_STEP (not advanced): sampled columns carry the
+ *     plain tendencies, and every column does when the pooled RMSE exceeds
+ *     the bound (s->judge_out receives the verdict, as in wx_step);
+ *   WX_PHYS_DATASET: t->features and t->labels as wx_dataset fills them
+ *     (t->dtheta / t->dq unused). */
 int wx_physics(wx_state *s, wx_tend *t, int mode);
 
 /* Compensated FP64 mass sums of the current state into mass_out (6 doubles),
@@ -425,6 +442,11 @@ typedef struct wx_hevi_grid {
   double dx;                     /* horizontal spacing [m], dy == dx                */
   double tau;                    /* short step [s]                                  */
   double c_sound, n_bv;          /* sound speed [m/s] > 0, buoyancy frequency [1/s] */
+  int32_t kernel;                /* 0 (set by init): for nz 16 and 58 the column's
+                                    intermediates stay in registers, other nz park
+                                    them in the outputs; 1: always park them
+                                    (the same results within rounding)           */
+  int32_t pad;
 } wx_hevi_grid;
 
 /* Fill *g for the given grid and constants (host only).  WX_E_INVAL on bad

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libwx.so")
 
 SOURCES = ["wx_host.hip", "wx_mlp_host.hip", "k_dycore.hip", "k_physics.hip", "k_mlp.hip",
-           "k_surrogate.hip", "k_judge.hip", "k_fused.hip", "k_reduced.hip", "k_hevi.hip", "hevi_host.hip"]
+           "k_surrogate.hip", "k_judge.hip", "k_fused.hip", "k_reduced.hip", "k_hevi.hip", "hevi_host.hip", "k_physics_scan.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

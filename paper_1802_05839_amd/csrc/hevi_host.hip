@@ -133,7 +133,7 @@ int hevi_run(const wx_hevi_grid *g, const double *dz, void *u, void *v, void *w,
         a.u_o = nxt[0]; a.v_o = nxt[1]; a.w_o = nxt[2]; a.b_o = nxt[3]; a.pi_o = nxt[4];
         a.e_o = nxt[2];
       }
-      HX_HIP(wx::launch_hevi_stage<T>(a, s == 1, st));
+      HX_HIP(wx::launch_hevi_stage<T>(a, s == 1, g->kernel == 0, st));
     }
     T **t = cur;
     cur = nxt;
@@ -178,6 +178,8 @@ int wx_hevi_grid_init(wx_hevi_grid *g, int nx, int ny, int nz, int dtype, double
   g->tau = tau;
   g->c_sound = c_sound;
   g->n_bv = n_bv;
+  g->kernel = 0;
+  g->pad = 0;
   return WX_OK;
 }
 
@@ -197,6 +199,7 @@ int wx_hevi_run(const wx_hevi_grid *g, const double *dz, void *u, void *v, void 
   for (const void *p : req)
     if (!p || !al16(p)) return hfail(WX_E_INVAL, "field or workspace pointer NULL or not 16-byte aligned");
   if (nsteps < 0) return hfail(WX_E_INVAL, "nsteps must be >= 0");
+  if (g->kernel != 0 && g->kernel != 1) return hfail(WX_E_INVAL, "kernel must be 0 or 1");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (g->dtype == WX_F32) return hevi_run<float>(g, dz, u, v, w, b, pi, workspace, nsteps, st);
   return hevi_run<double>(g, dz, u, v, w, b, pi, workspace, nsteps, st);

@@ -289,6 +289,15 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
   const int nk = (part & 1) ? kNZ - kHalf : kHalf;
   const int ob = (part < 2 ? 0 : kNZ) + kb;
   const float *yr = Y + col * YLD + ob;
+  if (a.tend_t) {
+    // tendency mode: d(theta)/dt or d(q)/dt at (i, j, k), i fastest
+    float *tf = part < 2 ? a.tend_t : a.tend_q;
+    for (int k = 0; k < nk; ++k) {
+      const float2 ms = yn[ob + k];
+      stg(tf, unsigned((kb + k) * ny + j) * unsigned(nx) + unsigned(i), fmaf(yr[k], ms.y, ms.x));
+    }
+    return;
+  }
   const unsigned gb = g0 + unsigned(kb) * a.g.sk;
   // all loads before any store: the stores may alias the loads, so a mixed
   // order would serialise one HBM round trip per level

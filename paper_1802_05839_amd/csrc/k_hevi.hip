@@ -116,11 +116,164 @@ __global__ __launch_bounds__(256) void k_hevi_stage(HeviArgs<T> a) {
   }
 }
 
+// The same stage for a compile-time level count (the 58- and 16-level
+// grids): the column's P_k = pi_k - h c^2 D_k and eliminated right-hand side
+// e_f stay in registers between the two marches instead of round-tripping
+// through memory, so the first stage moves exactly its five inputs and its
+// pi, and the second re-reads only w and b on the way down.  P_k forms
+// pi - h c^2 (D + dwm/dz) as (pi - h c^2 D) - h c^2 dwm/dz, one rounding
+// more than the generic kernel.
+template <typename T, bool FULL, int NZ>
+__global__ __launch_bounds__(256) void k_hevi_stage_reg(HeviArgs<T> a) {
+  const int nx = a.g.nx, ny = a.g.ny;
+  const int nbx = (nx + 63) / 64;
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int i = (L % nbx) * 64 + threadIdx.x, j = (L / nbx) * 4 + threadIdx.y;
+  if (i >= nx || j >= ny) return;
+  const unsigned sj = a.g.sj, sk = a.g.sk;
+  const unsigned col = a.g.origin + unsigned(i) + unsigned(j) * sj;
+  const long long sjl = sj;
+  const T *pe = plane(a.pp, 1), *pw = plane(a.pp, -1), *pn = plane(a.pp, sjl), *ps = plane(a.pp, -sjl);
+  const T *uw = plane(a.u, -1), *vs = plane(a.v, -sjl);
+  const T h = a.h, h2 = a.h2, a4 = a.a4, hc2 = a.hc2, hn2 = a.hn2, dx = a.dx, rdx = a.rdx;
+  const HeviCoef<T> *cf = a.coef;
+  const int di = i < 2 ? nx : (i >= nx - 2 ? -nx : 0);
+  const int dj = j < 2 ? ny * int(sj) : (j >= ny - 2 ? -ny * int(sj) : 0);
+  T P[NZ], E[NZ];
+  T d_lo = 0, pi_lo = 0, e_lo = 0;
+  // the twelve loads of a level are issued PF levels ahead (a register ring)
+  constexpr int PF = 3;
+  T rc[PF], re[PF], rw[PF], rn[PF], rs[PF], ru[PF], rv[PF], rx[PF], ry[PF], rp[PF], rwz[PF], rbz[PF];
+  auto fetch = [&](int lev, int sl) {
+    // an opaque per-level offset keeps the compiler from computing every
+    // level's address up front (NZ more live registers)
+    unsigned g = col + unsigned(lev) * sk;
+    asm volatile("" : "+v"(g));
+    rc[sl] = ldg(a.pp, g);
+    re[sl] = ldg(pe, g);
+    rw[sl] = ldg(pw, g);
+    rn[sl] = ldg(pn, g);
+    rs[sl] = ldg(ps, g);
+    ru[sl] = ldg(a.u, g);
+    rx[sl] = ldg(uw, g);
+    rv[sl] = ldg(a.v, g);
+    ry[sl] = ldg(vs, g);
+    rp[sl] = ldg(a.pi, g);
+    rwz[sl] = ldg(a.w, g);
+    rbz[sl] = ldg(a.b, g);
+  };
+#pragma unroll
+  for (int l = 0; l < PF; ++l)
+    if (l < NZ) fetch(l, l);
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) {
+    const int sl = k % PF;
+    unsigned g = col + unsigned(k) * sk;
+    asm volatile("" : "+v"(g));
+    const T pc = rc[sl];
+    const T ue = ru[sl] - over(h * (re[sl] - pc), dx, rdx);
+    const T uo = rx[sl] - over(h * (pc - rw[sl]), dx, rdx);
+    const T vn = rv[sl] - over(h * (rn[sl] - pc), dx, rdx);
+    const T vo = ry[sl] - over(h * (pc - rs[sl]), dx, rdx);
+    const T D = over(ue - uo, dx, rdx) + over(vn - vo, dx, rdx);
+    if (FULL) {
+      stg(a.u_o, g, ue);
+      stg(a.v_o, g, vn);
+    }
+    const T pik = rp[sl], wk = rwz[sl], bk = rbz[sl];
+    if (k + PF < NZ) fetch(k + PF, sl);
+    P[k] = pik - hc2 * D;
+    if (k > 0) {
+      const HeviCoef<T> c = cf[k];
+      const T rhs = (wk + h2 * (over(-(pik - pi_lo), c.dzf, c.rdzf) + bk)) +
+                    over(a4 * (D - d_lo), c.dzf, c.rdzf);
+      const T e = (rhs + c.lo * e_lo) * c.inv;
+      E[k] = e;
+      e_lo = e;
+    }
+    d_lo = D;
+    pi_lo = pik;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // the coefficients are read again on the way down through an opaque copy
+  // of the table pointer: reusing the upward march's values would keep all
+  // NZ levels of them live in registers across both marches
+  const HeviCoef<T> *cfd = cf;
+  asm volatile("" : "+s"(cfd));
+  T wm_hi = 0;
+  // w and b of the second stage, re-read on the way down PF levels ahead
+  T dw[PF], db[PF];
+  auto fetch_dn = [&](int lev, int sl) {
+    unsigned g = col + unsigned(lev) * sk;
+    asm volatile("" : "+v"(g));
+    dw[sl] = ldg(a.w, g);
+    db[sl] = ldg(a.b, g);
+  };
+  if (FULL) {
+#pragma unroll
+    for (int l = 0; l < PF; ++l)
+      if (NZ - 1 - l >= 1) fetch_dn(NZ - 1 - l, l);
+  }
+#pragma unroll
+  for (int k = NZ - 1; k >= 0; --k) {
+    unsigned g = col + unsigned(k) * sk;
+    asm volatile("" : "+v"(g));
+    const HeviCoef<T> c = cfd[k];
+    T wm = 0;
+    if (k > 0) {
+      wm = E[k] - c.cp * wm_hi;
+      if (FULL) {
+        const int sl = (NZ - 1 - k) % PF;
+        const T wk = dw[sl], bk = db[sl];
+        if (k - PF >= 1) fetch_dn(k - PF, sl);
+        stg(a.w_o, g, T(2) * wm - wk);
+        stg(a.b_o, g, bk - hn2 * wm);
+      }
+    }
+    stg(a.pi_o, g, P[k] - hc2 * over(wm_hi - wm, c.dz, c.rdz));
+    wm_hi = wm;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (FULL) {
+    stg(a.w_o, col, T(0));
+    stg(a.w_o, col + unsigned(NZ) * sk, T(0));
+    stg(a.b_o, col, T(0));
+    stg(a.b_o, col + unsigned(NZ) * sk, T(0));
+  }
+  // periodic halo images, written after both marches: a branch on the lane
+  // inside the unrolled marches would keep far more registers live.  The
+  // thread reads back its own stores (same addresses, program order).
+  if (di != 0 || dj != 0) {
+    for (int k = 0; k < NZ; ++k) {
+      const unsigned g = col + unsigned(k) * sk;
+      T *outs[3] = {a.pi_o, a.u_o, a.v_o};
+      for (int f = 0; f < (FULL ? 3 : 1); ++f) {
+        const T v = ldg(outs[f], g);
+        if (di != 0) stg(outs[f], g + di, v);
+        if (dj != 0) {
+          stg(outs[f], g + dj, v);
+          if (di != 0) stg(outs[f], g + dj + di, v);
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
 
 template <typename T>
-hipError_t launch_hevi_stage(const HeviArgs<T> &a, bool full, hipStream_t s) {
+hipError_t launch_hevi_stage(const HeviArgs<T> &a, bool full, bool regs, hipStream_t s) {
   const int nb = ((a.g.nx + 63) / 64) * ((a.g.ny + 3) / 4);
+  if (regs && (a.g.nz == 58 || a.g.nz == 16)) {
+    if (a.g.nz == 58) {
+      if (full) hipLaunchKernelGGL((k_hevi_stage_reg<T, true, 58>), dim3(nb), dim3(64, 4), 0, s, a);
+      else hipLaunchKernelGGL((k_hevi_stage_reg<T, false, 58>), dim3(nb), dim3(64, 4), 0, s, a);
+    } else {
+      if (full) hipLaunchKernelGGL((k_hevi_stage_reg<T, true, 16>), dim3(nb), dim3(64, 4), 0, s, a);
+      else hipLaunchKernelGGL((k_hevi_stage_reg<T, false, 16>), dim3(nb), dim3(64, 4), 0, s, a);
+    }
+    return hipGetLastError();
+  }
   if (full)
     hipLaunchKernelGGL((k_hevi_stage<T, true>), dim3(nb), dim3(64, 4), 0, s, a);
   else
@@ -128,7 +281,7 @@ hipError_t launch_hevi_stage(const HeviArgs<T> &a, bool full, hipStream_t s) {
   return hipGetLastError();
 }
 
-template hipError_t launch_hevi_stage<float>(const HeviArgs<float> &, bool, hipStream_t);
-template hipError_t launch_hevi_stage<double>(const HeviArgs<double> &, bool, hipStream_t);
+template hipError_t launch_hevi_stage<float>(const HeviArgs<float> &, bool, bool, hipStream_t);
+template hipError_t launch_hevi_stage<double>(const HeviArgs<double> &, bool, bool, hipStream_t);
 
 }  // namespace wx

@@ -166,6 +166,14 @@ __global__ void k_apply_sampled(ApplyArgs<T> a, const float *tend, const int *li
   const int di = i < 2 ? nx : (i >= nx - 2 ? -nx : 0);
   const int dj = j < 2 ? ny * int(a.g.sj) : (j >= ny - 2 ? -ny * int(a.g.sj) : 0);
   const float *row = tend + (size_t)s * TEND_ROW;
+  if (a.tend_t) {
+    for (int k = 0; k < nz; ++k) {
+      const unsigned o = unsigned(k * ny + j) * unsigned(nx) + unsigned(i);
+      stg(a.tend_t, o, row[k]);
+      stg(a.tend_q, o, row[nz + k]);
+    }
+    return;
+  }
   for (int k = 0; k < nz; ++k) {
     const unsigned g = g0 + unsigned(k) * a.g.sk;
     const T tn = ldg(a.th, g) + a.dt * T(row[k]);

@@ -30,19 +30,6 @@
 namespace wx {
 namespace {
 
-struct Kahan {
-  double s = 0.0, c = 0.0;
-  __device__ __forceinline__ void add(double x) {
-    const double t = s + x;
-    c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
-    s = t;
-  }
-  __device__ __forceinline__ void merge(double s2, double c2) {
-    const double t = s + s2;
-    c += c2 + ((fabs(s) >= fabs(s2)) ? ((s - t) + s2) : ((s2 - t) + s));
-    s = t;
-  }
-};
 
 // Fixed-order reduction over the 64 lanes of a wave; lane 0 holds the result.
 __device__ __forceinline__ void wave_merge(Kahan &k) {
@@ -54,11 +41,6 @@ __device__ __forceinline__ void wave_merge(Kahan &k) {
   }
 }
 
-__device__ __forceinline__ int wave_sum_i(int v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
 
 // c', d'_theta, d'_q storage: LDS [3][nz][64] or global [3][nz][ncol].
 template <typename E>
@@ -221,7 +203,7 @@ __device__ __forceinline__ void block_finish(const PhysArgs<float> *ap, double *
   const int tid = threadIdx.x + threadIdx.y * blockDim.x;
   const int lane = tid & 63, wv = tid >> 6;
   (void)ap;
-  const int nf = wave_sum_i(cnt.nonfinite), nr = wave_sum_i(cnt.rho_le0), nd = wave_sum_i(fp64);
+  const int nf = wave_sum_int(cnt.nonfinite), nr = wave_sum_int(cnt.rho_le0), nd = wave_sum_int(fp64);
   if (do_mass)
     for (int v = 0; v < 3; ++v) wave_merge(mass[v]);
   if (lane == 0) {
@@ -312,8 +294,11 @@ __global__ __launch_bounds__(256, KEEP ? 1 : 2) void k_physics_f32(PhysArgs<floa
     // west and south face winds through shifted (uniform) base pointers, so
     // that all seven loads of a level share one vector offset
     const float *uw = plane(a.u, -1), *vs = plane(a.v, -(long long)sj);
+    // per-level offsets are made opaque (asm) so that the compiler forms each
+    // where it is used instead of all NZ of them up front in registers
     auto fetch_up = [&](int lev, int slot) {
-      const unsigned g = g0 + unsigned(lev) * sk;
+      unsigned g = g0 + unsigned(lev) * sk;
+      asm volatile("" : "+v"(g));
       pr[slot] = ldg(a.rho, g);
       pt[slot] = ldg(a.th, g);
       pq[slot] = ldg(a.q, g);
@@ -407,7 +392,8 @@ __global__ __launch_bounds__(256, KEEP ? 1 : 2) void k_physics_f32(PhysArgs<floa
 #pragma unroll
         for (int l = 0; l < PF; ++l)
           if (NZ - 1 - l >= 0) {
-            const unsigned g = gd + unsigned(NZ - 1 - l) * sk;
+            unsigned g = gd + unsigned(NZ - 1 - l) * sk;
+            asm volatile("" : "+v"(g));
             dr[l] = ldg(a.rho, g);
             dtt[l] = ldg(a.th, g);
             dqq_[l] = ldg(a.q, g);
@@ -426,7 +412,8 @@ __global__ __launch_bounds__(256, KEEP ? 1 : 2) void k_physics_f32(PhysArgs<floa
           t = dtt[sl];
           q = dqq_[sl];
           if (k - PF >= 0) {
-            const unsigned g = gd + unsigned(k - PF) * sk;
+            unsigned g = gd + unsigned(k - PF) * sk;
+            asm volatile("" : "+v"(g));
             dr[sl] = ldg(a.rho, g);
             dtt[sl] = ldg(a.th, g);
             dqq_[sl] = ldg(a.q, g);
@@ -442,7 +429,8 @@ __global__ __launch_bounds__(256, KEEP ? 1 : 2) void k_physics_f32(PhysArgs<floa
         const float tr_lo = expf(-tau);
         const float heat = f0 * (tr_hi - tr_lo) * fast_rcp(cpa * (r * dzk));
         tr_hi = tr_lo;
-        const unsigned g = gd + unsigned(k) * sk;
+        unsigned g = gd + unsigned(k) * sk;
+        asm volatile("" : "+v"(g));
         if (MODE == 1) {
           if (a.tend_rows) {
             const unsigned o = unsigned(col) * TEND_ROW + unsigned(k);
@@ -460,13 +448,10 @@ __global__ __launch_bounds__(256, KEEP ? 1 : 2) void k_physics_f32(PhysArgs<floa
           const float qn = q + dqq;
           stg(a.th, g, tn);
           stg(a.q, g, qn);
-          if (di != 0) { stg(a.th, g + di, tn); stg(a.q, g + di, qn); }
-          if (dj != 0) {
-            stg(a.th, g + dj, tn); stg(a.q, g + dj, qn);
-            if (di != 0) { stg(a.th, g + dj + di, tn); stg(a.q, g + dj + di, qn); }
-          }
-          if (!(isfinite(r) && isfinite(tn) && isfinite(qn))) cnt.nonfinite++;
-          if (!(r > 0.f)) cnt.rho_le0++;
+          // (the periodic images are written after the loop: a per-lane
+          // branch inside the unrolled loop keeps many more registers live)
+          cnt.nonfinite += (isfinite(r) && isfinite(tn) && isfinite(qn)) ? 0 : 1;
+          cnt.rho_le0 += (r > 0.f) ? 0 : 1;
           if (a.do_mass) {
             const double mv = double(r) * s_vol[k];
             cm += mv;
@@ -480,6 +465,19 @@ __global__ __launch_bounds__(256, KEEP ? 1 : 2) void k_physics_f32(PhysArgs<floa
         mass[0].add(cm);
         mass[1].add(cmt);
         mass[2].add(cmq);
+      }
+      // periodic images of the updated column (the thread reads back its own
+      // stores: same addresses, program order)
+      if (MODE == 0 && (di != 0 || dj != 0)) {
+        for (int k = 0; k < NZ; ++k) {
+          const unsigned g = gd + unsigned(k) * sk;
+          const float tn = ldg(a.th, g), qn = ldg(a.q, g);
+          if (di != 0) { stg(a.th, g + di, tn); stg(a.q, g + di, qn); }
+          if (dj != 0) {
+            stg(a.th, g + dj, tn); stg(a.q, g + dj, qn);
+            if (di != 0) { stg(a.th, g + dj + di, tn); stg(a.q, g + dj + di, qn); }
+          }
+        }
       }
     }
   }
@@ -538,7 +536,7 @@ __global__ __launch_bounds__(PHYS_BX) void k_physics(PhysArgs<T> a) {
     }
   }
   // block (= one wave) reductions in a fixed order
-  const int nf = wave_sum_i(cnt.nonfinite), nr = wave_sum_i(cnt.rho_le0), nd = wave_sum_i(fp64);
+  const int nf = wave_sum_int(cnt.nonfinite), nr = wave_sum_int(cnt.rho_le0), nd = wave_sum_int(fp64);
   if (MODE == 0 && a.do_mass) {
     for (int v = 0; v < 3; ++v) wave_merge(mass[v]);
     if (lane == 0) {
@@ -578,7 +576,7 @@ __global__ __launch_bounds__(PHYS_BX) void k_mass(MassArgs<T> a) {
     }
   }
   for (int v = 0; v < 3; ++v) wave_merge(mass[v]);
-  const int nf = wave_sum_i(cnt.nonfinite), nr = wave_sum_i(cnt.rho_le0);
+  const int nf = wave_sum_int(cnt.nonfinite), nr = wave_sum_int(cnt.rho_le0);
   if (lane == 0) {
     double *p = a.partials + (long long)blockIdx.x * 6;
     for (int v = 0; v < 3; ++v) {
@@ -640,6 +638,7 @@ hipError_t launch_physics(const PhysArgs<T> &a, hipStream_t s) {
     return hipGetLastError();
   }
   if constexpr (sizeof(T) == 4) {
+    if (phys_uses_scan(4, a.g.nz, a.variant) && !a.tend_rows) return launch_physics_scan(a, s);
     const int nb = phys_reg_blocks(a.g.nx, a.g.ny);
     const dim3 blk(64, 4);
     const bool keep = a.variant != PHYS_VARIANT_REREAD;

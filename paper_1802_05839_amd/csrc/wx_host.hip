@@ -70,7 +70,8 @@ Layout layout(const wx_state *s, size_t es) {
   L.scratch = off;
   off += align256(3 * size_t(s->nz) * size_t(s->nx) * size_t(s->ny) * 8);
   L.partials = off;
-  const int nparts = std::max(wx::phys_blocks(s->nx, s->ny), wx::phys_reg_blocks(s->nx, s->ny));
+  const int nparts = std::max({wx::phys_blocks(s->nx, s->ny), wx::phys_reg_blocks(s->nx, s->ny),
+                               wx::phys_scan_blocks(s->nx, s->ny)});
   off += align256(size_t(nparts) * 6 * 8);
   L.total = off;
   return L;
@@ -334,7 +335,7 @@ struct Plan {
   int physics(int do_mass, Timer &tm) {
     WX_TRY(tm.begin(4));
     WX_HIP(wx::launch_physics<T>(phys_args(0, do_mass, nullptr, nullptr), st));
-    nparts = wx::phys_partials(sizeof(T), s->nx, s->ny, s->nz);
+    nparts = wx::phys_partials(sizeof(T), s->nx, s->ny, s->nz, int(impl_of(s)->param[WX_PARAM_PHYS_KERNEL]));
     return tm.end();
   }
 
@@ -361,8 +362,9 @@ struct Plan {
   // Surrogate physics of step t on the post-dycore state (optionally judged):
   // judge prelude on the sampled columns, then one fused launch over all
   // columns, then the plain tendencies of the sampled columns, or the plain
-  // physics everywhere when the judge rejected the step.
-  int surrogate(bool judged, uint64_t t, Timer &tm) {
+  // physics everywhere when the judge rejected the step.  With tend_t set the
+  // same decisions produce tendencies (flat, i fastest) and leave the state.
+  int surrogate(bool judged, uint64_t t, Timer &tm, float *tend_t = nullptr, float *tend_q = nullptr) {
     if (!std::is_same<T, float>::value) return fail(WX_E_UNSUPPORTED, "the surrogate needs an FP32 state");
     const Impl *im = impl_of(s);
     const SurrogateLayout L = surrogate_layout(s);
@@ -403,6 +405,8 @@ struct Plan {
     wx::FusedArgs fa = fused_args(s, s->mlp);
     fa.c0 = 0;
     fa.ncols = ncol;
+    fa.tend_t = tend_t;
+    fa.tend_q = tend_q;
     fa.fallback = judged ? fallback : nullptr;
     fa.judged = judged ? 1 : 0;
     fa.seed = seed;
@@ -412,7 +416,9 @@ struct Plan {
     WX_HIP(wx::launch_surrogate_fused(fa, st));
     WX_TRY(tm.end());
     if (judged) {
-      wx::ApplyArgs<T> aa;
+      wx::ApplyArgs<T> aa{};
+      aa.tend_t = tend_t;
+      aa.tend_q = tend_q;
       aa.th = base[1];
       aa.q = base[2];
       aa.g = geom(s);
@@ -426,7 +432,8 @@ struct Plan {
       aa.rate = rate;
       WX_TRY(tm.begin(8));
       WX_HIP(wx::launch_apply_sampled<T>(aa, tplain, list, n_list, L.cap, st));
-      wx::PhysArgs<T> pa = phys_args(0, 0, nullptr, nullptr);
+      wx::PhysArgs<T> pa = tend_t ? phys_args(1, 0, reinterpret_cast<T *>(tend_t), reinterpret_cast<T *>(tend_q))
+                                  : phys_args(0, 0, nullptr, nullptr);
       pa.run_if = fallback;
       WX_HIP(wx::launch_physics<T>(pa, st));
       WX_TRY(tm.end());
@@ -645,8 +652,8 @@ int wx_set_param(wx_state *s, int param, double value) {
   if ((param == WX_PARAM_MASS_EVERY || param == WX_PARAM_JUDGE_SEED || param == WX_PARAM_JUDGE_RATE ||
        param == WX_PARAM_STEP) && value != std::floor(value))
     return fail(WX_E_INVAL, "param %d must be an integer", param);
-  if (param == WX_PARAM_PHYS_KERNEL && value != 0.0 && value != 1.0)
-    return fail(WX_E_INVAL, "physics kernel must be 0 or 1");
+  if (param == WX_PARAM_PHYS_KERNEL && value != 0.0 && value != 1.0 && value != 2.0)
+    return fail(WX_E_INVAL, "physics kernel must be 0, 1 or 2");
   if (param == WX_PARAM_STAGE_TILE && (value != std::floor(value) || value >= wx::STAGE_TILE_VARIANTS))
     return fail(WX_E_INVAL, "stage tile must be an integer in 0..%d", wx::STAGE_TILE_VARIANTS - 1);
   if (param == WX_PARAM_JUDGE_SEED && value >= 4294967296.0) return fail(WX_E_INVAL, "judge seed must be < 2^32");
@@ -691,11 +698,27 @@ int wx_step(wx_state *s, int nsteps, void *stream) {
 
 int wx_physics(wx_state *s, wx_tend *t, int mode) {
   if (!s || !s->impl) return fail(WX_E_INVAL, "state is NULL");
-  if (mode != WX_PHYS_PLAIN) return fail(WX_E_UNSUPPORTED, "wx_physics mode %d is not supported", mode);
-  if (!t || !t->dtheta || !t->dq) return fail(WX_E_INVAL, "tendency buffers are NULL");
+  if (mode < WX_PHYS_PLAIN || mode > WX_PHYS_DATASET)
+    return fail(WX_E_UNSUPPORTED, "wx_physics mode %d is not supported", mode);
+  if (!t) return fail(WX_E_INVAL, "tendency struct is NULL");
+  if (mode == WX_PHYS_DATASET) return wx_dataset(s, static_cast<float *>(t->features), t->labels);
+  if (!t->dtheta || !t->dq) return fail(WX_E_INVAL, "tendency buffers are NULL");
   if (!aligned16(t->dtheta) || !aligned16(t->dq)) return fail(WX_E_INVAL, "tendency buffers must be 16-byte aligned");
   WX_TRY(check_fields(s, true));
   hipStream_t st = static_cast<hipStream_t>(s->stream);
+  if (mode == WX_PHYS_SURROGATE || mode == WX_PHYS_JUDGED) {
+    if (s->dtype != WX_F32) return fail(WX_E_UNSUPPORTED, "the surrogate modes need an FP32 state");
+    if (s->nz != wx::MLP_NZ) return fail(WX_E_UNSUPPORTED, "the surrogate needs nz == %d", wx::MLP_NZ);
+    if (!s->mlp || !s->surrogate_work || !aligned16(s->mlp) || !aligned16(s->surrogate_work))
+      return fail(WX_E_STATE, "surrogate modes need mlp and surrogate_work (16-byte aligned)");
+    if (mode == WX_PHYS_JUDGED && !s->judge_out) return fail(WX_E_STATE, "judged mode needs judge_out");
+    Plan<float> p(s, st);
+    WX_TRY(ensure_consts<float>(s, st));
+    Timer tm;
+    const uint64_t step = uint64_t(impl_of(s)->param[WX_PARAM_STEP]);
+    return p.surrogate(mode == WX_PHYS_JUDGED, step, tm, static_cast<float *>(t->dtheta),
+                       static_cast<float *>(t->dq));
+  }
   if (s->dtype == WX_F32) {
     Plan<float> p(s, st);
     WX_TRY(ensure_consts<float>(s, st));

@@ -49,6 +49,28 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   return x * q + min(x, r) + slot;
 }
 
+// Neumaier-compensated FP64 accumulator (sum s, compensation c).
+struct Kahan {
+  double s = 0.0, c = 0.0;
+  __device__ __forceinline__ void add(double x) {
+    const double t = s + x;
+    c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+    s = t;
+  }
+  __device__ __forceinline__ void merge(double s2, double c2) {
+    const double t = s + s2;
+    c += c2 + ((fabs(s) >= fabs(s2)) ? ((s - t) + s2) : ((s2 - t) + s));
+    s = t;
+  }
+};
+
+// Sum of an int over the 64 lanes of a wave (lane 0 holds the result).
+__device__ __forceinline__ int wave_sum_int(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
 // Reciprocal in the arithmetic precision: the hardware estimate (1 ulp) in
 // FP32, an exact division in FP64.
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -94,6 +116,10 @@ struct PhysArgs {
 // Variants of the FP32 register-column physics kernel (nz 16 and 58).
 constexpr int PHYS_VARIANT_KEEP = 0;     // column kept in registers, one wave per SIMD
 constexpr int PHYS_VARIANT_REREAD = 1;   // column read again on the way down, two waves per SIMD
+constexpr int PHYS_VARIANT_SCAN = 2;     // one wave per column, the k-recurrences as lane scans (nz <= 64)
+constexpr int PHYS_SCAN_COLS = 32;       // columns per block of the scan kernel
+inline int phys_scan_blocks(int nx, int ny) { return ((nx + PHYS_SCAN_COLS - 1) / PHYS_SCAN_COLS) * ny; }
+hipError_t launch_physics_scan(const PhysArgs<float> &a, hipStream_t s);
 
 
 template <typename T>
@@ -127,7 +153,7 @@ struct HeviArgs {
 };
 
 template <typename T>
-hipError_t launch_hevi_stage(const HeviArgs<T> &a, bool full, hipStream_t s);
+hipError_t launch_hevi_stage(const HeviArgs<T> &a, bool full, bool regs, hipStream_t s);
 
 constexpr int PHYS_BX = 64;        // columns per physics block (one wave)
 constexpr int PHYS_LDS_NZ_MAX = 80;
@@ -173,7 +199,11 @@ inline int phys_blocks(int nx, int ny) { return ((nx + PHYS_BX - 1) / PHYS_BX) *
 inline int phys_reg_blocks(int nx, int ny) { return ((nx + 63) / 64) * ((ny + 3) / 4); }
 // physics kernel variant for a state: register-resident columns for FP32 and these level counts
 inline bool phys_uses_reg(int elem_size, int nz) { return elem_size == 4 && (nz == 58 || nz == 16); }
-inline int phys_partials(int elem_size, int nx, int ny, int nz) {
+inline bool phys_uses_scan(int elem_size, int nz, int variant) {
+  return elem_size == 4 && nz <= 64 && variant == PHYS_VARIANT_SCAN;
+}
+inline int phys_partials(int elem_size, int nx, int ny, int nz, int variant = PHYS_VARIANT_KEEP) {
+  if (phys_uses_scan(elem_size, nz, variant)) return phys_scan_blocks(nx, ny);
   return phys_uses_reg(elem_size, nz) ? phys_reg_blocks(nx, ny) : phys_blocks(nx, ny);
 }
 

@@ -195,6 +195,7 @@ struct ApplyArgs {
   int judged;                  // skip sampled columns
   uint64_t seed, t;
   unsigned rate;
+  float *tend_t, *tend_q;      // when set: write the rows as flat tendencies, state untouched
 };
 
 template <typename T>
@@ -240,6 +241,9 @@ struct FusedArgs {
   const int *list, *n_list;
   int cap;
   float *rows_out;
+  // tendency mode (apply mode with tend_t set): the de-normalised tendencies
+  // go to tend_t / tend_q (nx*ny*nz, i fastest) and the state is not touched
+  float *tend_t, *tend_q;
 };
 
 hipError_t launch_surrogate_fused(const FusedArgs &a, hipStream_t s);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libwx.so")
 
 WX_OK, WX_E_INVAL, WX_E_HIP, WX_E_STATE, WX_E_UNSUPPORTED = 0, -1, -2, -3, -4
 WX_F32, WX_F64 = 0, 1
-WX_PHYS_OFF, WX_PHYS_PLAIN, WX_PHYS_SURROGATE, WX_PHYS_JUDGED = 0, 1, 2, 3
+WX_PHYS_OFF, WX_PHYS_PLAIN, WX_PHYS_SURROGATE, WX_PHYS_JUDGED, WX_PHYS_DATASET = 0, 1, 2, 3, 4
 PROFILE_CLASSES = ("halo", "stage1", "stage2", "stage3", "physics", "mass_final", "judge",
                    "surrogate", "sampled_apply")
 PARAMS = {"gamma4": 0, "k_min": 1, "mix_len": 2, "kappa_q": 3, "cp": 4, "t_dd": 5,
@@ -73,7 +73,8 @@ class _State(ctypes.Structure):
 
 
 class _Tend(ctypes.Structure):
-    _fields_ = [("dtheta", ctypes.c_void_p), ("dq", ctypes.c_void_p)]
+    _fields_ = [("dtheta", ctypes.c_void_p), ("dq", ctypes.c_void_p), ("features", ctypes.c_void_p),
+                ("labels", ctypes.c_void_p)]
 
 
 class _HeviGrid(ctypes.Structure):
@@ -82,7 +83,7 @@ class _HeviGrid(ctypes.Structure):
         ("stride_j", ctypes.c_int64), ("stride_k", ctypes.c_int64), ("origin", ctypes.c_int64),
         ("cell_elems", ctypes.c_int64), ("face_elems", ctypes.c_int64),
         ("dx", ctypes.c_double), ("tau", ctypes.c_double), ("c_sound", ctypes.c_double),
-        ("n_bv", ctypes.c_double),
+        ("n_bv", ctypes.c_double), ("kernel", ctypes.c_int32), ("pad", ctypes.c_int32),
     ]
 
 
@@ -310,15 +311,16 @@ class State:
         j = self.t["judge_out"].cpu().numpy()
         return float(j[0]), float(j[1]), bool(j[2]), int(j[3]), float(j[4]), float(j[5])
 
-    def tendencies(self, stream=None):
-        """Plain-physics tendencies (dtheta/dt, dq/dt) of the current state, (nz, ny, nx) float64."""
+    def tendencies(self, stream=None, mode: int = WX_PHYS_PLAIN):
+        """Tendencies (dtheta/dt, dq/dt) of the current state from wx_physics in
+        ``mode`` (plain, surrogate or judged), (nz, ny, nx) float64."""
         torch = _torch()
         s = self._p.contents
         s.stream = _stream_ptr(stream)
         tt = torch.zeros(self.nx * self.ny * self.nz, dtype=self.tdt, device=self.device)
         tq = torch.zeros_like(tt)
-        tend = _Tend(tt.data_ptr(), tq.data_ptr())
-        _check(self.lib.wx_physics(self._p, ctypes.byref(tend), WX_PHYS_PLAIN), "wx_physics")
+        tend = _Tend(tt.data_ptr(), tq.data_ptr(), None, None)
+        _check(self.lib.wx_physics(self._p, ctypes.byref(tend), int(mode)), "wx_physics")
         torch.cuda.synchronize(self.device)
         shp = (self.nz, self.ny, self.nx)
         return (tt.cpu().numpy().astype(np.float64).reshape(shp),
@@ -397,6 +399,17 @@ class State:
         if y_raw is None:
             y_raw = torch.zeros(n, MLP_NOUTP, dtype=torch.float32, device=self.device)
         _check(self.lib.wx_dataset(self._p, x_raw.data_ptr(), y_raw.data_ptr()), "wx_dataset")
+        return x_raw, y_raw
+
+    def dataset_via_physics(self, stream=None):
+        """The same rows through wx_physics(WX_PHYS_DATASET)."""
+        torch = _torch()
+        self._p.contents.stream = _stream_ptr(stream)
+        n = self.nx * self.ny
+        x_raw = torch.zeros(n, MLP_KIN, dtype=torch.float32, device=self.device)
+        y_raw = torch.zeros(n, MLP_NOUTP, dtype=torch.float32, device=self.device)
+        tend = _Tend(None, None, x_raw.data_ptr(), y_raw.data_ptr())
+        _check(self.lib.wx_physics(self._p, ctypes.byref(tend), WX_PHYS_DATASET), "wx_physics(DATASET)")
         return x_raw, y_raw
 
     def close(self) -> None:
@@ -616,7 +629,7 @@ class Hevi:
     FACE = ("w", "b")
 
     def __init__(self, f, tau: float, dtype: str = "f64", c_sound: float = 340.0, n_bv: float = 0.01,
-                 device: str = "cuda:0"):
+                 device: str = "cuda:0", kernel: int = 0):
         torch = _torch()
         self.lib = load_library()
         nz, ny, nx = f.pi.shape
@@ -625,6 +638,7 @@ class Hevi:
         _check(self.lib.wx_hevi_grid_init(ctypes.byref(self.g), nx, ny, nz, WX_F32 if dtype == "f32" else WX_F64,
                                           float(f.dx), float(tau), float(c_sound), float(n_bv)),
                "wx_hevi_grid_init")
+        self.g.kernel = int(kernel)
         self.dz = np.ascontiguousarray(f.dz, dtype=np.float64)
         self.sj = int(self.g.stride_j)
         self.tdt = torch.float32 if dtype == "f32" else torch.float64

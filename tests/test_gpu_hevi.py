@@ -52,16 +52,30 @@ def test_fp64_matches_oracle(nx, ny, nz, nsteps):
         assert e <= 1e-12, (n, errs)
 
 
-def test_fp32_matches_oracle():
-    _say("case: HEVI FP32 97x45x58, 3 steps")
-    f = inputs.hevi_fields(97, 45, 58, seed=3).astype(np.float32)
+@pytest.mark.parametrize("kernel,nz", [(0, 58), (1, 58), (0, 16), (1, 21)])
+def test_fp32_matches_oracle(kernel, nz):
+    # kernel 0 keeps the column in registers for nz 16 / 58, kernel 1 (and any
+    # other nz) parks it in the outputs
+    _say(f"case: HEVI FP32 97x45x{nz} kernel {kernel}, 3 steps")
+    f = inputs.hevi_fields(97, 45, nz, seed=3).astype(np.float32)
     tau = inputs.HEVI_TAU_DEFAULT
-    hv = wx.Hevi(f, tau, dtype="f32")
+    hv = wx.Hevi(f, tau, dtype="f32", kernel=kernel)
     hv.run(3)
     errs = _errors(hv.download(), _oracle(f, 3, tau))
     _say(f"fp32 errors {errs}")
     for n, e in errs.items():
         assert e <= 2e-5, (n, errs)
+
+
+@pytest.mark.parametrize("nz", [16, 58])
+def test_fp64_parked_kernel_matches_oracle(nz):
+    _say(f"case: HEVI FP64 70x37x{nz} parked kernel, 4 steps")
+    f = inputs.hevi_fields(70, 37, nz, seed=nz)
+    hv = wx.Hevi(f, inputs.HEVI_TAU_DEFAULT, dtype="f64", kernel=1)
+    hv.run(4)
+    errs = _errors(hv.download(), _oracle(f, 4, inputs.HEVI_TAU_DEFAULT))
+    for n, e in errs.items():
+        assert e <= 1e-12, (n, errs)
 
 
 def test_zero_steps_and_rest_state_bitwise():

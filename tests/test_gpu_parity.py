@@ -525,3 +525,53 @@ def test_shared_face_stage_kernel_matches_oracle():
     errs = _compare(outs[0][0], _oracle(inp32, 1), FP32_TOL, theta_ref=300.0)
     np.testing.assert_array_equal(outs[0][1], outs[1][1])
     _say(f"shared-face fp32 errors {errs}")
+
+
+@pytest.mark.parametrize("nz", [16, 58, 11])
+def test_scan_physics_kernel_matches_oracle(nz):
+    # one wave per column, the elimination, back substitution and optical
+    # depth as lane scans: the same arithmetic in another order, so the FP32
+    # bar against the oracle (state after a step, tendencies), mass sums equal
+    # to the exactly rounded sums of the stored state, the counters; and on
+    # stiff columns the FP64 scans meet the tight bar the FP64 elimination
+    # meets, with every column counted
+    _say(f"case: scan physics kernel nz={nz}")
+    inp = _f32_inputs(inputs.generate(97, 23, nz, seed=47))
+    st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
+    st.set_param("phys_kernel", 2)
+    tt, tq = st.tendencies()
+    st.step(1)
+    gpu = st.download()
+    mass = st.mass()
+    raw = {name: st.download_raw(name) for name in ("rho", "theta", "q")}
+    flags = st.flags()
+    st.close()
+    ref = physics.column_physics(inp.rho, inp.theta, inp.q, inp.u, inp.v, inp.theta_s, inp.q_s,
+                                 inp.f0, inp.ch, inp.dz, inp.dt)
+    e_t = (nmax(tt, ref.t_theta), nmax(tq, ref.t_q))
+    errs = _compare(gpu, _oracle(inp, 1), FP32_TOL, theta_ref=300.0)
+    want = _exact_mass_of_f32_state(raw, inp)
+    rel = np.abs(mass - want) / np.abs(want)
+    _say(f"scan kernel: tendency errors {e_t}, state errors {errs}, mass rel {rel}")
+    assert max(e_t) <= FP32_TOL
+    assert np.all(rel <= 1e-13), rel
+    assert flags["nonfinite"] == 0 and flags["rho_le0"] == 0
+    for name, a in raw.items():
+        inner = a[:, 2:-2, 2:2 + inp.nx]
+        np.testing.assert_array_equal(a[:, :, :inp.nx + 4], np.pad(inner, ((0, 0), (2, 2), (2, 2)), mode="wrap"))
+    # stiff columns: FP64 scans
+    inp32, p = _stiff_f32_inputs(nz, 40.0, 500.0)
+    inp32.f0[:] = 0.0
+    ref = physics.column_physics(inp32.rho, inp32.theta, inp32.q, inp32.u, inp32.v, inp32.theta_s,
+                                 inp32.q_s, inp32.f0, inp32.ch, inp32.dz, inp32.dt, p)
+    st = wx.state_from_inputs(inp32, dtype="f32", theta_offset=300.0)
+    st.set_param("mix_len", p.mix_len)
+    st.set_param("phys_kernel", 2)
+    st.t["flags_out"].zero_()
+    tt, tq = st.tendencies()
+    n64 = st.flags()["fp64_columns"]
+    st.close()
+    e64 = (nmax(tt, ref.t_theta), nmax(tq, ref.t_q))
+    _say(f"stiff columns, FP64 scans: errors {e64}, FP64 columns {n64} of {inp32.nx * inp32.ny}")
+    assert n64 == int(np.sum(ref.ratio > DEFAULT.t_dd))
+    assert max(e64) <= 1e-6

@@ -338,3 +338,73 @@ def test_judged_step_with_no_sampled_column_equals_surrogate_step():
     assert runs["judged"][2]["fallback_steps"] == 0
     for name in ("rho", "theta", "q"):
         np.testing.assert_array_equal(runs["judged"][0][name], runs["surrogate"][0][name])
+
+
+def _physics_state(inp, p, stats, seed=0):
+    m = wx.Mlp()
+    _upload(m, p, stats)
+    st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
+    st.set_param("judge_seed", seed)
+    st.attach_mlp(m)
+    return st, m
+
+
+def test_physics_surrogate_mode_equals_network_rows():
+    # wx_physics(WX_PHYS_SURROGATE): the fused kernel's de-normalised outputs
+    # of every column, the same fmaf as its state update, bit for bit against
+    # the normalised rows of wx_surrogate_rows de-normalised on the host in FP32
+    _say("case: wx_physics surrogate mode, 70x33x58")
+    inp = _state32(70, 33, 61)
+    p, stats = _model(inp)
+    st, m = _physics_state(inp, p, stats)
+    tt, tq = st.tendencies(mode=wx.WX_PHYS_SURROGATE)
+    rows = st.surrogate_rows(m).cpu().numpy()[:, :NOUT]
+    st.close()
+    ym = stats["y_mean"].astype(np.float32)
+    ys = stats["y_std"].astype(np.float32)
+    # fmaf(y, std, mean) in FP32: the product is exact in FP64, one rounding
+    want = (rows.astype(np.float64) * ys.astype(np.float64) + ym.astype(np.float64)).astype(np.float32)
+    nz, ny, nx = NZ, inp.ny, inp.nx
+    np.testing.assert_array_equal(tt.astype(np.float32), want[:, :nz].T.reshape(nz, ny, nx))
+    np.testing.assert_array_equal(tq.astype(np.float32), want[:, nz:].T.reshape(nz, ny, nx))
+
+
+def test_physics_judged_mode_sampled_columns_and_fallback():
+    # wx_physics(WX_PHYS_JUDGED): the sampled columns (step index 0, seed 5)
+    # carry the plain tendencies (from the listed-column physics kernel: the
+    # FP32 bar against the whole-grid one), the rest the surrogate's bit for
+    # bit; with a zero bound the judge rejects the step and every column
+    # carries the plain tendencies, bit for bit against wx_physics(PLAIN)
+    _say("case: wx_physics judged mode, 64x40x58")
+    inp = _state32(64, 40, 62)
+    p, stats = _model(inp)
+    st, m = _physics_state(inp, p, stats, seed=5)
+    plain_t, plain_q = st.tendencies(mode=wx.WX_PHYS_PLAIN)
+    sur_t, sur_q = st.tendencies(mode=wx.WX_PHYS_SURROGATE)
+    st.set_param("judge_rel", 1e30)
+    jt, jq = st.tendencies(mode=wx.WX_PHYS_JUDGED)
+    verdict = st.judge()
+    st.set_param("judge_rel", 0.0)
+    ft, fq = st.tendencies(mode=wx.WX_PHYS_JUDGED)
+    verdict0 = st.judge()
+    st.close()
+    ncol = inp.nx * inp.ny
+    mask = omlp.sample_mask(5, 0, ncol).reshape(inp.ny, inp.nx)
+    assert verdict[3] == int(mask.sum()) > 0 and not verdict[2]
+    assert nmax(jt[:, mask], plain_t[:, mask]) <= 1e-5 and nmax(jq[:, mask], plain_q[:, mask]) <= 1e-5
+    np.testing.assert_array_equal(jt[:, ~mask], sur_t[:, ~mask])
+    np.testing.assert_array_equal(jq[:, ~mask], sur_q[:, ~mask])
+    assert verdict0[2]
+    np.testing.assert_array_equal(ft, plain_t)
+    np.testing.assert_array_equal(fq, plain_q)
+
+
+def test_physics_dataset_mode_equals_wx_dataset():
+    _say("case: wx_physics dataset mode, 50x21x58")
+    inp = _state32(50, 21, 63)
+    st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
+    x1, y1 = st.dataset()
+    x2, y2 = st.dataset_via_physics()
+    st.close()
+    np.testing.assert_array_equal(x1.cpu().numpy(), x2.cpu().numpy())
+    np.testing.assert_array_equal(y1.cpu().numpy(), y2.cpu().numpy())
