@@ -39,6 +39,29 @@ __device__ __forceinline__ E shfl_down_or(E x, int o, E fill) {
   const E y = __shfl_down(x, o, 64);
   return (int(threadIdx.x) & 63) + o < 64 ? y : fill;
 }
+// Lane k - o's value (the identity where there is none) for the six steps
+// of a wave-wide inclusive prefix scan built from DPP moves: steps 0-3 shift
+// by 1, 2, 4, 8 lanes inside each row of 16, step 4 broadcasts lane 15 of
+// rows 0 and 2 to rows 1 and 3, step 5 broadcasts lane 31 to rows 2 and 3.
+// After the six steps every lane has combined all lanes below it.
+template <int STEP>
+__device__ __forceinline__ float dpp_low(float x, float ident) {
+  constexpr int ctrl = STEP == 0 ? 0x111 : STEP == 1 ? 0x112 : STEP == 2 ? 0x114 : STEP == 3 ? 0x118
+                     : STEP == 4 ? 0x142 : 0x143;
+  constexpr int rows = STEP < 4 ? 0xf : STEP == 4 ? 0xa : 0xc;
+  return __builtin_amdgcn_update_dpp(ident, x, ctrl, rows, 0xf, false);
+}
+template <int STEP>
+__device__ __forceinline__ double dpp_low(double x, double ident) {
+  const long long xv = __double_as_longlong(x), iv = __double_as_longlong(ident);
+  constexpr int ctrl = STEP == 0 ? 0x111 : STEP == 1 ? 0x112 : STEP == 2 ? 0x114 : STEP == 3 ? 0x118
+                     : STEP == 4 ? 0x142 : 0x143;
+  constexpr int rows = STEP < 4 ? 0xf : STEP == 4 ? 0xa : 0xc;
+  const int lo = __builtin_amdgcn_update_dpp(int(iv), int(xv), ctrl, rows, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(int(iv >> 32), int(xv >> 32), ctrl, rows, 0xf, false);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
 __device__ __forceinline__ float rcp_e(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp_e(double x) { return 1.0 / x; }
 
@@ -47,12 +70,10 @@ __device__ __forceinline__ double rcp_e(double x) { return 1.0 / x; }
 // or above nz carry the identity.  Returns delta_theta, delta_q.
 template <typename E>
 __device__ __forceinline__ void scan_solve(bool act, E alo, E ahi, E diag, E rt, E rq, E &dth, E &dqq) {
-  // prefix product of the Moebius matrices (high level on the left)
+  // prefix product of the Moebius matrices (high level on the left), six
+  // DPP steps
   E p00 = act ? E(0) : E(1), p01 = act ? -ahi : E(0), p10 = act ? alo : E(0), p11 = act ? diag : E(1);
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const E q00 = shfl_up_or(p00, o, E(1)), q01 = shfl_up_or(p01, o, E(0));
-    const E q10 = shfl_up_or(p10, o, E(0)), q11 = shfl_up_or(p11, o, E(1));
+  auto mstep = [&](E q00, E q01, E q10, E q11) {
     const E n00 = p00 * q00 + p01 * q10, n01 = p00 * q01 + p01 * q11;
     const E n10 = p10 * q00 + p11 * q10, n11 = p10 * q01 + p11 * q11;
     const E big = fmax(fmax(fabs(n00), fabs(n01)), fmax(fabs(n10), fabs(n11)));
@@ -61,19 +82,23 @@ __device__ __forceinline__ void scan_solve(bool act, E alo, E ahi, E diag, E rt,
     p01 = n01 * s;
     p10 = n10 * s;
     p11 = n11 * s;
-  }
+  };
+#define WX_MSTEP(S) mstep(dpp_low<S>(p00, E(1)), dpp_low<S>(p01, E(0)), dpp_low<S>(p10, E(0)), dpp_low<S>(p11, E(1)))
+  WX_MSTEP(0); WX_MSTEP(1); WX_MSTEP(2); WX_MSTEP(3); WX_MSTEP(4); WX_MSTEP(5);
+#undef WX_MSTEP
   const E cp = act ? p01 / p11 : E(0);
   const E cpm = shfl_up_or(cp, 1, E(0));
   const E inv = act ? rcp_e(diag + alo * cpm) : E(0);
   // d'_k = A_k d'_{k-1} + B_k: affine prefix scan (A shared by theta and q)
   E A = act ? alo * inv : E(1), Bt = act ? rt * inv : E(0), Bq = act ? rq * inv : E(0);
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const E la = shfl_up_or(A, o, E(1)), lt = shfl_up_or(Bt, o, E(0)), lq = shfl_up_or(Bq, o, E(0));
+  auto astep = [&](E la, E lt, E lq) {
     Bt = A * lt + Bt;
     Bq = A * lq + Bq;
     A = A * la;
-  }
+  };
+#define WX_ASTEP(S) astep(dpp_low<S>(A, E(1)), dpp_low<S>(Bt, E(0)), dpp_low<S>(Bq, E(0)))
+  WX_ASTEP(0); WX_ASTEP(1); WX_ASTEP(2); WX_ASTEP(3); WX_ASTEP(4); WX_ASTEP(5);
+#undef WX_ASTEP
   // delta_k = -c'_k delta_{k+1} + d'_k: affine suffix scan from the lid
   E C = act ? -cp : E(1), Dt = act ? Bt : E(0), Dq = act ? Bq : E(0);
 #pragma unroll
