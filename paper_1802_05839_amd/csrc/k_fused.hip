@@ -7,15 +7,16 @@
 // Work split (8 waves, 512 threads):
 //   features  thread (column = t % 128, part = t / 128); a wave covers 64
 //             consecutive columns of one field level, so state reads coalesce;
-//             part p forms levels [15 p, 15 p + 15) of the five profiles (part
-//             3 also the surface values and the padding);
+//             part p forms levels [16 p, 16 p + 16) of the five profiles (part
+//             3 also the surface values and the padding), two features per
+//             4-byte LDS store;
 //   layers    wave w owns hidden units [64 w, 64 w + 64) of the two hidden
 //             layers (2 x 4 tiles of v_mfma_f32_32x32x16_bf16, the shape that
 //             runs at the full matrix-core rate on gfx950) and a 32-output by
 //             64-sample block of the last; the weights are the first MFMA
 //             operand (streamed from global memory in fragment order, so each
-//             load is one 1 KiB run per wavefront, L2-resident, 0.98 MB, one
-//             k step ahead) and the activations the second (from LDS, the
+//             load is one 1 KiB run per wavefront, L2-resident, 0.98 MB, two
+//             k steps ahead) and the activations the second (from LDS, the
 //             fragments of a k step read before its MFMAs), so a lane ends
 //             with four consecutive units of one sample and stores them as
 //             one 8-byte LDS write;
@@ -57,43 +58,47 @@ static_assert(YNORM_OFF % 16 == 0 && YNORM_OFF + MLP_NOUTP * 8 <= LDS_BYTES, "ta
 constexpr double kThetaRef = 300.0;      // theta features are theta - 300 K
 constexpr int kNZ = MLP_NZ;              // levels (the network is built for 58)
 constexpr int kHalf = (kNZ + 1) / 2;     // levels per thread in the update
-constexpr int kPartLev = 15;             // levels per thread in the feature phase
+constexpr int kPartLev = 16;             // levels per thread in the feature phase (even: features go in pairs)
 static_assert(4 * kPartLev >= kNZ, "four parts must cover the column");
 
 // acc[y][x] += W(units n0 + 32 y.., k) X(samples s0 + 32 x.., k) over
 // k = 0..K-1 in steps of 16 (ascending, as in the stand-alone GEMM), on
 // v_mfma_f32_32x32x16_bf16.  The weights are the first operand (global, in
 // fragment order: the 32 x 16 block (R, S) of the [N][K] matrix is 512
-// contiguous values, so a wavefront reads it as one 1 KiB run; one 32-wide k
-// step fetched ahead), the activations the second (LDS [samples][lda], the
+// contiguous values, so a wavefront reads it as one 1 KiB run; fetched two
+// 32-wide k steps ahead, so an L2 round trip overlaps two steps of MFMAs),
+// the activations the second (LDS [samples][lda], the
 // fragments of a k step read before its MFMAs).  A lane feeds row (or column)
 // lane % 32 at k = 8 (lane / 32)..+7.
-template <int NU, int NS>
+template <int NU, int NS, int K>
 __device__ __forceinline__ void tile_gemm(f32x16 (&acc)[NU][NS], const uint16_t *X, int lda, int s0,
-                                          const uint16_t *W, int n0, int K, int lane) {
+                                          const uint16_t *W, int n0, int lane) {
+  constexpr int ks = K >> 4;                              // 16-wide k blocks per row block
+  constexpr int NSTEP = K / 32;                           // 32-wide k steps
+  constexpr int D = 2;                                    // steps the weights are fetched ahead
+  static_assert(K % 32 == 0, "K must be a multiple of 32");
   const int kl = 8 * (lane >> 5), rl = lane & 31;
-  const int ks = K >> 4;                                  // 16-wide k blocks per row block
   const uint16_t *wp = W + (size_t)(n0 >> 5) * ks * 512 + lane * 8;
   const uint16_t *xp = X + (s0 + rl) * lda + kl;
-  bf16x8 wcur[2][NU], wnext[2][NU];
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int y = 0; y < NU; ++y)
-      wcur[h][y] = *reinterpret_cast<const bf16x8 *>(wp + (size_t)(y * ks + h) * 512);
-#pragma unroll 1
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    const int kn = k0 + 32 < K ? k0 + 32 : k0;   // last step reloads its own slice
+  bf16x8 wr[D + 1][2][NU];
+  auto wload = [&](int s) {
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int y = 0; y < NU; ++y)
-        wnext[h][y] = *reinterpret_cast<const bf16x8 *>(wp + (size_t)(y * ks + (kn >> 4) + h) * 512);
+        wr[s % (D + 1)][h][y] = *reinterpret_cast<const bf16x8 *>(wp + (size_t)(y * ks + 2 * s + h) * 512);
+  };
+#pragma unroll
+  for (int s = 0; s < D; ++s)
+    if (s < NSTEP) wload(s);
+#pragma unroll
+  for (int s = 0; s < NSTEP; ++s) {
+    if (s + D < NSTEP) wload(s + D);
     bf16x8 xf[2][NS];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int x = 0; x < NS; ++x) xf[h][x] = *reinterpret_cast<const bf16x8 *>(xp + x * 32 * lda + k0 + 16 * h);
+      for (int x = 0; x < NS; ++x) xf[h][x] = *reinterpret_cast<const bf16x8 *>(xp + x * 32 * lda + 32 * s + 16 * h);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -101,11 +106,7 @@ __device__ __forceinline__ void tile_gemm(f32x16 (&acc)[NU][NS], const uint16_t 
       for (int y = 0; y < NU; ++y)
 #pragma unroll
         for (int x = 0; x < NS; ++x)
-          acc[y][x] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wcur[h][y], xf[h][x], acc[y][x], 0, 0, 0);
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int y = 0; y < NU; ++y) wcur[h][y] = wnext[h][y];
+          acc[y][x] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[s % (D + 1)][h][y], xf[h][x], acc[y][x], 0, 0, 0);
   }
 }
 
@@ -126,8 +127,8 @@ __device__ __forceinline__ void store_hidden(const f32x16 (&acc)[NU][NS], const 
         const float v0 = acc[y][x][4 * q] + bn.x, v1 = acc[y][x][4 * q + 1] + bn.y;
         const float v2 = acc[y][x][4 * q + 2] + bn.z, v3 = acc[y][x][4 * q + 3] + bn.w;
         uint2 pk;
-        pk.x = uint32_t(f2bf(v0 > 0.f ? v0 : 0.f)) | (uint32_t(f2bf(v1 > 0.f ? v1 : 0.f)) << 16);
-        pk.y = uint32_t(f2bf(v2 > 0.f ? v2 : 0.f)) | (uint32_t(f2bf(v3 > 0.f ? v3 : 0.f)) << 16);
+        pk.x = f2bf2(v0 > 0.f ? v0 : 0.f, v1 > 0.f ? v1 : 0.f);
+        pk.y = f2bf2(v2 > 0.f ? v2 : 0.f, v3 > 0.f ? v3 : 0.f);
         *reinterpret_cast<uint2 *>(H + (32 * x + (lane & 31)) * HLD + n) = pk;
       }
     }
@@ -149,70 +150,89 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
   float *Y = reinterpret_cast<float *>(lds);
 
   // ---- feature rows -> X ---------------------------------------------------
+  // thread (column = t % 128, part = t / 128); part p builds levels
+  // [16 p, 16 p + 16) of the five profiles (part 3 also the surface values
+  // and the padding).  Its loads (its levels and the one below, about 100
+  // independent loads) are issued before the normalisation constants are
+  // staged, so the two global round trips overlap.
   float2 *xn = reinterpret_cast<float2 *>(lds + XNORM_OFF);
+  const int fcol = tid & (FT - 1), part = tid >> 7;
+  int c = -1;
+  {
+    const int r = r0 + fcol;
+    if (r < nrows) c = rows_mode ? (a.list ? a.list[r] : r) : a.c0 + r;
+    if (c >= nx * a.g.ny) c = -1;                    // not a column: zero row
+  }
+  const int kb = part * kPartLev, ke = min(kNZ, kb + kPartLev);
+  // slot n holds level kb - 1 + n (slot 0: the level below, none for part 0)
+  float th[kPartLev + 1], qq[kPartLev + 1], ul[kPartLev + 1], uh[kPartLev + 1], vl[kPartLev + 1],
+      vh[kPartLev + 1];
+  float srf[4] = {0.f, 0.f, 0.f, 0.f};
+  if (c >= 0) {
+    const int i = c % nx, j = c / nx;
+    const unsigned g0 = a.g.origin + unsigned(i) + unsigned(j) * a.g.sj;
+    const unsigned sk = a.g.sk, sj = a.g.sj;
+#pragma unroll
+    for (int n = 0; n <= kPartLev; ++n) {
+      const int k = kb - 1 + n;
+      if (k >= 0 && k < ke) {
+        const unsigned g = g0 + unsigned(k) * sk;
+        th[n] = ldg(a.th, g);
+        qq[n] = ldg(a.q, g);
+        ul[n] = ldg(a.u, g - 1);
+        uh[n] = ldg(a.u, g);
+        vl[n] = ldg(a.v, g - sj);
+        vh[n] = ldg(a.v, g);
+      }
+    }
+    if (part == 3) {
+      srf[0] = ldg(a.th_s, unsigned(c));
+      srf[1] = ldg(a.q_s, unsigned(c));
+      srf[2] = ldg(a.f0, unsigned(c));
+      srf[3] = ldg(a.ch, unsigned(c));
+    }
+  }
   for (int f = tid; f < MLP_KIN; f += FTHREADS) xn[f] = make_float2(a.xmean[f], a.xinvstd[f]);
   __syncthreads();
   {
-    const int col = tid & (FT - 1), part = tid >> 7;
-    const int r = r0 + col;
-    int c = -1;
-    if (r < nrows) c = rows_mode ? (a.list ? a.list[r] : r) : a.c0 + r;
-    if (c >= nx * a.g.ny) c = -1;                    // not a column: zero row
-    uint16_t *xr = X + col * XLD;
-    auto put = [&](int f, float x) {
-      const float2 mn = xn[f];
-      xr[f] = f2bf((x - mn.x) * mn.y);
+    uint16_t *xr = X + fcol * XLD;
+    // normalised BF16 pair (f, f + 1), f even: one 4-byte LDS store
+    auto put2 = [&](int f, float x0, float x1) {
+      const float2 m0 = xn[f], m1 = xn[f + 1];
+      *reinterpret_cast<uint32_t *>(xr + f) = f2bf2((x0 - m0.x) * m0.y, (x1 - m1.x) * m1.y);
     };
     if (c < 0) {
-      for (int f = part; f < MLP_KIN; f += 4) xr[f] = 0;
+      for (int f = 2 * part; f < MLP_KIN; f += 8) *reinterpret_cast<uint32_t *>(xr + f) = 0u;
     } else {
-      const int i = c % nx, j = c / nx;
-      const unsigned g0 = a.g.origin + unsigned(i) + unsigned(j) * a.g.sj;
-      const unsigned sk = a.g.sk, sj = a.g.sj;
-      // part p builds levels [15 p, 15 p + 15) of all five profiles: it
-      // first loads its levels (and the one below) into registers, so about
-      // 96 independent loads are in flight, then forms the features
-      const int kb = part * kPartLev, ke = min(kNZ, kb + kPartLev);
-      const int k0 = kb > 0 ? kb - 1 : 0;
-      float th[kPartLev + 1], qq[kPartLev + 1], ul[kPartLev + 1], uh[kPartLev + 1], vl[kPartLev + 1],
-          vh[kPartLev + 1];
-#pragma unroll
-      for (int n = 0; n <= kPartLev; ++n) {
-        const int k = k0 + n;
-        if (k < ke) {
-          const unsigned g = g0 + unsigned(k) * sk;
-          th[n] = ldg(a.th, g);
-          qq[n] = ldg(a.q, g);
-          ul[n] = ldg(a.u, g - 1);
-          uh[n] = ldg(a.u, g);
-          vl[n] = ldg(a.v, g - sj);
-          vh[n] = ldg(a.v, g);
-        }
-      }
       LevelVals prev{};
+      float fe[5];
 #pragma unroll
       for (int n = 0; n <= kPartLev; ++n) {
-        const int k = k0 + n;
+        const int k = kb - 1 + n;
         if (k >= ke) break;
+        if (k < 0) continue;
         LevelVals cur;
         cur.th = float(double(th[n]) + a.theta_off - kThetaRef);
         cur.q = qq[n];
         cur.u = (ul[n] + uh[n]) * 0.5f;
         cur.v = (vl[n] + vh[n]) * 0.5f;
-        if (k >= kb) {
+        if (n >= 1) {
           float fv[5];
           level_features(k, cur, prev, fv);
+          if (n & 1) {
 #pragma unroll
-          for (int q5 = 0; q5 < 5; ++q5) put(q5 * kNZ + k, fv[q5]);
+            for (int q5 = 0; q5 < 5; ++q5) fe[q5] = fv[q5];
+          } else {
+#pragma unroll
+            for (int q5 = 0; q5 < 5; ++q5) put2(q5 * kNZ + k - 1, fe[q5], fv[q5]);
+          }
         }
         prev = cur;
       }
       if (part == 3) {
-        put(5 * kNZ, float(double(ldg(a.th_s, unsigned(c))) + a.theta_off - kThetaRef));
-        put(5 * kNZ + 1, ldg(a.q_s, unsigned(c)));
-        put(5 * kNZ + 2, ldg(a.f0, unsigned(c)));
-        put(5 * kNZ + 3, ldg(a.ch, unsigned(c)));
-        for (int f = 5 * kNZ + 4; f < MLP_KIN; ++f) xr[f] = 0;
+        put2(5 * kNZ, float(double(srf[0]) + a.theta_off - kThetaRef), srf[1]);
+        put2(5 * kNZ + 2, srf[2], srf[3]);
+        for (int f = 5 * kNZ + 4; f < MLP_KIN; f += 2) *reinterpret_cast<uint32_t *>(xr + f) = 0u;
       }
     }
   }
@@ -227,7 +247,7 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
     for (int x = 0; x < 4; ++x)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[y][x][r] = 0.f;
-  tile_gemm<2, 4>(acc, X, XLD, 0, a.w1, n0, MLP_KIN, lane);
+  tile_gemm<2, 4, MLP_KIN>(acc, X, XLD, 0, a.w1, n0, lane);
   __syncthreads();   // every wave has read X
   store_hidden<2, 4>(acc, a.b1, n0, H, lane);
   __syncthreads();
@@ -239,7 +259,7 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
     for (int x = 0; x < 4; ++x)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[y][x][r] = 0.f;
-  tile_gemm<2, 4>(acc, H, HLD, 0, a.w2, n0, MLP_NHID, lane);
+  tile_gemm<2, 4, MLP_NHID>(acc, H, HLD, 0, a.w2, n0, lane);
   __syncthreads();
   store_hidden<2, 4>(acc, a.b2, n0, H, lane);
   __syncthreads();
@@ -252,7 +272,7 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc3[0][x][r] = 0.f;
   const int o3 = 32 * (wave & 3), s3 = 64 * (wave >> 2);
-  tile_gemm<1, 2>(acc3, H, HLD, s3, a.w3, o3, MLP_NHID, lane);
+  tile_gemm<1, 2, MLP_NHID>(acc3, H, HLD, s3, a.w3, o3, lane);
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -275,30 +295,30 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
     }
     return;
   }
-  const int col = tid & (FT - 1), part = tid >> 7;
+  const int col = fcol;
   if (r0 + col >= nrows) return;
-  const int c = a.c0 + r0 + col;
-  if (a.judged && judge_sampled(a.seed, a.t, unsigned(c), a.rate)) return;
+  const int cu = a.c0 + r0 + col;
+  if (a.judged && judge_sampled(a.seed, a.t, unsigned(cu), a.rate)) return;
   const int ny = a.g.ny;
-  const int i = c % nx, j = c / nx;
+  const int i = cu % nx, j = cu / nx;
   const unsigned g0 = a.g.origin + unsigned(i) + unsigned(j) * a.g.sj;
   const int di = i < 2 ? nx : (i >= nx - 2 ? -nx : 0);
   const int dj = j < 2 ? ny * int(a.g.sj) : (j >= ny - 2 ? -ny * int(a.g.sj) : 0);
   float *fld = part < 2 ? a.th : a.q;
-  const int kb = (part & 1) ? kHalf : 0;
+  const int kbu = (part & 1) ? kHalf : 0;
   const int nk = (part & 1) ? kNZ - kHalf : kHalf;
-  const int ob = (part < 2 ? 0 : kNZ) + kb;
+  const int ob = (part < 2 ? 0 : kNZ) + kbu;
   const float *yr = Y + col * YLD + ob;
   if (a.tend_t) {
     // tendency mode: d(theta)/dt or d(q)/dt at (i, j, k), i fastest
     float *tf = part < 2 ? a.tend_t : a.tend_q;
     for (int k = 0; k < nk; ++k) {
       const float2 ms = yn[ob + k];
-      stg(tf, unsigned((kb + k) * ny + j) * unsigned(nx) + unsigned(i), fmaf(yr[k], ms.y, ms.x));
+      stg(tf, unsigned((kbu + k) * ny + j) * unsigned(nx) + unsigned(i), fmaf(yr[k], ms.y, ms.x));
     }
     return;
   }
-  const unsigned gb = g0 + unsigned(kb) * a.g.sk;
+  const unsigned gb = g0 + unsigned(kbu) * a.g.sk;
   // all loads before any store: the stores may alias the loads, so a mixed
   // order would serialise one HBM round trip per level
   float old[kHalf];

@@ -16,12 +16,16 @@ constexpr int MLP_NHID = 512;
 constexpr int MLP_NOUT = 2 * MLP_NZ;       // 116 outputs
 constexpr int MLP_NOUTP = 128;             // padded output width
 
-// FP32 -> BF16 bits, round to nearest even (finite inputs).
-__device__ __forceinline__ uint16_t f2bf(float x) {
-  uint32_t b = __float_as_uint(x);
-  b += 0x7FFFu + ((b >> 16) & 1u);
-  return uint16_t(b >> 16);
+// FP32 -> BF16 bits, round to nearest even, on the conversion instruction of
+// the target (v_cvt_pk_bf16_f32; NaN stays NaN); f2bf2 packs two values, the
+// first in the low half.
+typedef float wx_f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 wx_bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t f2bf2(float lo, float hi) {
+  const wx_f32x2 v = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, wx_bf16x2));
 }
+__device__ __forceinline__ uint16_t f2bf(float x) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(x)); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 
 // Position of element (r, c) of a [N][K] BF16 matrix in matrix-core fragment
