@@ -136,6 +136,9 @@ __device__ __forceinline__ void store_hidden(const f32x16 (&acc)[NU][NS], const 
 
 __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[LDS_BYTES];
+  // the three bias vectors, staged with the feature loads: read from LDS in
+  // the layer epilogues, they never wait behind a global round trip
+  __shared__ __attribute__((aligned(16))) float s_bias[2 * MLP_NHID + MLP_NOUTP];
   if (a.fallback && *a.fallback) return;
   const bool rows_mode = a.rows_out != nullptr;
   const int nrows = rows_mode ? (a.n_list ? min(*a.n_list, a.cap) : a.cap) : a.ncols;
@@ -193,6 +196,11 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
     }
   }
   for (int f = tid; f < MLP_KIN; f += FTHREADS) xn[f] = make_float2(a.xmean[f], a.xinvstd[f]);
+  for (int n = tid; n < MLP_NHID; n += FTHREADS) {
+    s_bias[n] = a.b1[n];
+    s_bias[MLP_NHID + n] = a.b2[n];
+  }
+  if (tid < MLP_NOUTP) s_bias[2 * MLP_NHID + tid] = a.b3[tid];
   __syncthreads();
   {
     uint16_t *xr = X + fcol * XLD;
@@ -249,7 +257,7 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
       for (int r = 0; r < 16; ++r) acc[y][x][r] = 0.f;
   tile_gemm<2, 4, MLP_KIN>(acc, X, XLD, 0, a.w1, n0, lane);
   __syncthreads();   // every wave has read X
-  store_hidden<2, 4>(acc, a.b1, n0, H, lane);
+  store_hidden<2, 4>(acc, s_bias, n0, H, lane);
   __syncthreads();
 
   // ---- hidden layer 2: H = relu(H W2^T + b2) ---------------------------------
@@ -261,7 +269,7 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
       for (int r = 0; r < 16; ++r) acc[y][x][r] = 0.f;
   tile_gemm<2, 4, MLP_NHID>(acc, H, HLD, 0, a.w2, n0, lane);
   __syncthreads();
-  store_hidden<2, 4>(acc, a.b2, n0, H, lane);
+  store_hidden<2, 4>(acc, s_bias + MLP_NHID, n0, H, lane);
   __syncthreads();
 
   // ---- output layer: Y = H W3^T + b3 (normalised tendencies) -----------------
@@ -280,7 +288,7 @@ __global__ __launch_bounds__(FTHREADS) void k_surrogate_fused(FusedArgs a) {
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) Y[(s3 + 32 * x + (lane & 31)) * YLD + o + c] = acc3[0][x][4 * q + c] + a.b3[o + c];
+      for (int c = 0; c < 4; ++c) Y[(s3 + 32 * x + (lane & 31)) * YLD + o + c] = acc3[0][x][4 * q + c] + s_bias[2 * MLP_NHID + o + c];
   }
   float2 *yn = reinterpret_cast<float2 *>(lds + YNORM_OFF);
   if (!rows_mode)

@@ -80,14 +80,87 @@ struct GemmArgs {
   uint16_t *C2;                // EP_MASK_F32_BF16: BF16 copy of the output
 };
 
+// Tile (m0, n0, split) of this block.  Blocks are dealt round-robin to the 8
+// XCDs; the remap gives each XCD a contiguous run of the linear order (n
+// fastest, then m, then the split), so an XCD's blocks share their A rows and
+// K range in its L2 and the blocks running together spread over all n tiles.
+struct GemmTile {
+  int m0, n0, z;
+};
+__device__ __forceinline__ GemmTile gemm_tile() {
+  const int nbn = gridDim.x, nbm = gridDim.y;
+  const int lin = blockIdx.x + nbn * (blockIdx.y + nbm * blockIdx.z);
+  const int L = xcd_remap(lin, nbn * nbm * gridDim.z);
+  GemmTile t;
+  t.n0 = (L % nbn) * GBN;
+  t.m0 = ((L / nbn) % nbm) * GBM;
+  t.z = L / (nbn * nbm);
+  return t;
+}
+
+// Output of one wave's 32 x 32 tile (origin m0 + wm, n0 + wn).
+template <int EP>
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs &a, const f32x16 &acc, int m0, int n0, int z, int wm,
+                                              int wn, int lane) {
+  // accumulator r of the lane holds C[8 (r / 4) + 4 (lane / 32) + r % 4][lane % 32]
+  // of the wave's 32 x 32 tile.  Everything the lane reads (its column's bias,
+  // the masks of its 16 rows) is read before its first store: a read after a
+  // store that may alias it would wait for a full memory round trip per row.
+  const int n = n0 + wn + (lane & 31);
+  const bool nok = n < a.N;
+  float bias = 0.f;
+  if ((EP == EP_BIAS_F32 || EP == EP_BIAS_RELU_BF16) && nok) bias = a.bias[n];
+  uint16_t mk[16];
+  if (EP == EP_MASK_F32_BF16) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      mk[r] = (m < a.M && nok) ? a.mask[(size_t)m * a.ldc + n] : uint16_t(0);
+    }
+  }
+  auto emit = [&](int r, int m) {
+    float v = acc[r];
+    if (EP == EP_F32) {
+      static_cast<float *>(a.C)[(size_t)m * a.ldc + n] = v;
+    } else if (EP == EP_BIAS_F32) {
+      static_cast<float *>(a.C)[(size_t)m * a.ldc + n] = v + bias;
+    } else if (EP == EP_BIAS_RELU_BF16) {
+      v += bias;
+      static_cast<uint16_t *>(a.C)[(size_t)m * a.ldc + n] = f2bf(v > 0.f ? v : 0.f);
+    } else if (EP == EP_MASK_F32_BF16) {
+      // hidden-layer gradient: (upstream @ W) * (h > 0), FP32 and its BF16 operand
+      const size_t o = (size_t)m * a.ldc + n;
+      const float g = bf2f(mk[r]) > 0.f ? v : 0.f;
+      static_cast<float *>(a.C)[o] = g;
+      a.C2[o] = f2bf(g);
+    } else {
+      static_cast<float *>(a.C)[z * a.split_stride + (size_t)m * a.ldc + n] = v;
+    }
+  };
+  // a wave whose 32 x 32 tile lies inside C stores with no per-row test:
+  // divergent per-row branches would make every store wait for the one
+  // before it (the vector-memory counter also counts stores)
+  if (m0 + wm + 32 <= a.M && n0 + wn + 32 <= a.N) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) emit(r, m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3));
+  } else {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      if (m < a.M && nok) emit(r, m);
+    }
+  }
+}
+
 template <bool AK, bool BK_, int EP>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t sA[2][GBM * GLD];
   __shared__ __attribute__((aligned(16))) uint16_t sB[2][GBN * GLD];
-  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
-  const int kb = blockIdx.z * a.k_split;
+  const GemmTile tile = gemm_tile();
+  const int m0 = tile.m0, n0 = tile.n0;
+  const int kb = tile.z * a.k_split;
   const int ke = min(a.K, kb + a.k_split);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   f32x16 acc;
 #pragma unroll
@@ -116,31 +189,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
     }
     __syncthreads();
   }
-  // accumulator r of the lane holds C[8 (r / 4) + 4 (lane / 32) + r % 4][lane % 32]
-  // of the wave's 32 x 32 tile
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int m = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    const int n = n0 + wn + (lane & 31);
-    if (m >= a.M || n >= a.N) continue;
-    float v = acc[r];
-    if (EP == EP_F32) {
-      static_cast<float *>(a.C)[(size_t)m * a.ldc + n] = v;
-    } else if (EP == EP_BIAS_F32) {
-      static_cast<float *>(a.C)[(size_t)m * a.ldc + n] = v + a.bias[n];
-    } else if (EP == EP_BIAS_RELU_BF16) {
-      v += a.bias[n];
-      static_cast<uint16_t *>(a.C)[(size_t)m * a.ldc + n] = f2bf(v > 0.f ? v : 0.f);
-    } else if (EP == EP_MASK_F32_BF16) {
-      // hidden-layer gradient: (upstream @ W) * (h > 0), FP32 and its BF16 operand
-      const size_t o = (size_t)m * a.ldc + n;
-      const float g = bf2f(a.mask[o]) > 0.f ? v : 0.f;
-      static_cast<float *>(a.C)[o] = g;
-      a.C2[o] = f2bf(g);
-    } else {
-      static_cast<float *>(a.C)[blockIdx.z * a.split_stride + (size_t)m * a.ldc + n] = v;
-    }
-  }
+  gemm_epilogue<EP>(a, acc, m0, n0, tile.z, wm, wn, lane);
 }
 
 // Loss and output gradient: d = 2 (y - t) / (B * nout) on the first nout
@@ -202,7 +251,22 @@ __device__ __forceinline__ void colsum_block(const ColsumArgs &a, int b, const A
   float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
   if (J.vec) {
     if (c < J.cols) {
-      for (int r = g; r < a.rows; r += 64) {
+      // rows in batches of 8: the loads of a batch are in flight together,
+      // the sums still run over r in order
+      int r = g;
+      for (; r + 7 * 64 < a.rows; r += 8 * 64) {
+        float4 x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = *reinterpret_cast<const float4 *>(J.a + (size_t)(r + 64 * u) * J.lda + c);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          s0 += x[u].x;
+          s1 += x[u].y;
+          s2 += x[u].z;
+          s3 += x[u].w;
+        }
+      }
+      for (; r < a.rows; r += 64) {
         const float4 x = *reinterpret_cast<const float4 *>(J.a + (size_t)r * J.lda + c);
         s0 += x.x;
         s1 += x.y;
@@ -236,25 +300,41 @@ __device__ __forceinline__ void colsum_block(const ColsumArgs &a, int b, const A
   }
 }
 
-// Weight gradients as ordered sums of split-K slices (first blocks), then the
-// bias-gradient and loss column sums (remaining blocks); with adam_on each
-// gradient element also takes its Adam update right where it is formed.
+// The bias-gradient and loss column sums (first blocks: each sums all batch
+// rows of 16 columns, the longest blocks of the launch, so they start first),
+// then the weight gradients as ordered sums of split-K slices; with adam_on
+// each gradient element also takes its Adam update right where it is formed.
 __global__ void __launch_bounds__(256) k_grad_finish(GradFinishArgs a) {
   int b = blockIdx.x;
+  int csb = 0;
+  for (int j = 0; j < a.cs.njobs; ++j) csb += a.cs.job[j].blocks;
+  if (b < csb) {
+    colsum_block(a.cs, b, a.adam_on ? &a.adam : nullptr, a.cs_seg);
+    return;
+  }
+  b -= csb;
   for (int j = 0; j < a.nsj; ++j) {
     const SplitJob &J = a.sj[j];
     if (b < J.blocks) {
       const int i = b * 256 + threadIdx.x;
       if (i >= J.n) return;
+      // slices in batches of 8 loads in flight, summed in slice order
       float s = 0.f;
-      for (int p = 0; p < J.nsplit; ++p) s += J.part[p * J.stride + i];
+      int p = 0;
+      for (; p + 8 <= J.nsplit; p += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = J.part[(p + u) * J.stride + i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+      }
+      for (; p < J.nsplit; ++p) s += J.part[p * J.stride + i];
       J.out[i] = s;
       if (a.adam_on) adam_elem(a.adam, a.adam.seg[a.sj_seg[j]], size_t(i), s);
       return;
     }
     b -= J.blocks;
   }
-  colsum_block(a.cs, b, a.adam_on ? &a.adam : nullptr, a.cs_seg);
 }
 
 // Adam over the six parameter tensors in one launch (element i of the

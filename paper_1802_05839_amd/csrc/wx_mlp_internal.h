@@ -141,8 +141,8 @@ struct ColsumArgs {
   int njobs, rows;
 };
 
-// The end of the backward pass in one launch: the weight gradients as ordered
-// sums of their split-K partial slices, then the column sums of ColsumArgs.
+// The end of the backward pass in one launch: the column sums of ColsumArgs,
+// then the weight gradients as ordered sums of their split-K partial slices.
 struct SplitJob {
   const float *part;   // [nsplit][stride]
   int nsplit;
