@@ -96,11 +96,14 @@ typedef enum wx_param {
                                 column, column kept in registers (one wave per
                                 SIMD; nz 16 and 58); 1 the same, column read
                                 again on the way down (two waves per SIMD);
-                                0 and 1 give the same bits; 2 wave per column,
-                                the k-recurrences (elimination, back
-                                substitution, optical depth) as scans over the
-                                lanes (nz <= 64; same arithmetic in another
-                                order: equal within rounding) [0]                */
+                                2 wave per column, the k-recurrences
+                                (elimination, back substitution, optical
+                                depth) as scans over the lanes (nz <= 64; same
+                                arithmetic in another order: equal within
+                                rounding); 3 as 0, each level fetched with two
+                                16-byte loads per lane through LDS (field
+                                pointers 16-byte aligned); 0, 1 and 3 give the
+                                same bits [0]                                    */
   WX_PARAM_STAGE_TILE = 13,  /* tile of the RK3 stage kernel (columns x rows), same
                                 results bit for bit: 0 64x8, 1 64x4, 2 64x12,
                                 3 32x16, 4 128x4, 5 64x8 with each face value,

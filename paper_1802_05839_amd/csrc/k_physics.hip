@@ -258,9 +258,23 @@ __device__ __forceinline__ void block_finish(const PhysArgs<float> *ap, double *
 // earlier, so they come from the caches, not HBM) through a prefetch ring of
 // its own.  That halves the registers, so two waves share each SIMD and one
 // wave's loads overlap the other's arithmetic.
-template <int NZ, int MODE, bool KEEP>
+//
+// WIDE (with KEEP) is the variant whose upward pass fetches a level with two
+// 16-byte loads per lane instead of seven 4-byte ones: a wave loads its row's
+// columns i0-2 .. i0+65 of rho, theta, q, u, v and of v in row j-1 (17
+// aligned 16-byte chunks each), writes them to its own LDS slot and reads its
+// column back (LDS runs a wave's accesses in order: no barrier).  At one wave
+// per SIMD the number of vector-memory instructions a wave keeps in flight,
+// not their size, bounds the bandwidth, so 16-byte loads move about four
+// times as much.  Whole waves take part in the loads: a lane past the grid
+// edge works on column nx-1 (the same values and the same stores as the lane
+// that owns it) and counts nothing.
+template <int NZ, int MODE, bool KEEP, bool WIDE = false>
 __global__ __launch_bounds__(256, KEEP ? 1 : 2) void k_physics_f32(PhysArgs<float> a) {
+  static_assert(!WIDE || KEEP, "the wide upward pass keeps the column in registers");
   constexpr int PF = KEEP ? 8 : 4;     // levels prefetched ahead (two waves per SIMD need half)
+  constexpr int WROW = 68, WSLOT = WIDE ? 6 * WROW : 1;   // floats per field row and per wave slot
+  __shared__ __attribute__((aligned(16))) float s_w[4][WSLOT];
   extern __shared__ float s_c[];          // [NZ][256]
   // the per-level constants, staged once per block: read through LDS they
   // never wait behind the kernel's own global stores (on this target the
@@ -278,15 +292,18 @@ __global__ __launch_bounds__(256, KEEP ? 1 : 2) void k_physics_f32(PhysArgs<floa
   __syncthreads();
   const int nbx = (a.g.nx + 63) / 64;
   const int L = xcd_remap(blockIdx.x, gridDim.x);   // j-neighbours share an XCD's L2 (the v row below)
-  const int i = (L % nbx) * 64 + tx, j = (L / nbx) * 4 + ty;
+  const int i0 = (L % nbx) * 64, i = i0 + tx, j = (L / nbx) * 4 + ty;
   const bool active = (i < a.g.nx) && (j < a.g.ny);
+  // WIDE: the whole wave of a row inside the grid runs, on column min(i, nx-1)
+  const bool run = WIDE ? (j < a.g.ny) : active;
+  const int ic = WIDE ? min(i, a.g.nx - 1) : i;
   Kahan mass[3];
   Counters cnt;
   int fp64 = 0;
-  if (active) {
+  if (run) {
     const unsigned sj = a.g.sj, sk = a.g.sk;
-    const unsigned g0 = a.g.origin + unsigned(i) + unsigned(j) * sj;
-    const int col = i + a.g.nx * j;
+    const unsigned g0 = a.g.origin + unsigned(ic) + unsigned(j) * sj;
+    const int col = ic + a.g.nx * j;
     const float dt = a.dt, kmin = a.kmin, l2 = a.l2;
 
     // ---- upward pass: build row k from a one-level look-ahead, eliminate
@@ -307,12 +324,65 @@ __global__ __launch_bounds__(256, KEEP ? 1 : 2) void k_physics_f32(PhysArgs<floa
       pv[slot] = ldg(vs, g);
       pn[slot] = ldg(a.v, g);
     };
-    float r0 = ldg(a.rho, g0), t0 = ldg(a.th, g0), q0 = ldg(a.q, g0);
-    float ub0 = (ldg(uw, g0) + ldg(a.u, g0)) * 0.5f;
-    float vb0 = (ldg(vs, g0) + ldg(a.v, g0)) * 0.5f;
+    // WIDE: this lane's chunk of the wave's two loads per level (field f,
+    // 16-byte chunk c of the row segment starting at column i0-2): fields
+    // 0-5 are rho, theta, q, u, v and v of row j-1; lanes 38-63 of the second
+    // load repeat lane 37's chunk
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    f32x4 wa[WIDE ? PF : 1], wb[WIDE ? PF : 1];
+    const float *pa = nullptr, *pb = nullptr;
+    int wa_o = 0, wb_o = 0;
+    float *slot_w = s_w[ty];
+    const int xr = ic - i0;
+    if (WIDE) {
+      const int fa = tx < 51 ? tx / 17 : 3, ca = tx < 51 ? tx % 17 : tx - 51;
+      const int fb = tx < 4 ? 3 : (tx < 21 ? 4 : 5);
+      const int cb = tx < 4 ? 13 + tx : (tx < 21 ? tx - 4 : (tx < 38 ? tx - 21 : 16));
+      const unsigned row = a.g.origin - 2u + unsigned(i0) + unsigned(j) * sj;   // column i0-2: 16-byte aligned
+      auto base = [&](int f, int c) -> const float * {
+        const float *fp = f == 0 ? a.rho : f == 1 ? a.th : f == 2 ? a.q : f == 3 ? a.u : a.v;
+        return fp + row + unsigned(4 * c) - (f == 5 ? sj : 0u);
+      };
+      pa = base(fa, ca);
+      pb = base(fb, cb);
+      wa_o = fa * WROW + 4 * ca;
+      wb_o = fb * WROW + 4 * cb;
+    }
+    auto fetch_w = [&](int lev, int slot) {
+      size_t off = size_t(lev) * sk;
+      asm volatile("" : "+v"(off));
+      wa[slot] = *reinterpret_cast<const f32x4 *>(pa + off);
+      wb[slot] = *reinterpret_cast<const f32x4 *>(pb + off);
+    };
+    // level values of this lane's column from a staged pair of loads
+    auto stage_w = [&](int slot, float &r, float &t, float &q, float &ub, float &vb) {
+      *reinterpret_cast<f32x4 *>(slot_w + wa_o) = wa[slot];
+      *reinterpret_cast<f32x4 *>(slot_w + wb_o) = wb[slot];
+      r = slot_w[xr + 2];
+      t = slot_w[WROW + xr + 2];
+      q = slot_w[2 * WROW + xr + 2];
+      ub = (slot_w[3 * WROW + xr + 1] + slot_w[3 * WROW + xr + 2]) * 0.5f;
+      vb = (slot_w[5 * WROW + xr + 2] + slot_w[4 * WROW + xr + 2]) * 0.5f;
+    };
+    float r0, t0, q0, ub0, vb0;
+    if (WIDE) {
+      // level 0 goes through slot 0 first; level PF refills it after
+      fetch_w(0, 0);
 #pragma unroll
-    for (int l = 1; l <= PF; ++l)
-      if (l < NZ) fetch_up(l, l % PF);
+      for (int l = 1; l < PF; ++l)
+        if (l < NZ) fetch_w(l, l);
+      stage_w(0, r0, t0, q0, ub0, vb0);
+      if (PF < NZ) fetch_w(PF, 0);
+    } else {
+      r0 = ldg(a.rho, g0);
+      t0 = ldg(a.th, g0);
+      q0 = ldg(a.q, g0);
+      ub0 = (ldg(uw, g0) + ldg(a.u, g0)) * 0.5f;
+      vb0 = (ldg(vs, g0) + ldg(a.v, g0)) * 0.5f;
+#pragma unroll
+      for (int l = 1; l <= PF; ++l)
+        if (l < NZ) fetch_up(l, l % PF);
+    }
     const float beta = dt * r0 * ldg(a.ch, unsigned(col));
     const float ths = ldg(a.th_s, unsigned(col)), qs = ldg(a.q_s, unsigned(col));
     float dtr[NZ], dqr[NZ];
@@ -323,12 +393,17 @@ __global__ __launch_bounds__(256, KEEP ? 1 : 2) void k_physics_f32(PhysArgs<floa
       float ahi = 0.f, r1 = 0.f, t1 = t0, q1 = q0, ub1 = 0.f, vb1 = 0.f;
       if (k + 1 < NZ) {
         const int sl = (k + 1) % PF;
-        r1 = pr[sl];
-        t1 = pt[sl];
-        q1 = pq[sl];
-        ub1 = (pu[sl] + pe[sl]) * 0.5f;
-        vb1 = (pv[sl] + pn[sl]) * 0.5f;
-        if (k + 1 + PF < NZ) fetch_up(k + 1 + PF, sl);
+        if (WIDE) {
+          stage_w(sl, r1, t1, q1, ub1, vb1);
+          if (k + 1 + PF < NZ) fetch_w(k + 1 + PF, sl);
+        } else {
+          r1 = pr[sl];
+          t1 = pt[sl];
+          q1 = pq[sl];
+          ub1 = (pu[sl] + pe[sl]) * 0.5f;
+          vb1 = (pv[sl] + pn[sl]) * 0.5f;
+          if (k + 1 + PF < NZ) fetch_up(k + 1 + PF, sl);
+        }
         const float rdzi = s_rdzi[k];
         const float du = ub1 - ub0, dv = vb1 - vb0;
         const float kz = kmin + l2 * (__builtin_amdgcn_sqrtf(du * du + dv * dv) * rdzi);
@@ -376,7 +451,7 @@ __global__ __launch_bounds__(256, KEEP ? 1 : 2) void k_physics_f32(PhysArgs<floa
       const int nx = a.g.nx, ny = a.g.ny;
       const float f0 = ldg(a.f0, unsigned(col));
       const float kappa = a.kappa, cpa = a.cp;
-      const int di = i < 2 ? nx : (i >= nx - 2 ? -nx : 0);
+      const int di = ic < 2 ? nx : (ic >= nx - 2 ? -nx : 0);
       const int dj = j < 2 ? ny * int(sj) : (j >= ny - 2 ? -ny * int(sj) : 0);
       // the column's rho, theta, q come from registers (kept by the upward
       // pass; the 512-register budget of a lone wave holds them), so this
@@ -439,7 +514,7 @@ __global__ __launch_bounds__(256, KEEP ? 1 : 2) void k_physics_f32(PhysArgs<floa
             if (k == 0)
               for (int p = 2 * NZ; p < TEND_ROW; ++p) stg(a.tend_t, unsigned(col) * TEND_ROW + unsigned(p), 0.f);
           } else {
-            const unsigned o = unsigned(k * ny + j) * unsigned(nx) + unsigned(i);
+            const unsigned o = unsigned(k * ny + j) * unsigned(nx) + unsigned(ic);
             stg(a.tend_t, o, dth / dt + heat);
             stg(a.tend_q, o, dqq / dt);
           }
@@ -480,6 +555,11 @@ __global__ __launch_bounds__(256, KEEP ? 1 : 2) void k_physics_f32(PhysArgs<floa
         }
       }
     }
+  }
+  if (WIDE && !active) {   // a duplicate of column nx-1 (or a row past the grid) counts nothing
+    mass[0] = mass[1] = mass[2] = Kahan{};
+    cnt = Counters{};
+    fp64 = 0;
   }
   block_finish<4>(&a, a.partials, a.flags, MODE == 0 && a.do_mass, MODE == 0, mass, cnt, fp64);
 }
@@ -642,9 +722,13 @@ hipError_t launch_physics(const PhysArgs<T> &a, hipStream_t s) {
     const int nb = phys_reg_blocks(a.g.nx, a.g.ny);
     const dim3 blk(64, 4);
     const bool keep = a.variant != PHYS_VARIANT_REREAD;
+    const bool wide = a.variant == PHYS_VARIANT_WIDE;
     if (a.g.nz == 58) {
       const size_t lds = 58 * 256 * sizeof(float);
-      if (keep) {
+      if (wide) {
+        if (a.mode == 0) hipLaunchKernelGGL((k_physics_f32<58, 0, true, true>), dim3(nb), blk, lds, s, a);
+        else hipLaunchKernelGGL((k_physics_f32<58, 1, true, true>), dim3(nb), blk, lds, s, a);
+      } else if (keep) {
         if (a.mode == 0) hipLaunchKernelGGL((k_physics_f32<58, 0, true>), dim3(nb), blk, lds, s, a);
         else hipLaunchKernelGGL((k_physics_f32<58, 1, true>), dim3(nb), blk, lds, s, a);
       } else {
@@ -655,7 +739,10 @@ hipError_t launch_physics(const PhysArgs<T> &a, hipStream_t s) {
     }
     if (a.g.nz == 16) {
       const size_t lds = 16 * 256 * sizeof(float);
-      if (keep) {
+      if (wide) {
+        if (a.mode == 0) hipLaunchKernelGGL((k_physics_f32<16, 0, true, true>), dim3(nb), blk, lds, s, a);
+        else hipLaunchKernelGGL((k_physics_f32<16, 1, true, true>), dim3(nb), blk, lds, s, a);
+      } else if (keep) {
         if (a.mode == 0) hipLaunchKernelGGL((k_physics_f32<16, 0, true>), dim3(nb), blk, lds, s, a);
         else hipLaunchKernelGGL((k_physics_f32<16, 1, true>), dim3(nb), blk, lds, s, a);
       } else {

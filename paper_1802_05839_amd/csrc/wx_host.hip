@@ -652,8 +652,8 @@ int wx_set_param(wx_state *s, int param, double value) {
   if ((param == WX_PARAM_MASS_EVERY || param == WX_PARAM_JUDGE_SEED || param == WX_PARAM_JUDGE_RATE ||
        param == WX_PARAM_STEP) && value != std::floor(value))
     return fail(WX_E_INVAL, "param %d must be an integer", param);
-  if (param == WX_PARAM_PHYS_KERNEL && value != 0.0 && value != 1.0 && value != 2.0)
-    return fail(WX_E_INVAL, "physics kernel must be 0, 1 or 2");
+  if (param == WX_PARAM_PHYS_KERNEL && value != 0.0 && value != 1.0 && value != 2.0 && value != 3.0)
+    return fail(WX_E_INVAL, "physics kernel must be 0, 1, 2 or 3");
   if (param == WX_PARAM_STAGE_TILE && (value != std::floor(value) || value >= wx::STAGE_TILE_VARIANTS))
     return fail(WX_E_INVAL, "stage tile must be an integer in 0..%d", wx::STAGE_TILE_VARIANTS - 1);
   if (param == WX_PARAM_JUDGE_SEED && value >= 4294967296.0) return fail(WX_E_INVAL, "judge seed must be < 2^32");

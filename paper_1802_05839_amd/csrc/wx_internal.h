@@ -117,6 +117,7 @@ struct PhysArgs {
 constexpr int PHYS_VARIANT_KEEP = 0;     // column kept in registers, one wave per SIMD
 constexpr int PHYS_VARIANT_REREAD = 1;   // column read again on the way down, two waves per SIMD
 constexpr int PHYS_VARIANT_SCAN = 2;     // one wave per column, the k-recurrences as lane scans (nz <= 64)
+constexpr int PHYS_VARIANT_WIDE = 3;     // as KEEP, the upward pass fetching each level with 16-byte loads per lane
 constexpr int PHYS_SCAN_COLS = 32;       // columns per block of the scan kernel
 inline int phys_scan_blocks(int nx, int ny) { return ((nx + PHYS_SCAN_COLS - 1) / PHYS_SCAN_COLS) * ny; }
 hipError_t launch_physics_scan(const PhysArgs<float> &a, hipStream_t s);
