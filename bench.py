@@ -408,7 +408,8 @@ def ablation_leg(host_inp, stream, steps: int = 10):
         log(f"stage tile {name}: {out['stage_tiles'][name]}")
     st.set_param("stage_tile", 0)
     for var, name in ((0, "column in registers, 1 wave/SIMD"), (1, "column re-read, 2 waves/SIMD"),
-                      (2, "wave per column, lane scans"), (3, "column in registers, 16-byte row loads")):
+                      (2, "wave per column, lane scans"), (3, "column in registers, 16-byte row loads"),
+                      (4, "two lanes per column, two waves/SIMD")):
         st.set_param("phys_kernel", var)
         st.step(1)
         d = st.profile(steps, stream).tolist()[4]

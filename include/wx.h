@@ -103,7 +103,11 @@ typedef enum wx_param {
                                 rounding); 3 as 0, each level fetched with two
                                 16-byte loads per lane through LDS (field
                                 pointers 16-byte aligned); 0, 1 and 3 give the
-                                same bits [0]                                    */
+                                same bits; 4 two lanes per column, the
+                                elimination run from the ground and from the
+                                lid and joined at mid-column (two waves per
+                                SIMD; nz 16 and 58; equal to 0 within
+                                rounding) [4]                                    */
   WX_PARAM_STAGE_TILE = 13,  /* tile of the RK3 stage kernel (columns x rows), same
                                 results bit for bit: 0 64x8, 1 64x4, 2 64x12,
                                 3 32x16, 4 128x4, 5 64x8 with each face value,

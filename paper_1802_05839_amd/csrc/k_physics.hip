@@ -564,6 +564,251 @@ __global__ __launch_bounds__(256, KEEP ? 1 : 2) void k_physics_f32(PhysArgs<floa
   block_finish<4>(&a, a.partials, a.flags, MODE == 0 && a.do_mass, MODE == 0, mass, cnt, fp64);
 }
 
+// FP32 state, two lanes per column (nz even): the column physics with the
+// tridiagonal solve split at mid-column (a two-sided elimination).  Lane x of
+// a wave (x < 32) takes levels 0 .. H-1 of column i0 + x and eliminates
+// upward from the ground, lane x + 32 takes levels H .. NZ-1 of the same
+// column and eliminates downward from the lid, each with the same recurrence
+// in its own march direction (its "lower" neighbour is the level it came
+// from).  Their last rows meet in a 2 x 2 system for levels H-1 and H, which
+// both lanes solve with the same arithmetic; each then back-substitutes
+// outward.  Every diffusion coefficient (one per interface) is formed from
+// the same operands as in the thread-per-column kernel.  The optical depth
+// runs from the lid down: the upper lane forms it, and its heating, while it
+// eliminates; the lower lane starts from the upper lane's total and forms it
+// while it back-substitutes.  A lane holds half a column (c', rho and most
+// of q in LDS, d', theta and the rest of q in registers), so two waves share
+// each SIMD and each dependent chain is half as long as the
+// thread-per-column kernel's.  32 x 4 columns
+// per block; a lane past the grid edge works on column nx-1 (same values,
+// same stores) and counts nothing.  Columns whose dominance ratio exceeds
+// T_dd are solved whole in FP64 by their lower lane.
+template <int NZ, int MODE>
+__global__ __launch_bounds__(256, 2) void k_physics_f32_split(PhysArgs<float> a) {
+  static_assert(NZ % 2 == 0, "the two halves need an even level count");
+  constexpr int H = NZ / 2;
+  constexpr int PF = 4;                   // levels prefetched ahead
+  constexpr int QL = PHYS_SPLIT_QL < H ? PHYS_SPLIT_QL : H;   // levels of q kept in LDS
+  // LDS per lane and level: c', rho, and q of the first QL levels (the rest
+  // of q, d', and theta stay in registers); two blocks fit on a CU
+  extern __shared__ float s_c[];          // [H][256] c', [H][256] rho, [QL][256] q
+  float *s_r = s_c + H * 256, *s_q = s_c + 2 * H * 256;
+  __shared__ float s_dz[NZ], s_rdzi[NZ];
+  __shared__ double s_vol[NZ];
+  if (a.run_if && *a.run_if == 0) return;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
+  for (int k = tid; k < NZ; k += 256) {
+    s_dz[k] = a.dz[k];
+    s_rdzi[k] = k + 1 < NZ ? a.rdzi[k] : 0.f;
+    s_vol[k] = a.vol[k];
+  }
+  __syncthreads();
+  const int nx = a.g.nx, ny = a.g.ny;
+  const int nbx = (nx + 31) / 32;
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  const int i = (L % nbx) * 32 + (tx & 31), j = (L / nbx) * 4 + ty;
+  const bool up = tx >= 32;               // the upper half of the column
+  const bool active = (i < nx) && (j < ny);
+  const int ic = min(i, nx - 1);
+  Kahan mass[3];
+  Counters cnt;
+  int fp64 = 0;
+  if (j < ny) {                           // whole waves
+    const unsigned sj = a.g.sj, sk = a.g.sk;
+    const unsigned g0 = a.g.origin + unsigned(ic) + unsigned(j) * sj;
+    const int col = ic + nx * j;
+    const float dt = a.dt, kmin = a.kmin, l2 = a.l2, kappa = a.kappa, cpa = a.cp;
+    // level and offset of local step l (0 at the ground or the lid)
+    auto lev = [&](int l) { return up ? NZ - 1 - l : l; };
+    const unsigned gb = up ? g0 + unsigned(NZ - 1) * sk : g0;
+    auto off = [&](int l) {
+      unsigned g = up ? gb - unsigned(l) * sk : gb + unsigned(l) * sk;
+      asm volatile("" : "+v"(g));
+      return g;
+    };
+    const float *uw = plane(a.u, -1), *vs = plane(a.v, -(long long)sj);
+    float pr[PF], pt[PF], pq[PF], pu[PF], pe[PF], pv[PF], pn[PF];   // prefetch ring, steps l+1 .. l+PF
+    auto fetch = [&](int l, int slot) {
+      const unsigned g = off(l);
+      pr[slot] = ldg(a.rho, g);
+      pt[slot] = ldg(a.th, g);
+      pq[slot] = ldg(a.q, g);
+      pu[slot] = ldg(uw, g);
+      pe[slot] = ldg(a.u, g);
+      pv[slot] = ldg(vs, g);
+      pn[slot] = ldg(a.v, g);
+    };
+    float r0, t0, q0, ub0, vb0;
+    {
+      const unsigned g = off(0);
+      r0 = ldg(a.rho, g);
+      t0 = ldg(a.th, g);
+      q0 = ldg(a.q, g);
+      ub0 = (ldg(uw, g) + ldg(a.u, g)) * 0.5f;
+      vb0 = (ldg(vs, g) + ldg(a.v, g)) * 0.5f;
+    }
+#pragma unroll
+    for (int l = 1; l <= PF; ++l)
+      if (l <= H) fetch(l, l % PF);       // step H is the other half's first level
+    const float beta = up ? 0.f : dt * r0 * ldg(a.ch, unsigned(col));
+    const float ths = ldg(a.th_s, unsigned(col)), qs = ldg(a.q_s, unsigned(col));
+    const float f0 = ldg(a.f0, unsigned(col));
+    float dtr[H], dqr[H], colt[H], colq[H];
+    float alo = 0.f, tm1 = t0, qm1 = q0, cpv = 0.f, dtp = 0.f, dqp = 0.f, rmax = 0.f;
+    float tau1 = 0.f, trh1 = 1.f;         // optical depth from the lid (valid in the upper lane)
+
+    // ---- first pass: toward mid-column
+#pragma unroll
+    for (int l = 0; l < H; ++l) {
+      const int k = lev(l);
+      const int sl = (l + 1) % PF;
+      const float r1 = pr[sl], t1 = pt[sl], q1 = pq[sl];
+      const float ub1 = (pu[sl] + pe[sl]) * 0.5f, vb1 = (pv[sl] + pn[sl]) * 0.5f;
+      if (l + 1 + PF <= H) fetch(l + 1 + PF, sl);
+      // the interface toward the next level of the march (k+1/2 going up, k-1/2 going down)
+      const float rdzi = s_rdzi[up ? NZ - 2 - l : l];
+      const float du = ub1 - ub0, dv = vb1 - vb0;
+      const float kz = kmin + l2 * (__builtin_amdgcn_sqrtf(du * du + dv * dv) * rdzi);
+      const float ahi = dt * ((r0 + r1) * 0.5f) * kz * rdzi;
+      const float dzk = s_dz[k];
+      // optical depth and heating from the lid down (the upper lane's levels)
+      tau1 += kappa * r0 * (q0 > 0.f ? q0 : 0.f) * dzk;
+      const float trl = expf(-tau1);
+      const float heat1 = f0 * (trh1 - trl) * fast_rcp(cpa * (r0 * dzk));
+      trh1 = trl;
+      s_r[l * 256 + tid] = r0;
+      if (l < QL) s_q[l * 256 + tid] = q0;
+      else colq[l] = q0;
+      {
+        // the upper lane's heating enters theta (or the tendency) here; the
+        // value is formed here (empty asm), not where it is used
+        float ct = MODE == 0 ? (up ? t0 + dt * heat1 : t0) : (up ? heat1 : 0.f);
+        asm volatile("" : "+v"(ct));
+        colt[l] = ct;
+      }
+      const float m = r0 * dzk;
+      float diag = m + alo + ahi;
+      float rt = ahi * (t1 - t0) - alo * (t0 - tm1);
+      float rq = ahi * (q1 - q0) - alo * (q0 - qm1);
+      if (l == 0) {                         // the ground row (lower lane) takes the surface exchange
+        diag += beta;
+        rt += beta * (ths - t0);
+        rq += beta * (qs - q0);
+      }
+      const float rk = (alo + ahi) * fast_rcp(m);
+      rmax = rk > rmax ? rk : rmax;
+      const float inv = fast_rcp(diag + alo * cpv);
+      cpv = -ahi * inv;
+      dtp = (rt + alo * dtp) * inv;
+      dqp = (rq + alo * dqp) * inv;
+      s_c[l * 256 + tid] = cpv;
+      dtr[l] = dtp;
+      dqr[l] = dqp;
+      alo = ahi;
+      tm1 = t0; t0 = t1;
+      qm1 = q0; q0 = q1;
+      r0 = r1; ub0 = ub1; vb0 = vb1;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+
+    // ---- the two halves meet: x_lo = (d_lo - c_lo d_hi) / (1 - c_lo c_hi), x_hi = d_hi - c_hi x_lo
+    const float o_c = __shfl_xor(cpv, 32), o_t = __shfl_xor(dtp, 32), o_q = __shfl_xor(dqp, 32);
+    const float o_rmax = __shfl_xor(rmax, 32), o_tau = __shfl_xor(tau1, 32), o_trh = __shfl_xor(trh1, 32);
+    const float c_lo = up ? o_c : cpv, c_hi = up ? cpv : o_c;
+    const float t_lo = up ? o_t : dtp, t_hi = up ? dtp : o_t;
+    const float q_lo = up ? o_q : dqp, q_hi = up ? dqp : o_q;
+    const float rden = fast_rcp(1.f - c_lo * c_hi);
+    const float xt_lo = (t_lo - c_lo * t_hi) * rden, xq_lo = (q_lo - c_lo * q_hi) * rden;
+    const float xt_hi = t_hi - c_hi * xt_lo, xq_hi = q_hi - c_hi * xq_lo;
+    const float rcol = rmax > o_rmax ? rmax : o_rmax;
+
+    if (rcol > a.tdd) {
+      if (!up) {
+        const Column<float> c{a, g0, col, col};
+        const unsigned ncol = unsigned(nx) * unsigned(ny);
+        const GlobalStore<double> gs{a.scratch, NZ, ncol, unsigned(col)};
+        upward<float, double, 0>(c, gs);
+        downward<float, double, 0, MODE>(c, gs, mass, cnt);
+        fp64 = 1;
+      }
+    } else {
+      // ---- second pass: back substitution outward, the lower lane's optical depth, update
+      const int di = ic < 2 ? nx : (ic >= nx - 2 ? -nx : 0);
+      const int dj = j < 2 ? ny * int(sj) : (j >= ny - 2 ? -ny * int(sj) : 0);
+      // the first unknown past this half's last row: level H for the lower lane, H-1 for the upper
+      float dtn = up ? xt_lo : xt_hi, dqn = up ? xq_lo : xq_hi;
+      float tau2 = o_tau, trh2 = o_trh;       // the lower lane continues the upper lane's optical depth
+      double cm = 0.0, cmt = 0.0, cmq = 0.0;
+#pragma unroll
+      for (int l = H - 1; l >= 0; --l) {
+        const int k = lev(l);
+        const float ck = s_c[l * 256 + tid];
+        const float dth = dtr[l] - ck * dtn;
+        const float dqq = dqr[l] - ck * dqn;
+        dtn = dth;
+        dqn = dqq;
+        const float r = s_r[l * 256 + tid], q = l < QL ? s_q[l * 256 + tid] : colq[l], dzk = s_dz[k];
+        tau2 += kappa * r * (q > 0.f ? q : 0.f) * dzk;
+        const float trl = expf(-tau2);
+        const float heat2 = up ? 0.f : f0 * (trh2 - trl) * fast_rcp(cpa * (r * dzk));
+        trh2 = trl;
+        const unsigned g = off(l);
+        if (MODE == 1) {
+          const float heat = colt[l] + heat2;
+          if (a.tend_rows) {
+            const unsigned o = unsigned(col) * TEND_ROW + unsigned(k);
+            stg(a.tend_t, o, dth / dt + heat);
+            stg(a.tend_t, o + unsigned(NZ), dqq / dt);
+          } else {
+            const unsigned o = unsigned(k * ny + j) * unsigned(nx) + unsigned(ic);
+            stg(a.tend_t, o, dth / dt + heat);
+            stg(a.tend_q, o, dqq / dt);
+          }
+        } else {
+          const float tn = colt[l] + dth + dt * heat2;
+          const float qn = q + dqq;
+          stg(a.th, g, tn);
+          stg(a.q, g, qn);
+          cnt.nonfinite += (isfinite(r) && isfinite(tn) && isfinite(qn)) ? 0 : 1;
+          cnt.rho_le0 += (r > 0.f) ? 0 : 1;
+          if (a.do_mass) {
+            const double mv = double(r) * s_vol[k];
+            cm += mv;
+            cmt += mv * (double(tn) + a.theta_off);
+            cmq += mv * double(qn);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (MODE == 1 && a.tend_rows && !up)
+        for (int p = 2 * NZ; p < TEND_ROW; ++p) stg(a.tend_t, unsigned(col) * TEND_ROW + unsigned(p), 0.f);
+      if (MODE == 0 && a.do_mass) {
+        mass[0].add(cm);
+        mass[1].add(cmt);
+        mass[2].add(cmq);
+      }
+      // periodic images of this half's levels (the lane reads back its own stores)
+      if (MODE == 0 && (di != 0 || dj != 0)) {
+        for (int l = 0; l < H; ++l) {
+          const unsigned g = off(l);
+          const float tn = ldg(a.th, g), qn = ldg(a.q, g);
+          if (di != 0) { stg(a.th, g + di, tn); stg(a.q, g + di, qn); }
+          if (dj != 0) {
+            stg(a.th, g + dj, tn); stg(a.q, g + dj, qn);
+            if (di != 0) { stg(a.th, g + dj + di, tn); stg(a.q, g + dj + di, qn); }
+          }
+        }
+      }
+    }
+  }
+  if (!active) {   // a duplicate of column nx-1 (or a row past the grid) counts nothing
+    mass[0] = mass[1] = mass[2] = Kahan{};
+    cnt = Counters{};
+    fp64 = 0;
+  }
+  block_finish<4>(&a, a.partials, a.flags, MODE == 0 && a.do_mass, MODE == 0, mass, cnt, fp64);
+}
+
 template <typename T, int MODE>
 __global__ __launch_bounds__(PHYS_BX) void k_physics(PhysArgs<T> a) {
   extern __shared__ unsigned char s_raw[];
@@ -721,6 +966,18 @@ hipError_t launch_physics(const PhysArgs<T> &a, hipStream_t s) {
     if (phys_uses_scan(4, a.g.nz, a.variant) && !a.tend_rows) return launch_physics_scan(a, s);
     const int nb = phys_reg_blocks(a.g.nx, a.g.ny);
     const dim3 blk(64, 4);
+    if (a.variant == PHYS_VARIANT_SPLIT && (a.g.nz == 58 || a.g.nz == 16)) {
+      const int nbs = phys_split_blocks(a.g.nx, a.g.ny);
+      const size_t lds = phys_split_lds(a.g.nz);
+      if (a.g.nz == 58) {
+        if (a.mode == 0) hipLaunchKernelGGL((k_physics_f32_split<58, 0>), dim3(nbs), blk, lds, s, a);
+        else hipLaunchKernelGGL((k_physics_f32_split<58, 1>), dim3(nbs), blk, lds, s, a);
+      } else {
+        if (a.mode == 0) hipLaunchKernelGGL((k_physics_f32_split<16, 0>), dim3(nbs), blk, lds, s, a);
+        else hipLaunchKernelGGL((k_physics_f32_split<16, 1>), dim3(nbs), blk, lds, s, a);
+      }
+      return hipGetLastError();
+    }
     const bool keep = a.variant != PHYS_VARIANT_REREAD;
     const bool wide = a.variant == PHYS_VARIANT_WIDE;
     if (a.g.nz == 58) {

@@ -37,7 +37,7 @@ int fail(int code, const char *fmt, ...) {
 
 // Default constants (the readings; see wx_param in wx.h).
 const double kDefaults[WX_PARAM_COUNT] = {1.0 / 256.0, 0.1, 50.0, 0.02, 1004.0, 64.0, 0.0, 1.0,
-                                          0.0,         0.05, 100.0, 0.0, 0.0, 0.0};
+                                          0.0,         0.05, 100.0, 0.0, 4.0, 0.0};
 
 struct Impl {
   std::vector<double> dz;
@@ -71,7 +71,7 @@ Layout layout(const wx_state *s, size_t es) {
   off += align256(3 * size_t(s->nz) * size_t(s->nx) * size_t(s->ny) * 8);
   L.partials = off;
   const int nparts = std::max({wx::phys_blocks(s->nx, s->ny), wx::phys_reg_blocks(s->nx, s->ny),
-                               wx::phys_scan_blocks(s->nx, s->ny)});
+                               wx::phys_scan_blocks(s->nx, s->ny), wx::phys_split_blocks(s->nx, s->ny)});
   off += align256(size_t(nparts) * 6 * 8);
   L.total = off;
   return L;
@@ -652,8 +652,8 @@ int wx_set_param(wx_state *s, int param, double value) {
   if ((param == WX_PARAM_MASS_EVERY || param == WX_PARAM_JUDGE_SEED || param == WX_PARAM_JUDGE_RATE ||
        param == WX_PARAM_STEP) && value != std::floor(value))
     return fail(WX_E_INVAL, "param %d must be an integer", param);
-  if (param == WX_PARAM_PHYS_KERNEL && value != 0.0 && value != 1.0 && value != 2.0 && value != 3.0)
-    return fail(WX_E_INVAL, "physics kernel must be 0, 1, 2 or 3");
+  if (param == WX_PARAM_PHYS_KERNEL && (value != std::floor(value) || value < 0.0 || value > 4.0))
+    return fail(WX_E_INVAL, "physics kernel must be 0, 1, 2, 3 or 4");
   if (param == WX_PARAM_STAGE_TILE && (value != std::floor(value) || value >= wx::STAGE_TILE_VARIANTS))
     return fail(WX_E_INVAL, "stage tile must be an integer in 0..%d", wx::STAGE_TILE_VARIANTS - 1);
   if (param == WX_PARAM_JUDGE_SEED && value >= 4294967296.0) return fail(WX_E_INVAL, "judge seed must be < 2^32");

@@ -118,6 +118,7 @@ constexpr int PHYS_VARIANT_KEEP = 0;     // column kept in registers, one wave p
 constexpr int PHYS_VARIANT_REREAD = 1;   // column read again on the way down, two waves per SIMD
 constexpr int PHYS_VARIANT_SCAN = 2;     // one wave per column, the k-recurrences as lane scans (nz <= 64)
 constexpr int PHYS_VARIANT_WIDE = 3;     // as KEEP, the upward pass fetching each level with 16-byte loads per lane
+constexpr int PHYS_VARIANT_SPLIT = 4;    // two lanes per column: two-sided elimination, two waves per SIMD (nz 16, 58)
 constexpr int PHYS_SCAN_COLS = 32;       // columns per block of the scan kernel
 inline int phys_scan_blocks(int nx, int ny) { return ((nx + PHYS_SCAN_COLS - 1) / PHYS_SCAN_COLS) * ny; }
 hipError_t launch_physics_scan(const PhysArgs<float> &a, hipStream_t s);
@@ -203,8 +204,17 @@ inline bool phys_uses_reg(int elem_size, int nz) { return elem_size == 4 && (nz 
 inline bool phys_uses_scan(int elem_size, int nz, int variant) {
   return elem_size == 4 && nz <= 64 && variant == PHYS_VARIANT_SCAN;
 }
+inline int phys_split_blocks(int nx, int ny) { return ((nx + 31) / 32) * ((ny + 3) / 4); }
+// levels of q the split kernel keeps in LDS, and its dynamic LDS (c', rho and
+// those q levels per lane; with the static arrays under 80 KB per block)
+constexpr int PHYS_SPLIT_QL = 20;
+inline size_t phys_split_lds(int nz) {
+  const int h = nz / 2;
+  return size_t(2 * h + (PHYS_SPLIT_QL < h ? PHYS_SPLIT_QL : h)) * 256 * sizeof(float);
+}
 inline int phys_partials(int elem_size, int nx, int ny, int nz, int variant = PHYS_VARIANT_KEEP) {
   if (phys_uses_scan(elem_size, nz, variant)) return phys_scan_blocks(nx, ny);
+  if (phys_uses_reg(elem_size, nz) && variant == PHYS_VARIANT_SPLIT) return phys_split_blocks(nx, ny);
   return phys_uses_reg(elem_size, nz) ? phys_reg_blocks(nx, ny) : phys_blocks(nx, ny);
 }
 

@@ -249,8 +249,9 @@ def test_fp32_mass_sums_are_exact_sums_of_the_state(nx, ny, nz, phys):
     assert np.all(rel <= 1e-13), rel
 
 
+@pytest.mark.parametrize("kernel", [0, 4])
 @pytest.mark.parametrize("nz", [12, 16, 58])
-def test_fp64_elimination_is_what_stiff_columns_need(nz):
+def test_fp64_elimination_is_what_stiff_columns_need(nz, kernel):
     # Columns with dominance ratios r ~ 1e3 .. 4e4 (dt x 40, mixing length
     # 500 m), radiation off so the tendencies are the implicit diffusion alone.
     # The FP32 forward elimination loses about r * eps32 relative to the
@@ -261,7 +262,9 @@ def test_fp64_elimination_is_what_stiff_columns_need(nz):
     # diagonally dominant M-matrix, whose solution is insensitive to relative
     # perturbations of its off-diagonals and of m), ~1e-7.  T_dd = 0 forces
     # every column through FP64, T_dd = 1e30 none; the counter says which.
-    _say(f"case: stiff columns nz={nz}, forced FP32 and forced FP64 elimination")
+    # (kernel 0: one thread per column; kernel 4: two lanes per column, the
+    # elimination run from both ends; nz 12 takes the generic kernel)
+    _say(f"case: stiff columns nz={nz} kernel {kernel}, forced FP32 and forced FP64 elimination")
     inp32, p = _stiff_f32_inputs(nz, 40.0, 500.0)
     inp32.f0[:] = 0.0
     ref = physics.column_physics(inp32.rho, inp32.theta, inp32.q, inp32.u, inp32.v, inp32.theta_s,
@@ -273,6 +276,7 @@ def test_fp64_elimination_is_what_stiff_columns_need(nz):
         st = wx.state_from_inputs(inp32, dtype="f32", theta_offset=300.0)
         st.set_param("mix_len", p.mix_len)
         st.set_param("t_dd", tdd)
+        st.set_param("phys_kernel", kernel)
         st.t["flags_out"].zero_()
         tt, tq = st.tendencies()
         flags = st.flags()
@@ -529,6 +533,58 @@ def test_shared_face_stage_kernel_matches_oracle():
     errs = _compare(outs[0][0], _oracle(inp32, 1), FP32_TOL, theta_ref=300.0)
     np.testing.assert_array_equal(outs[0][1], outs[1][1])
     _say(f"shared-face fp32 errors {errs}")
+
+
+@pytest.mark.parametrize("nz", [16, 58])
+def test_split_physics_kernel_matches_oracle(nz):
+    # two lanes per column, the elimination run from the ground and from the
+    # lid and joined at mid-column: the same arithmetic in another order, so
+    # the FP32 bar against the oracle (state after a step, tendencies), mass
+    # sums equal to the exactly rounded sums of the stored state, the
+    # counters and the halo ring; 97 x 23 leaves one live column in the last
+    # tile of 32 and three live rows in the last row of tiles; on stiff
+    # columns the whole-column FP64 path meets the tight bar with every
+    # column counted
+    _say(f"case: split physics kernel nz={nz}")
+    inp = _f32_inputs(inputs.generate(97, 23, nz, seed=48))
+    st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
+    st.set_param("phys_kernel", 4)
+    tt, tq = st.tendencies()
+    st.step(1)
+    gpu = st.download()
+    mass = st.mass()
+    raw = {name: st.download_raw(name) for name in ("rho", "theta", "q")}
+    flags = st.flags()
+    st.close()
+    ref = physics.column_physics(inp.rho, inp.theta, inp.q, inp.u, inp.v, inp.theta_s, inp.q_s,
+                                 inp.f0, inp.ch, inp.dz, inp.dt)
+    e_t = (nmax(tt, ref.t_theta), nmax(tq, ref.t_q))
+    errs = _compare(gpu, _oracle(inp, 1), FP32_TOL, theta_ref=300.0)
+    want = _exact_mass_of_f32_state(raw, inp)
+    rel = np.abs(mass - want) / np.abs(want)
+    _say(f"split kernel: tendency errors {e_t}, state errors {errs}, mass rel {rel}")
+    assert max(e_t) <= FP32_TOL
+    assert np.all(rel <= 1e-13), rel
+    assert flags["nonfinite"] == 0 and flags["rho_le0"] == 0 and flags["fp64_columns"] == 0
+    for name, a in raw.items():
+        inner = a[:, 2:-2, 2:2 + inp.nx]
+        np.testing.assert_array_equal(a[:, :, :inp.nx + 4], np.pad(inner, ((0, 0), (2, 2), (2, 2)), mode="wrap"))
+    # stiff columns: FP64 for the whole column
+    inp32, p = _stiff_f32_inputs(nz, 40.0, 500.0)
+    inp32.f0[:] = 0.0
+    ref = physics.column_physics(inp32.rho, inp32.theta, inp32.q, inp32.u, inp32.v, inp32.theta_s,
+                                 inp32.q_s, inp32.f0, inp32.ch, inp32.dz, inp32.dt, p)
+    st = wx.state_from_inputs(inp32, dtype="f32", theta_offset=300.0)
+    st.set_param("mix_len", p.mix_len)
+    st.set_param("phys_kernel", 4)
+    st.t["flags_out"].zero_()
+    tt, tq = st.tendencies()
+    n64 = st.flags()["fp64_columns"]
+    st.close()
+    e64 = (nmax(tt, ref.t_theta), nmax(tq, ref.t_q))
+    _say(f"stiff columns, split kernel: errors {e64}, FP64 columns {n64} of {inp32.nx * inp32.ny}")
+    assert n64 == int(np.sum(ref.ratio > DEFAULT.t_dd))
+    assert max(e64) <= 1e-6
 
 
 @pytest.mark.parametrize("nz", [16, 58, 11])
