@@ -459,8 +459,9 @@ VALUES_HEVI = 6 + 11
 
 def hevi_leg(nx: int, ny: int, nz: int, stream, steps: int = 50):
     """Fast-mode (HEVI) short steps at the benchmark grid, FP32: time per short
-    step and the HBM roofline of its two launches, for the register kernel
-    (the default) and the one that parks the column in its outputs."""
+    step and the HBM roofline of its two launches, for the two-lane kernel
+    (the default), the one-lane register kernel and the one that parks the
+    column in its outputs."""
     import torch
 
     from paper_1802_05839_amd import inputs, wx
@@ -468,7 +469,7 @@ def hevi_leg(nx: int, ny: int, nz: int, stream, steps: int = 50):
     f = inputs.hevi_fields(nx, ny, nz, seed=2).astype(np.float32)
     ncells = nx * ny * nz
     out = {}
-    for kernel, name in ((0, "registers"), (1, "parked")):
+    for kernel, name in ((0, "registers"), (1, "parked"), (2, "two_sided")):
         hv = wx.Hevi(f, inputs.HEVI_TAU_DEFAULT, dtype="f32", kernel=kernel)
         hv.run(4, stream)
         torch.cuda.synchronize()

@@ -449,10 +449,14 @@ typedef struct wx_hevi_grid {
   double dx;                     /* horizontal spacing [m], dy == dx                */
   double tau;                    /* short step [s]                                  */
   double c_sound, n_bv;          /* sound speed [m/s] > 0, buoyancy frequency [1/s] */
-  int32_t kernel;                /* 0 (set by init): for nz 16 and 58 the column's
-                                    intermediates stay in registers, other nz park
-                                    them in the outputs; 1: always park them
-                                    (the same results within rounding)           */
+  int32_t kernel;                /* 2 (set by init): for nz 16 and 58 two lanes per
+                                    column, the vertical system eliminated from the
+                                    ground and from the lid and joined at face
+                                    nz/2; 0: for nz 16 and 58 one lane per column,
+                                    the column's intermediates in registers; 1:
+                                    park them in the outputs (any nz; also what 0
+                                    and 2 do for other nz); all give the same
+                                    results within rounding                       */
   int32_t pad;
 } wx_hevi_grid;
 

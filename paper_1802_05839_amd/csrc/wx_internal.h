@@ -150,12 +150,15 @@ struct HeviArgs {
   T *u_o, *v_o, *w_o, *b_o, *pi_o; // outputs (u, v, w, b only in the second stage)
   T *e_o;                          // face field parking the eliminated right-hand side
   const HeviCoef<T> *coef;         // [nz]
+  const HeviCoef<T> *coef2;        // [nz] two-sided factors (kernel 2): see hevi_host
   Geom g;
   T h, h2, a4, hc2, hn2, dx, rdx;  // h, h/2, h^2 c^2/4, h c^2, h N^2, dx, 1/dx
 };
 
+// kernel: 0 column in registers (nz 16, 58), 1 parked in the outputs, 2 two
+// lanes per column with the two-sided factors (nz 16, 58)
 template <typename T>
-hipError_t launch_hevi_stage(const HeviArgs<T> &a, bool full, bool regs, hipStream_t s);
+hipError_t launch_hevi_stage(const HeviArgs<T> &a, bool full, int kernel, hipStream_t s);
 
 constexpr int PHYS_BX = 64;        // columns per physics block (one wave)
 constexpr int PHYS_LDS_NZ_MAX = 80;

@@ -629,7 +629,7 @@ class Hevi:
     FACE = ("w", "b")
 
     def __init__(self, f, tau: float, dtype: str = "f64", c_sound: float = 340.0, n_bv: float = 0.01,
-                 device: str = "cuda:0", kernel: int = 0):
+                 device: str = "cuda:0", kernel: int = 2):
         torch = _torch()
         self.lib = load_library()
         nz, ny, nx = f.pi.shape

@@ -52,10 +52,11 @@ def test_fp64_matches_oracle(nx, ny, nz, nsteps):
         assert e <= 1e-12, (n, errs)
 
 
-@pytest.mark.parametrize("kernel,nz", [(0, 58), (1, 58), (0, 16), (1, 21)])
+@pytest.mark.parametrize("kernel,nz", [(0, 58), (1, 58), (0, 16), (1, 21), (2, 58), (2, 16)])
 def test_fp32_matches_oracle(kernel, nz):
     # kernel 0 keeps the column in registers for nz 16 / 58, kernel 1 (and any
-    # other nz) parks it in the outputs
+    # other nz) parks it in the outputs, kernel 2 gives a column two lanes and
+    # solves from both ends (97 = 3 x 32 + 1: one live column in the last tile)
     _say(f"case: HEVI FP32 97x45x{nz} kernel {kernel}, 3 steps")
     f = inputs.hevi_fields(97, 45, nz, seed=3).astype(np.float32)
     tau = inputs.HEVI_TAU_DEFAULT
@@ -65,6 +66,20 @@ def test_fp32_matches_oracle(kernel, nz):
     _say(f"fp32 errors {errs}")
     for n, e in errs.items():
         assert e <= 2e-5, (n, errs)
+
+
+@pytest.mark.parametrize("nz", [16, 58])
+def test_fp64_two_sided_kernel_matches_oracle(nz):
+    # the elimination from the ground and from the lid joined at face nz/2 is
+    # an exact solve of the same system: the FP64 bar of the one-sided kernels
+    _say(f"case: HEVI FP64 70x37x{nz} two-sided kernel, 4 steps")
+    f = inputs.hevi_fields(70, 37, nz, seed=nz + 1)
+    hv = wx.Hevi(f, inputs.HEVI_TAU_DEFAULT, dtype="f64", kernel=2)
+    hv.run(4)
+    errs = _errors(hv.download(), _oracle(f, 4, inputs.HEVI_TAU_DEFAULT))
+    _say(f"fp64 two-sided errors {errs}")
+    for n, e in errs.items():
+        assert e <= 1e-12, (n, errs)
 
 
 @pytest.mark.parametrize("nz", [16, 58])
