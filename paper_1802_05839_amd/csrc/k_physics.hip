@@ -240,7 +240,8 @@ __device__ __forceinline__ void block_finish(const PhysArgs<float> *ap, double *
   }
 }
 
-// FP32 state with a compile-time level count NZ: the production path.
+// FP32 state with a compile-time level count NZ, one thread per column (the
+// two-lane kernel below is the default; these are its ablation variants).
 //
 // 64 x 4 columns per block, one thread per column.  The forward elimination
 // keeps c' in LDS (one float per level and column) and d'_theta, d'_q and the
