@@ -268,11 +268,13 @@ __global__ __launch_bounds__(256) void k_hevi_stage_reg(HeviArgs<T> a) {
 // row that both lanes solve with the same operands; then each lane
 // back-substitutes outward.  Every right-hand side is formed from the same
 // operands as in the one-sided kernels.  Half a column per lane halves the
-// registers (four waves per SIMD at nz = 58) and the length of each
-// dependent chain.  32 x 4 columns per block; a lane past the grid edge works
+// registers per lane (218 at nz = 58: two waves per SIMD) and the length of each
+// dependent chain.  32 x 8 columns per block (eight rows: the neighbour rows
+// that the divergence reads from outside the block are an eighth of its own;
+// four rows took 1.4% longer, two 8%); a lane past the grid edge works
 // on column nx-1 (the same values and the same stores).
 template <typename T, bool FULL, int NZ>
-__global__ __launch_bounds__(256) void k_hevi_stage_split(HeviArgs<T> a) {
+__global__ __launch_bounds__(512) void k_hevi_stage_split(HeviArgs<T> a) {
   static_assert(NZ % 2 == 0 && NZ >= 4, "two halves of at least two cells");
   constexpr int H = NZ / 2;
   // the two-sided table, staged once per block: read per lane (the halves
@@ -287,7 +289,7 @@ __global__ __launch_bounds__(256) void k_hevi_stage_split(HeviArgs<T> a) {
   const int nx = a.g.nx, ny = a.g.ny;
   const int nbx = (nx + 31) / 32;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
-  const int i = (L % nbx) * 32 + (int(threadIdx.x) & 31), j = (L / nbx) * 4 + int(threadIdx.y);
+  const int i = (L % nbx) * 32 + (int(threadIdx.x) & 31), j = (L / nbx) * 8 + int(threadIdx.y);
   if (j >= ny) return;                     // whole waves
   const bool up = threadIdx.x >= 32;
   const int ic = min(i, nx - 1);
@@ -454,13 +456,13 @@ hipError_t launch_hevi_stage(const HeviArgs<T> &a, bool full, int kernel, hipStr
   const int nb = ((a.g.nx + 63) / 64) * ((a.g.ny + 3) / 4);
   const bool fixed = a.g.nz == 58 || a.g.nz == 16;
   if (kernel == 2 && fixed) {
-    const int nb2 = ((a.g.nx + 31) / 32) * ((a.g.ny + 3) / 4);
+    const int nb2 = ((a.g.nx + 31) / 32) * ((a.g.ny + 7) / 8);
     if (a.g.nz == 58) {
-      if (full) hipLaunchKernelGGL((k_hevi_stage_split<T, true, 58>), dim3(nb2), dim3(64, 4), 0, s, a);
-      else hipLaunchKernelGGL((k_hevi_stage_split<T, false, 58>), dim3(nb2), dim3(64, 4), 0, s, a);
+      if (full) hipLaunchKernelGGL((k_hevi_stage_split<T, true, 58>), dim3(nb2), dim3(64, 8), 0, s, a);
+      else hipLaunchKernelGGL((k_hevi_stage_split<T, false, 58>), dim3(nb2), dim3(64, 8), 0, s, a);
     } else {
-      if (full) hipLaunchKernelGGL((k_hevi_stage_split<T, true, 16>), dim3(nb2), dim3(64, 4), 0, s, a);
-      else hipLaunchKernelGGL((k_hevi_stage_split<T, false, 16>), dim3(nb2), dim3(64, 4), 0, s, a);
+      if (full) hipLaunchKernelGGL((k_hevi_stage_split<T, true, 16>), dim3(nb2), dim3(64, 8), 0, s, a);
+      else hipLaunchKernelGGL((k_hevi_stage_split<T, false, 16>), dim3(nb2), dim3(64, 8), 0, s, a);
     }
     return hipGetLastError();
   }
