@@ -20,6 +20,8 @@
 // Every output element is produced by one lane with a fixed k order, and a
 // split over K writes partial tiles that a second kernel sums in a fixed order,
 // so results are bitwise reproducible.
+#include <type_traits>
+
 #include "wx_internal.h"
 #include "wx_mlp_internal.h"
 
@@ -30,35 +32,53 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int GBM = 64, GBN = 64, GBK = 32, GLD = GBK + 8;  // LDS row stride (bf16 elements)
+constexpr int GPF = 4;      // k steps whose operand chunks are in flight beyond the one in LDS (even)
+constexpr int GKIDX = 256;  // longest k range per block whose k rows may be gathered
 
-// Load one 64 x 32 operand tile (rows r0.., k k0..) into LDS as [row][k].
-// KCONTIG: memory is [rows][ld] with k contiguous; else [K][ld] with rows
-// contiguous.  rows_idx optionally indirects the row index (batch gather).
+// Staging of one 64 x 32 operand tile (rows r0.., k k0..) into LDS as
+// [row][k], split into its global half (this thread's 16-byte chunk, loaded
+// a few k steps ahead into registers) and its LDS half.
+// KCONTIG: memory is [rows][ld] with k contiguous; the thread owns tile row
+// t / 4 (memory row grow: the batch gather resolved once per block, -1 past
+// the operand) at k = k0 + 8 (t % 4).  Otherwise memory is [K][ld] with rows
+// contiguous; the thread owns k row k0 + t / 8 (memory row kidx[k - kb] when
+// the k rows are gathered, from the block's index table in LDS) at tile rows
+// 8 (t % 8)..+7, transposed on the way into LDS.  In a transposed tile the
+// four 8-wide k chunks of row r sit in the order chunk ^ ((r / 8) % 4): the
+// eight rows a thread writes are 8 apart, which with any 16-byte-aligned row
+// stride falls on one LDS bank, and the swizzle spreads them over four.
+__device__ __forceinline__ int tile_slot(int r, int k, bool swz) {
+  return r * GLD + (swz ? ((((k >> 3) ^ (r >> 3)) & 3) << 3) + (k & 7) : k);
+}
 template <bool KCONTIG>
-__device__ __forceinline__ void load_tile(uint16_t *lds, const uint16_t *g, int ld, int r0, int k0,
-                                          int nrows, int nk, const int *rows_idx) {
+__device__ __forceinline__ uint4 chunk_load(const uint16_t *g, int ld, int r0, int k0, int nrows, int nk, int grow,
+                                            const int *kidx, int kb) {
   const int t = threadIdx.x;
+  uint4 v = make_uint4(0, 0, 0, 0);
   if (KCONTIG) {
-    const int r = t >> 2, kk = (t & 3) * 8;             // 64 rows x 4 chunks of 8
-    const int gr = r0 + r, gk = k0 + kk;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (gr < nrows && gk < nk) {
-      const int row = rows_idx ? rows_idx[gr] : gr;
-      v = *reinterpret_cast<const uint4 *>(g + (size_t)row * ld + gk);
-    }
-    *reinterpret_cast<uint4 *>(lds + r * GLD + kk) = v;
+    const int gk = k0 + (t & 3) * 8;
+    if (grow >= 0 && gk < nk) v = *reinterpret_cast<const uint4 *>(g + (size_t)grow * ld + gk);
   } else {
-    // rows_idx here indirects the k index (a batch gather of [K][ld] rows)
-    const int kk = t >> 3, r = (t & 7) * 8;             // 32 k x 8 chunks of 8 rows
-    const int gr = r0 + r, gk = k0 + kk;
-    uint4 v = make_uint4(0, 0, 0, 0);
+    const int gk = k0 + (t >> 3), gr = r0 + (t & 7) * 8;
     if (gk < nk && gr < nrows) {
-      const int krow = rows_idx ? rows_idx[gk] : gk;
+      const int krow = kidx ? kidx[gk - kb] : gk;
       v = *reinterpret_cast<const uint4 *>(g + (size_t)krow * ld + gr);
     }
+  }
+  return v;
+}
+
+template <bool KCONTIG>
+__device__ __forceinline__ void chunk_store(uint16_t *lds, const uint4 &v) {
+  const int t = threadIdx.x;
+  if (KCONTIG) {
+    *reinterpret_cast<uint4 *>(lds + (t >> 2) * GLD + (t & 3) * 8) = v;
+  } else {
+    const int kk = t >> 3, r = (t & 7) * 8;
+    uint16_t *dst = lds + tile_slot(r, kk, true);   // rows r..r+7 share the chunk order
     const uint16_t *e = reinterpret_cast<const uint16_t *>(&v);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) lds[(r + q) * GLD + kk] = e[q];
+    for (int q = 0; q < 8; ++q) dst[q * GLD] = e[q];
   }
 }
 
@@ -156,38 +176,88 @@ template <bool AK, bool BK_, int EP>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t sA[2][GBM * GLD];
   __shared__ __attribute__((aligned(16))) uint16_t sB[2][GBN * GLD];
+  __shared__ int s_ka[AK ? 1 : GKIDX], s_kb[BK_ ? 1 : GKIDX];
   const GemmTile tile = gemm_tile();
   const int m0 = tile.m0, n0 = tile.n0;
   const int kb = tile.z * a.k_split;
   const int ke = min(a.K, kb + a.k_split);
-  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.f;
 
+  // the gathers, resolved before the k loop: a k-contiguous operand's row
+  // per thread, a row-contiguous operand's k rows into an LDS table
+  const int *ka = nullptr, *kbt = nullptr;
+  int growa = -1, growb = -1;
+  if (AK) {
+    const int gr = m0 + (t >> 2);
+    if (gr < a.M) growa = a.rows_a ? a.rows_a[gr] : gr;
+  } else if (a.rows_a) {
+    for (int q = t; q < ke - kb; q += 256) s_ka[q] = a.rows_a[kb + q];
+    ka = s_ka;
+  }
+  if (BK_) {
+    const int gr = n0 + (t >> 2);
+    if (gr < a.N) growb = a.rows_b ? a.rows_b[gr] : gr;
+  } else if (a.rows_b) {
+    for (int q = t; q < ke - kb; q += 256) s_kb[q] = a.rows_b[kb + q];
+    kbt = s_kb;
+  }
+  __syncthreads();
+
+  // k step s is staged in LDS buffer s & 1; the chunks of the next GPF steps
+  // are in flight in register slots (step s in slot s % GPF), so the global
+  // round trip of a step overlaps the matrix work of the GPF steps before it
   const int nsteps = (ke - kb + GBK - 1) / GBK;
+  uint4 pa[GPF], pb[GPF];
+  auto fetch = [&](int s, int slot) {
+    const int k0 = kb + s * GBK;
+    pa[slot] = chunk_load<AK>(a.A, a.lda, m0, k0, a.M, ke, growa, ka, kb);
+    pb[slot] = chunk_load<BK_>(a.B, a.ldb, n0, k0, a.N, ke, growb, kbt, kb);
+  };
+#pragma unroll
+  for (int d = 0; d < GPF; ++d)
+    if (d < nsteps) fetch(d, d);
   if (nsteps > 0) {
-    load_tile<AK>(sA[0], a.A, a.lda, m0, kb, a.M, ke, a.rows_a);
-    load_tile<BK_>(sB[0], a.B, a.ldb, n0, kb, a.N, ke, a.rows_b);
+    chunk_store<AK>(sA[0], pa[0]);
+    chunk_store<BK_>(sB[0], pb[0]);
+    if (GPF < nsteps) fetch(GPF, 0);
   }
   __syncthreads();
   // lane holds row (or column) lane % 32 of its operand at k = 8 (lane / 32)..+7
-  const int ra = (wm + (lane & 31)) * GLD + 8 * (lane >> 5);
-  const int rb = (wn + (lane & 31)) * GLD + 8 * (lane >> 5);
-  for (int s = 0; s < nsteps; ++s) {
-    const int cur = s & 1;
-    if (s + 1 < nsteps) {
-      load_tile<AK>(sA[cur ^ 1], a.A, a.lda, m0, kb + (s + 1) * GBK, a.M, ke, a.rows_a);
-      load_tile<BK_>(sB[cur ^ 1], a.B, a.ldb, n0, kb + (s + 1) * GBK, a.N, ke, a.rows_b);
-    }
+  // of each 16-wide half of a step (transposed tiles: swizzled chunks)
+  const int ra0 = tile_slot(wm + (lane & 31), 8 * (lane >> 5), !AK);
+  const int ra1 = tile_slot(wm + (lane & 31), 16 + 8 * (lane >> 5), !AK);
+  const int rb0 = tile_slot(wn + (lane & 31), 8 * (lane >> 5), !BK_);
+  const int rb1 = tile_slot(wn + (lane & 31), 16 + 8 * (lane >> 5), !BK_);
+  // step s with c = s % GPF a compile-time constant, so that every register
+  // slot and LDS buffer is fixed
+  auto step = [&](int s, auto cc) __attribute__((always_inline)) {
+    constexpr int c = decltype(cc)::value;
+    constexpr int buf = c & 1, nslot = (c + 1) % GPF;
+    static_assert(GBK == 32, "two 16-wide halves per step");
 #pragma unroll
-    for (int kk = 0; kk < GBK; kk += 16) {
-      const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(sA[cur] + ra + kk);
-      const bf16x8 fb = *reinterpret_cast<const bf16x8 *>(sB[cur] + rb + kk);
+    for (int h = 0; h < 2; ++h) {
+      const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(sA[buf] + (h ? ra1 : ra0));
+      const bf16x8 fb = *reinterpret_cast<const bf16x8 *>(sB[buf] + (h ? rb1 : rb0));
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb, acc, 0, 0, 0);
     }
+    if (s + 1 < nsteps) {
+      // buffer buf ^ 1 was last read in step s - 1, which every wave has left
+      chunk_store<AK>(sA[buf ^ 1], pa[nslot]);
+      chunk_store<BK_>(sB[buf ^ 1], pb[nslot]);
+      if (s + 1 + GPF < nsteps) fetch(s + 1 + GPF, nslot);
+    }
     __syncthreads();
+  };
+  static_assert(GPF == 4, "the loop below is unrolled for four slots");
+  for (int s0 = 0; s0 < nsteps; s0 += GPF) {
+    step(s0, std::integral_constant<int, 0>());
+    if (s0 + 1 < nsteps) step(s0 + 1, std::integral_constant<int, 1>());
+    if (s0 + 2 < nsteps) step(s0 + 2, std::integral_constant<int, 2>());
+    if (s0 + 3 < nsteps) step(s0 + 3, std::integral_constant<int, 3>());
   }
   gemm_epilogue<EP>(a, acc, m0, n0, tile.z, wm, wn, lane);
 }
@@ -234,11 +304,14 @@ __device__ __forceinline__ void adam_elem(const AdamArgs &a, const AdamSeg &S, s
   }
 }
 
-// Column sums of up to four [rows][lda] FP32 matrices (one block's share).  Block b
-// covers 16 columns of one matrix; thread (quad q, group g) sums columns
-// 16b + 4q .. 16b + 4q + 3 over rows g, g + 64, ... in order (float4 loads
-// when the matrix allows), then the 64 group sums are folded in a fixed tree.
+// Column sums of up to four [rows][lda] FP32 matrices (one block's share).
+// Block b covers COLSUM_COLS = 16 columns of one matrix; thread (quad q,
+// group g) sums columns 16b + 4q .. 16b + 4q + 3 over rows g, g + 64, ... in
+// order (float4 loads when the matrix allows, sixteen rows in flight
+// together), then the 64 group sums are folded in a fixed tree.  These
+// blocks run on few CUs, so their speed is the bytes each keeps in flight.
 __device__ __forceinline__ void colsum_block(const ColsumArgs &a, int b, const AdamArgs *adam, const int *seg) {
+  static_assert(COLSUM_COLS == 16, "four float4 quads of columns per block");
   __shared__ float sh[64][17];
   int jb = 0;
   while (jb + 1 < a.njobs && b >= a.job[jb].blocks) {
@@ -251,15 +324,13 @@ __device__ __forceinline__ void colsum_block(const ColsumArgs &a, int b, const A
   float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
   if (J.vec) {
     if (c < J.cols) {
-      // rows in batches of 8: the loads of a batch are in flight together,
-      // the sums still run over r in order
       int r = g;
-      for (; r + 7 * 64 < a.rows; r += 8 * 64) {
-        float4 x[8];
+      for (; r + 15 * 64 < a.rows; r += 16 * 64) {
+        float4 x[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = *reinterpret_cast<const float4 *>(J.a + (size_t)(r + 64 * u) * J.lda + c);
+        for (int u = 0; u < 16; ++u) x[u] = *reinterpret_cast<const float4 *>(J.a + (size_t)(r + 64 * u) * J.lda + c);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 16; ++u) {
           s0 += x[u].x;
           s1 += x[u].y;
           s2 += x[u].z;
@@ -275,12 +346,32 @@ __device__ __forceinline__ void colsum_block(const ColsumArgs &a, int b, const A
       }
     }
   } else {
-    for (int r = g; r < a.rows; r += 64) {
-      const float *row = J.a + (size_t)r * J.lda;
-      if (c < J.cols) s0 += row[c];
-      if (c + 1 < J.cols) s1 += row[c + 1];
-      if (c + 2 < J.cols) s2 += row[c + 2];
-      if (c + 3 < J.cols) s3 += row[c + 3];
+    // scalar loads (the loss column): also sixteen rows in flight; a loop
+    // with one load per row would wait a full round trip per row
+    const int nc = min(4, J.cols - c);
+    int r = g;
+    for (; r + 15 * 64 < a.rows; r += 16 * 64) {
+      float x[16][4];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const float *row = J.a + (size_t)(r + 64 * u) * J.lda + c;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[u][e] = e < nc ? row[e] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        s0 += x[u][0];
+        s1 += x[u][1];
+        s2 += x[u][2];
+        s3 += x[u][3];
+      }
+    }
+    for (; r < a.rows; r += 64) {
+      const float *row = J.a + (size_t)r * J.lda + c;
+      if (nc > 0) s0 += row[0];
+      if (nc > 1) s1 += row[1];
+      if (nc > 2) s2 += row[2];
+      if (nc > 3) s3 += row[3];
     }
   }
   sh[g][4 * q] = s0;
@@ -318,15 +409,15 @@ __global__ void __launch_bounds__(256) k_grad_finish(GradFinishArgs a) {
     if (b < J.blocks) {
       const int i = b * 256 + threadIdx.x;
       if (i >= J.n) return;
-      // slices in batches of 8 loads in flight, summed in slice order
+      // slices in batches of 16 loads in flight, summed in slice order
       float s = 0.f;
       int p = 0;
-      for (; p + 8 <= J.nsplit; p += 8) {
-        float v[8];
+      for (; p + 16 <= J.nsplit; p += 16) {
+        float v[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = J.part[(p + u) * J.stride + i];
+        for (int u = 0; u < 16; ++u) v[u] = J.part[(p + u) * J.stride + i];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s += v[u];
+        for (int u = 0; u < 16; ++u) s += v[u];
       }
       for (; p < J.nsplit; ++p) s += J.part[p * J.stride + i];
       J.out[i] = s;
@@ -386,6 +477,8 @@ hipError_t launch_gemm(const GemmSpec &g, hipStream_t s) {
   a.C = g.C; a.ldc = g.ldc; a.split_stride = g.split_stride;
   a.mask = g.mask; a.C2 = g.C2;
   const int splits = g.splits > 1 ? (g.K + a.k_split - 1) / a.k_split : 1;
+  // a gather over k goes through a per-block index table of GKIDX entries
+  if (((!g.a_kcontig && g.rows_a) || (!g.b_kcontig && g.rows_b)) && a.k_split > GKIDX) return hipErrorInvalidValue;
   dim3 grid((g.N + GBN - 1) / GBN, (g.M + GBM - 1) / GBM, splits);
 #define WX_G(AK, BK, EP) hipLaunchKernelGGL((k_gemm<AK, BK, EP>), grid, dim3(256), 0, s, a)
   const int key = (g.a_kcontig ? 1 : 0) | (g.b_kcontig ? 2 : 0);

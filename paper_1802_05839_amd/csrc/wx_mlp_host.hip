@@ -240,9 +240,9 @@ int forward_backward(void *blob, void *work, const void *x, const float *y, cons
   ColsumArgs &cs = gf.cs;
   cs.rows = B;
   cs.njobs = 4;
-  cs.job[0] = {w.d3f, MLP_NOUTP, MLP_NOUTP, sec<float>(blob, WX_MLP_GRAD + 5), MLP_NOUTP / 16, 1};
-  cs.job[1] = {w.g2f, MLP_NHID, MLP_NHID, sec<float>(blob, WX_MLP_GRAD + 3), MLP_NHID / 16, 1};
-  cs.job[2] = {w.g1f, MLP_NHID, MLP_NHID, sec<float>(blob, WX_MLP_GRAD + 1), MLP_NHID / 16, 1};
+  cs.job[0] = {w.d3f, MLP_NOUTP, MLP_NOUTP, sec<float>(blob, WX_MLP_GRAD + 5), MLP_NOUTP / COLSUM_COLS, 1};
+  cs.job[1] = {w.g2f, MLP_NHID, MLP_NHID, sec<float>(blob, WX_MLP_GRAD + 3), MLP_NHID / COLSUM_COLS, 1};
+  cs.job[2] = {w.g1f, MLP_NHID, MLP_NHID, sec<float>(blob, WX_MLP_GRAD + 1), MLP_NHID / COLSUM_COLS, 1};
   cs.job[3] = {w.row_loss, 1, 1, loss_sum, 1, 0};
   if (adam) {
     gf.adam = *adam;

@@ -129,11 +129,12 @@ struct AdamArgs {
   float lr, bc1, bc2;
 };
 // Column sums of up to four matrices (fixed order), run inside launch_grad_finish.
+constexpr int COLSUM_COLS = 16;  // columns per column-sum block
 struct ColsumJob {
   const float *a;   // [rows][lda]
   int cols, lda;
   float *out;       // [cols]
-  int blocks;       // (cols + 15) / 16
+  int blocks;       // (cols + COLSUM_COLS - 1) / COLSUM_COLS
   int vec;          // cols and lda multiples of 4, a 16-byte aligned
 };
 struct ColsumArgs {
