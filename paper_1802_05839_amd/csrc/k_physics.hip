@@ -583,7 +583,10 @@ __global__ __launch_bounds__(256, KEEP ? 1 : 2) void k_physics_f32(PhysArgs<floa
 // thread-per-column kernel's.  32 x 4 columns
 // per block; a lane past the grid edge works on column nx-1 (same values,
 // same stores) and counts nothing.  Columns whose dominance ratio exceeds
-// T_dd are solved whole in FP64 by their lower lane.
+// T_dd are solved whole in FP64 by their lower lane.  With a column list
+// (tendency rows, MODE 1) block b takes list slots 128 b .. 128 b + 127, slot
+// s writing row s; a slot past the list's length works on column 0 and
+// stores nothing.
 template <int NZ, int MODE>
 __global__ __launch_bounds__(256, 2) void k_physics_f32_split(PhysArgs<float> a) {
   static_assert(NZ % 2 == 0, "the two halves need an even level count");
@@ -605,11 +608,24 @@ __global__ __launch_bounds__(256, 2) void k_physics_f32_split(PhysArgs<float> a)
   }
   __syncthreads();
   const int nx = a.g.nx, ny = a.g.ny;
-  const int nbx = (nx + 31) / 32;
-  const int L = xcd_remap(blockIdx.x, gridDim.x);
-  const int i = (L % nbx) * 32 + (tx & 31), j = (L / nbx) * 4 + ty;
+  const bool listed = MODE == 1 && a.col_list != nullptr;
+  int i, j, slot = 0;
+  bool active;
+  if (listed) {
+    slot = blockIdx.x * 128 + ty * 32 + (tx & 31);
+    active = slot < min(*a.n_list, a.list_cap);
+    const int cc = active ? a.col_list[slot] : 0;
+    i = cc % nx;
+    j = cc / nx;
+  } else {
+    const int nbx = (nx + 31) / 32;
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    i = (L % nbx) * 32 + (tx & 31);
+    j = (L / nbx) * 4 + ty;
+    active = (i < nx) && (j < ny);
+  }
   const bool up = tx >= 32;               // the upper half of the column
-  const bool active = (i < nx) && (j < ny);
+  const bool stores = !listed || active;  // a spare list slot computes but stores nothing
   const int ic = min(i, nx - 1);
   Kahan mass[3];
   Counters cnt;
@@ -618,6 +634,7 @@ __global__ __launch_bounds__(256, 2) void k_physics_f32_split(PhysArgs<float> a)
     const unsigned sj = a.g.sj, sk = a.g.sk;
     const unsigned g0 = a.g.origin + unsigned(ic) + unsigned(j) * sj;
     const int col = ic + nx * j;
+    const int trow = listed ? slot : col;   // tendency row
     const float dt = a.dt, kmin = a.kmin, l2 = a.l2, kappa = a.kappa, cpa = a.cp;
     // level and offset of local step l (0 at the ground or the lid)
     auto lev = [&](int l) { return up ? NZ - 1 - l : l; };
@@ -724,8 +741,8 @@ __global__ __launch_bounds__(256, 2) void k_physics_f32_split(PhysArgs<float> a)
     const float rcol = rmax > o_rmax ? rmax : o_rmax;
 
     if (rcol > a.tdd) {
-      if (!up) {
-        const Column<float> c{a, g0, col, col};
+      if (!up && stores) {
+        const Column<float> c{a, g0, col, trow};
         const unsigned ncol = unsigned(nx) * unsigned(ny);
         const GlobalStore<double> gs{a.scratch, NZ, ncol, unsigned(col)};
         upward<float, double, 0>(c, gs);
@@ -757,9 +774,11 @@ __global__ __launch_bounds__(256, 2) void k_physics_f32_split(PhysArgs<float> a)
         if (MODE == 1) {
           const float heat = colt[l] + heat2;
           if (a.tend_rows) {
-            const unsigned o = unsigned(col) * TEND_ROW + unsigned(k);
-            stg(a.tend_t, o, dth / dt + heat);
-            stg(a.tend_t, o + unsigned(NZ), dqq / dt);
+            const unsigned o = unsigned(trow) * TEND_ROW + unsigned(k);
+            if (stores) {
+              stg(a.tend_t, o, dth / dt + heat);
+              stg(a.tend_t, o + unsigned(NZ), dqq / dt);
+            }
           } else {
             const unsigned o = unsigned(k * ny + j) * unsigned(nx) + unsigned(ic);
             stg(a.tend_t, o, dth / dt + heat);
@@ -781,8 +800,8 @@ __global__ __launch_bounds__(256, 2) void k_physics_f32_split(PhysArgs<float> a)
         }
         __builtin_amdgcn_sched_barrier(0);
       }
-      if (MODE == 1 && a.tend_rows && !up)
-        for (int p = 2 * NZ; p < TEND_ROW; ++p) stg(a.tend_t, unsigned(col) * TEND_ROW + unsigned(p), 0.f);
+      if (MODE == 1 && a.tend_rows && !up && stores)
+        for (int p = 2 * NZ; p < TEND_ROW; ++p) stg(a.tend_t, unsigned(trow) * TEND_ROW + unsigned(p), 0.f);
       if (MODE == 0 && a.do_mass) {
         mass[0].add(cm);
         mass[1].add(cmt);
@@ -958,6 +977,14 @@ template <typename T>
 hipError_t launch_physics(const PhysArgs<T> &a, hipStream_t s) {
   if (a.col_list) {
     if (a.mode != 1 || a.list_cap <= 0) return hipErrorInvalidValue;
+    if constexpr (sizeof(T) == 4) {
+      // listed tendency rows of 58-level columns: the two-lane kernel
+      if (a.variant == PHYS_VARIANT_SPLIT && a.tend_rows && a.g.nz == 58) {
+        hipLaunchKernelGGL((k_physics_f32_split<58, 1>), dim3((a.list_cap + 127) / 128), dim3(64, 4),
+                           phys_split_lds(58), s, a);
+        return hipGetLastError();
+      }
+    }
     const int nb = (a.list_cap + PHYS_BX - 1) / PHYS_BX;
     const size_t lds = (sizeof(T) == 4 && a.use_lds) ? size_t(3) * a.g.nz * PHYS_BX * sizeof(float) : 0;
     hipLaunchKernelGGL((k_physics<T, 1>), dim3(nb), dim3(PHYS_BX), lds, s, a);
