@@ -264,26 +264,32 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
 
 // Loss and output gradient: d = 2 (y - t) / (B * nout) on the first nout
 // outputs (0 on padding), as FP32 and BF16; per-row partial loss sums.
-__global__ void k_loss(const float *y, const float *t, const int *rows, int batch, int nout, int ldy,
-                       float *d32, uint16_t *d16, float *row_loss) {
-  const int m = blockIdx.x;
-  const int n = threadIdx.x;                        // 128 threads = padded outputs
+__global__ __launch_bounds__(256) void k_loss(const float *y, const float *t, const int *rows, int batch, int nout,
+                                              int ldy, float *d32, uint16_t *d16, float *row_loss) {
+  // a wave per batch row; lane l holds outputs l and l + 64 of the 128 padded
+  const int lane = threadIdx.x & 63;
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (m >= batch) return;                           // whole waves
   const int row = rows ? rows[m] : m;
-  float e = 0.f, g = 0.f;
-  if (n < nout) {
-    e = y[(size_t)m * ldy + n] - t[(size_t)row * ldy + n];
-    g = 2.f * e / float(batch * nout);
+  float sq[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int n = lane + 64 * h;
+    float e = 0.f, g = 0.f;
+    if (n < nout) {
+      e = y[(size_t)m * ldy + n] - t[(size_t)row * ldy + n];
+      g = 2.f * e / float(batch * nout);
+    }
+    d32[(size_t)m * ldy + n] = g;
+    d16[(size_t)m * ldy + n] = f2bf(g);
+    sq[h] = settle(e * e);
   }
-  d32[(size_t)m * ldy + n] = g;
-  d16[(size_t)m * ldy + n] = f2bf(g);
-  __shared__ float sh[128];
-  sh[n] = e * e;
-  __syncthreads();
-  for (int w = 64; w >= 1; w >>= 1) {
-    if (n < w) sh[n] += sh[n + w];
-    __syncthreads();
-  }
-  if (n == 0) row_loss[m] = sh[0];
+  // the row's sum of squares by halving: (n, n + 64), then (n, n + 32), ...
+  // down to lane 0, each partial a rounded FP32 sum
+  float v = sq[0] + sq[1];
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) v = settle(v + __shfl_down(v, w));
+  if (lane == 0) row_loss[m] = v;
 }
 
 // One Adam update of element i of tensor S with gradient g; refreshes the
@@ -512,7 +518,8 @@ hipError_t launch_gemm(const GemmSpec &g, hipStream_t s) {
 
 hipError_t launch_loss(const float *y, const float *t, const int *rows, int batch, int nout, int ldy,
                        float *d32, uint16_t *d16, float *row_loss, hipStream_t s) {
-  hipLaunchKernelGGL(k_loss, dim3(batch), dim3(128), 0, s, y, t, rows, batch, nout, ldy, d32, d16, row_loss);
+  if (nout > 128) return hipErrorInvalidValue;       // a wave covers 128 padded outputs
+  hipLaunchKernelGGL(k_loss, dim3((batch + 3) / 4), dim3(256), 0, s, y, t, rows, batch, nout, ldy, d32, d16, row_loss);
   return hipGetLastError();
 }
 

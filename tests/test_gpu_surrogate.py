@@ -402,6 +402,27 @@ def test_physics_judged_mode_sampled_columns_and_fallback():
     np.testing.assert_array_equal(fq, plain_q)
 
 
+def test_physics_judged_mode_stiff_sampled_columns():
+    # every column forced onto the FP64 elimination (T_dd = 0): the listed
+    # sampled columns take the two-lane kernel's whole-column FP64 path, which
+    # writes the tendency row of the list slot; bit for bit the whole-grid
+    # launch's FP64 tendencies at those columns
+    _say("case: wx_physics judged mode, FP64 columns, 64x40x58")
+    inp = _state32(64, 40, 62)
+    p, stats = _model(inp)
+    st, m = _physics_state(inp, p, stats, seed=5)
+    st.set_param("t_dd", 0.0)
+    plain_t, plain_q = st.tendencies(mode=wx.WX_PHYS_PLAIN)
+    st.set_param("judge_rel", 1e30)
+    jt, jq = st.tendencies(mode=wx.WX_PHYS_JUDGED)
+    verdict = st.judge()
+    st.close()
+    mask = omlp.sample_mask(5, 0, inp.nx * inp.ny).reshape(inp.ny, inp.nx)
+    assert verdict[3] == int(mask.sum()) > 0 and not verdict[2]
+    np.testing.assert_array_equal(jt[:, mask], plain_t[:, mask])
+    np.testing.assert_array_equal(jq[:, mask], plain_q[:, mask])
+
+
 def test_physics_dataset_mode_equals_wx_dataset():
     _say("case: wx_physics dataset mode, 50x21x58")
     inp = _state32(50, 21, 63)
