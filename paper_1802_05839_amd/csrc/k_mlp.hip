@@ -100,17 +100,16 @@ struct GemmArgs {
   uint16_t *C2;                // EP_MASK_F32_BF16: BF16 copy of the output
 };
 
-// Tile (m0, n0, split) of this block.  Blocks are dealt round-robin to the 8
+// Tile (m0, n0, split) of linear block lin of a GEMM whose grid is nbn x nbm
+// x nbz (n tiles, m tiles, K splits).  Blocks are dealt round-robin to the 8
 // XCDs; the remap gives each XCD a contiguous run of the linear order (n
 // fastest, then m, then the split), so an XCD's blocks share their A rows and
 // K range in its L2 and the blocks running together spread over all n tiles.
 struct GemmTile {
   int m0, n0, z;
 };
-__device__ __forceinline__ GemmTile gemm_tile() {
-  const int nbn = gridDim.x, nbm = gridDim.y;
-  const int lin = blockIdx.x + nbn * (blockIdx.y + nbm * blockIdx.z);
-  const int L = xcd_remap(lin, nbn * nbm * gridDim.z);
+__device__ __forceinline__ GemmTile gemm_tile(int lin, int nbn, int nbm, int nbz) {
+  const int L = xcd_remap(lin, nbn * nbm * nbz);
   GemmTile t;
   t.n0 = (L % nbn) * GBN;
   t.m0 = ((L / nbn) % nbm) * GBM;
@@ -172,12 +171,22 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs &a, const f32x16 &a
   }
 }
 
+// LDS of one GEMM block: the two staged k steps of both operands and the k
+// gather tables.
+struct GemmLds {
+  uint16_t sA[2][GBM * GLD];
+  uint16_t sB[2][GBN * GLD];
+  int ka[GKIDX], kb[GKIDX];
+};
+
+// One 64 x 64 output tile: linear block lin of a GEMM with an nbn x nbm x
+// nbz grid.
 template <bool AK, bool BK_, int EP>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t sA[2][GBM * GLD];
-  __shared__ __attribute__((aligned(16))) uint16_t sB[2][GBN * GLD];
-  __shared__ int s_ka[AK ? 1 : GKIDX], s_kb[BK_ ? 1 : GKIDX];
-  const GemmTile tile = gemm_tile();
+__device__ __forceinline__ void gemm_block(const GemmArgs &a, GemmLds &lds, int lin, int nbn, int nbm, int nbz) {
+  uint16_t (&sA)[2][GBM * GLD] = lds.sA;
+  uint16_t (&sB)[2][GBN * GLD] = lds.sB;
+  int *s_ka = lds.ka, *s_kb = lds.kb;
+  const GemmTile tile = gemm_tile(lin, nbn, nbm, nbz);
   const int m0 = tile.m0, n0 = tile.n0;
   const int kb = tile.z * a.k_split;
   const int ke = min(a.K, kb + a.k_split);
@@ -260,6 +269,34 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
     if (s0 + 3 < nsteps) step(s0 + 3, std::integral_constant<int, 3>());
   }
   gemm_epilogue<EP>(a, acc, m0, n0, tile.z, wm, wn, lane);
+}
+
+template <bool AK, bool BK_, int EP>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
+  __shared__ __attribute__((aligned(16))) GemmLds lds;
+  gemm_block<AK, BK_, EP>(a, lds, blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), gridDim.x,
+                          gridDim.y, gridDim.z);
+}
+
+// Two independent GEMMs in one launch (the weight gradient and the input
+// gradient that read the same upstream delta): blocks [0, n1) are the first
+// GEMM's, [n1p, n1p + n2) the second's, n1p = n1 rounded up to a multiple of 8
+// so that each GEMM's blocks keep their XCD order (the blocks in between
+// return at once).  Each block computes exactly what it would in a launch of
+// its own; the smaller GEMM runs in the larger one's shadow instead of after
+// it.
+struct GemmGrid {
+  int nbn, nbm, nbz;
+};
+template <bool AK1, bool BK1, int EP1, bool AK2, bool BK2, int EP2>
+__global__ __launch_bounds__(256) void k_gemm_pair(GemmArgs a1, GemmGrid g1, GemmArgs a2, GemmGrid g2, int n1p) {
+  __shared__ __attribute__((aligned(16))) GemmLds lds;
+  const int b = blockIdx.x;
+  if (b < n1p) {
+    if (b < g1.nbn * g1.nbm * g1.nbz) gemm_block<AK1, BK1, EP1>(a1, lds, b, g1.nbn, g1.nbm, g1.nbz);
+  } else {
+    gemm_block<AK2, BK2, EP2>(a2, lds, b - n1p, g2.nbn, g2.nbm, g2.nbz);
+  }
 }
 
 // Loss and output gradient: d = 2 (y - t) / (B * nout) on the first nout
@@ -473,8 +510,8 @@ __global__ void k_he_init(float *w, int ld, int fan_out, int fan_in, uint64_t se
 
 }  // namespace
 
-hipError_t launch_gemm(const GemmSpec &g, hipStream_t s) {
-  GemmArgs a;
+// Kernel arguments and grid of a GEMM; false if the spec is not supported.
+static bool gemm_setup(const GemmSpec &g, GemmArgs &a, GemmGrid &grid) {
   a.A = g.A; a.B = g.B; a.lda = g.lda; a.ldb = g.ldb;
   a.M = g.M; a.N = g.N; a.K = g.K;
   a.k_split = g.splits > 1 ? (g.K + g.splits - 1) / g.splits : g.K;
@@ -484,35 +521,40 @@ hipError_t launch_gemm(const GemmSpec &g, hipStream_t s) {
   a.mask = g.mask; a.C2 = g.C2;
   const int splits = g.splits > 1 ? (g.K + a.k_split - 1) / a.k_split : 1;
   // a gather over k goes through a per-block index table of GKIDX entries
-  if (((!g.a_kcontig && g.rows_a) || (!g.b_kcontig && g.rows_b)) && a.k_split > GKIDX) return hipErrorInvalidValue;
-  dim3 grid((g.N + GBN - 1) / GBN, (g.M + GBM - 1) / GBM, splits);
-#define WX_G(AK, BK, EP) hipLaunchKernelGGL((k_gemm<AK, BK, EP>), grid, dim3(256), 0, s, a)
+  if (((!g.a_kcontig && g.rows_a) || (!g.b_kcontig && g.rows_b)) && a.k_split > GKIDX) return false;
+  if (g.epilogue == GEMM_MASK_F32_BF16 && (!g.mask || !g.C2)) return false;
+  grid = {(g.N + GBN - 1) / GBN, (g.M + GBM - 1) / GBM, splits};
   const int key = (g.a_kcontig ? 1 : 0) | (g.b_kcontig ? 2 : 0);
+  return g.epilogue == GEMM_PARTIAL_F32 ? key == 0 : key == 3;
+}
+
+hipError_t launch_gemm(const GemmSpec &g, hipStream_t s) {
+  GemmArgs a;
+  GemmGrid gg;
+  if (!gemm_setup(g, a, gg)) return hipErrorInvalidValue;
+  const dim3 grid(gg.nbn, gg.nbm, gg.nbz);
+#define WX_G(AK, BK, EP) hipLaunchKernelGGL((k_gemm<AK, BK, EP>), grid, dim3(256), 0, s, a)
   switch (g.epilogue) {
-    case GEMM_BIAS_RELU_BF16:
-      if (key != 3) return hipErrorInvalidValue;
-      WX_G(true, true, EP_BIAS_RELU_BF16);
-      break;
-    case GEMM_BIAS_F32:
-      if (key != 3) return hipErrorInvalidValue;
-      WX_G(true, true, EP_BIAS_F32);
-      break;
-    case GEMM_F32:
-      if (key != 3) return hipErrorInvalidValue;
-      WX_G(true, true, EP_F32);
-      break;
-    case GEMM_MASK_F32_BF16:
-      if (key != 3 || !g.mask || !g.C2) return hipErrorInvalidValue;
-      WX_G(true, true, EP_MASK_F32_BF16);
-      break;
-    case GEMM_PARTIAL_F32:
-      if (key != 0) return hipErrorInvalidValue;
-      WX_G(false, false, EP_PARTIAL_F32);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case GEMM_BIAS_RELU_BF16: WX_G(true, true, EP_BIAS_RELU_BF16); break;
+    case GEMM_BIAS_F32: WX_G(true, true, EP_BIAS_F32); break;
+    case GEMM_F32: WX_G(true, true, EP_F32); break;
+    case GEMM_MASK_F32_BF16: WX_G(true, true, EP_MASK_F32_BF16); break;
+    case GEMM_PARTIAL_F32: WX_G(false, false, EP_PARTIAL_F32); break;
+    default: return hipErrorInvalidValue;
   }
 #undef WX_G
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_pair(const GemmSpec &g1, const GemmSpec &g2, hipStream_t s) {
+  if (g1.epilogue != GEMM_PARTIAL_F32 || g2.epilogue != GEMM_MASK_F32_BF16) return hipErrorInvalidValue;
+  GemmArgs a1, a2;
+  GemmGrid gg1, gg2;
+  if (!gemm_setup(g1, a1, gg1) || !gemm_setup(g2, a2, gg2)) return hipErrorInvalidValue;
+  const int n1 = gg1.nbn * gg1.nbm * gg1.nbz, n2 = gg2.nbn * gg2.nbm * gg2.nbz;
+  const int n1p = (n1 + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_gemm_pair<false, false, EP_PARTIAL_F32, true, true, EP_MASK_F32_BF16>), dim3(n1p + n2),
+                     dim3(256), 0, s, a1, gg1, a2, gg2, n1p);
   return hipGetLastError();
 }
 

@@ -146,8 +146,8 @@ int forward_layers(const void *blob, const uint16_t *x, const int *rows, int n, 
 // dW[n][k] = sum_m d[m][n] act[act_rows[m]][k] over the batch (act row m when
 // act_rows is null) as split-K partial slices; *job describes their ordered
 // sum into out (run by launch_grad_finish).
-int weight_grad(const uint16_t *d, int ldd, int nout, const uint16_t *act, const int *act_rows, int lda, int kin,
-                int B, float *part, float *out, SplitJob *job, hipStream_t st) {
+GemmSpec weight_grad(const uint16_t *d, int ldd, int nout, const uint16_t *act, const int *act_rows, int lda, int kin,
+                     int B, float *part, float *out, SplitJob *job) {
   GemmSpec g{};
   g.a_kcontig = g.b_kcontig = false;
   g.A = d; g.lda = ldd; g.B = act; g.ldb = lda; g.rows_b = act_rows;
@@ -155,26 +155,24 @@ int weight_grad(const uint16_t *d, int ldd, int nout, const uint16_t *act, const
   g.splits = (B + Work::kSplitRows - 1) / Work::kSplitRows;
   g.C = part; g.ldc = kin; g.split_stride = size_t(nout) * kin;
   g.epilogue = GEMM_PARTIAL_F32;
-  MLP_HIP(launch_gemm(g, st));
   const int k_split = ((B + g.splits - 1) / g.splits + 31) / 32 * 32;
   const int nsplit = (B + k_split - 1) / k_split;
   const int n = nout * kin;
   *job = {part, nsplit, g.split_stride, out, n, (n + 255) / 256};
-  return WX_OK;
+  return g;
 }
 
 // Hidden-layer gradient: g = (sum_n d[m][n] W[n][k]) * (h[m][k] > 0), with W
 // given transposed as [k][n]; FP32 into out and its BF16 operand into out16.
-int input_grad(const uint16_t *d, int ldd, int nred, const uint16_t *wt, int kout, int B, const uint16_t *h,
-               float *out, uint16_t *out16, hipStream_t st) {
+GemmSpec input_grad(const uint16_t *d, int ldd, int nred, const uint16_t *wt, int kout, int B, const uint16_t *h,
+                    float *out, uint16_t *out16) {
   GemmSpec g{};
   g.a_kcontig = g.b_kcontig = true;
   g.A = d; g.lda = ldd; g.B = wt; g.ldb = nred;
   g.M = B; g.N = kout; g.K = nred; g.splits = 1;
   g.C = out; g.ldc = kout; g.epilogue = GEMM_MASK_F32_BF16;
   g.mask = h; g.C2 = out16;
-  MLP_HIP(launch_gemm(g, st));
-  return WX_OK;
+  return g;
 }
 
 // Adam step t with rate lr over the six parameter tensors of the blob (their
@@ -216,24 +214,23 @@ int forward_backward(void *blob, void *work, const void *x, const float *y, cons
   MLP_HIP(launch_loss(w.y, y, rows, B, MLP_NOUT, MLP_NOUTP, w.d3f, w.d3b, w.row_loss, st));
   GradFinishArgs gf{};
   gf.nsj = 3;
-  // output layer
-  if (int rc = weight_grad(w.d3b, MLP_NOUTP, MLP_NOUTP, w.h2, nullptr, MLP_NHID, MLP_NHID, B, w.part3,
-                           sec<float>(blob, WX_MLP_GRAD + 4), &gf.sj[0], st))
-    return rc;
-  // hidden layer 2 (the ReLU mask and BF16 rounding in the GEMM's epilogue)
-  if (int rc = input_grad(w.d3b, MLP_NOUTP, MLP_NOUTP, sec<uint16_t>(blob, WX_MLP_W3T_BF16), MLP_NHID, B, w.h2,
-                          w.g2f, w.g2b, st))
-    return rc;
-  if (int rc = weight_grad(w.g2b, MLP_NHID, MLP_NHID, w.h1, nullptr, MLP_NHID, MLP_NHID, B, w.part2,
-                           sec<float>(blob, WX_MLP_GRAD + 2), &gf.sj[1], st))
-    return rc;
-  // hidden layer 1
-  if (int rc = input_grad(w.g2b, MLP_NHID, MLP_NHID, sec<uint16_t>(blob, WX_MLP_W2T_BF16), MLP_NHID, B, w.h1,
-                          w.g1f, w.g1b, st))
-    return rc;
-  if (int rc = weight_grad(w.g1b, MLP_NHID, MLP_NHID, xs, rows, MLP_KIN, MLP_KIN, B, w.part1,
-                           sec<float>(blob, WX_MLP_GRAD + 0), &gf.sj[2], st))
-    return rc;
+  // output layer and hidden layer 2 in one launch: both read the output
+  // delta (the ReLU mask and BF16 rounding of the hidden gradient in its
+  // GEMM's epilogue)
+  MLP_HIP(launch_gemm_pair(weight_grad(w.d3b, MLP_NOUTP, MLP_NOUTP, w.h2, nullptr, MLP_NHID, MLP_NHID, B, w.part3,
+                                       sec<float>(blob, WX_MLP_GRAD + 4), &gf.sj[0]),
+                           input_grad(w.d3b, MLP_NOUTP, MLP_NOUTP, sec<uint16_t>(blob, WX_MLP_W3T_BF16), MLP_NHID, B,
+                                      w.h2, w.g2f, w.g2b),
+                           st));
+  // hidden layer 2's weights and hidden layer 1: both read its delta
+  MLP_HIP(launch_gemm_pair(weight_grad(w.g2b, MLP_NHID, MLP_NHID, w.h1, nullptr, MLP_NHID, MLP_NHID, B, w.part2,
+                                       sec<float>(blob, WX_MLP_GRAD + 2), &gf.sj[1]),
+                           input_grad(w.g2b, MLP_NHID, MLP_NHID, sec<uint16_t>(blob, WX_MLP_W2T_BF16), MLP_NHID, B,
+                                      w.h1, w.g1f, w.g1b),
+                           st));
+  MLP_HIP(launch_gemm(weight_grad(w.g1b, MLP_NHID, MLP_NHID, xs, rows, MLP_KIN, MLP_KIN, B, w.part1,
+                                  sec<float>(blob, WX_MLP_GRAD + 0), &gf.sj[2]),
+                      st));
   // one launch for the rest, fixed order: the weight gradients (ordered sums
   // of their split-K slices), the bias gradients (column sums of the
   // unrounded FP32 deltas) and the loss (sum of the per-row sums)

@@ -111,6 +111,10 @@ struct GemmSpec {
 };
 
 hipError_t launch_gemm(const GemmSpec &g, hipStream_t s);
+// A weight-gradient GEMM (GEMM_PARTIAL_F32) and an independent hidden-layer
+// gradient GEMM (GEMM_MASK_F32_BF16) in one launch; each output is bit for bit
+// that of its own launch_gemm.
+hipError_t launch_gemm_pair(const GemmSpec &weight_grad, const GemmSpec &input_grad, hipStream_t s);
 hipError_t launch_loss(const float *y, const float *t, const int *rows, int batch, int nout, int ldy, float *d32,
                        uint16_t *d16, float *row_loss, hipStream_t s);
 
