@@ -107,7 +107,8 @@ typedef enum wx_param {
                                 elimination run from the ground and from the
                                 lid and joined at mid-column (two waves per
                                 SIMD; nz 16 and 58; equal to 0 within
-                                rounding) [4]                                    */
+                                rounding; at nz 58 also the judge's sampled
+                                columns, bit for bit the whole-grid result) [4] */
   WX_PARAM_STAGE_TILE = 13,  /* tile of the RK3 stage kernel (columns x rows), same
                                 results bit for bit: 0 64x8, 1 64x4, 2 64x12,
                                 3 32x16, 4 128x4, 5 64x8 with each face value,
