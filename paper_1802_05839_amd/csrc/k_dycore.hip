@@ -258,10 +258,20 @@ __global__ __launch_bounds__(BX * BY) void k_stage(StageArgs<T> a) {
       const T tnew = tracer(Th, t0, tfT, tfb, bt);
       const T qnew = tracer(Q, q0, qfT, qfb, bq);
 
-      // store the cell and its periodic images in the halo ring
-      stg(a.out_r, gc, rnew);
-      stg(a.out_t, gc, tnew);
-      stg(a.out_q, gc, qnew);
+      // store the cell and its periodic images in the halo ring.  Stage 3's
+      // output (the new state) is read next by the physics launch from its
+      // first column on, which the memory-side cache no longer holds once
+      // the whole grid has been written, so it is stored non-temporally
+      // (1.38 -> 1.36 ms); on stages 1 and 2 the hint costs 7%
+      if (STAGE == 3) {
+        __builtin_nontemporal_store(rnew, a.out_r + gc);
+        __builtin_nontemporal_store(tnew, a.out_t + gc);
+        __builtin_nontemporal_store(qnew, a.out_q + gc);
+      } else {
+        stg(a.out_r, gc, rnew);
+        stg(a.out_t, gc, tnew);
+        stg(a.out_q, gc, qnew);
+      }
       const int di = i < 2 ? nx : (i >= nx - 2 ? -nx : 0);
       const int dj = j < 2 ? ny * int(sj) : (j >= ny - 2 ? -ny * int(sj) : 0);
       if (di != 0) {
@@ -591,8 +601,10 @@ void launch_stage_shape(const StageArgs<T> &a, int stage, hipStream_t s) {
   const dim3 block(BX, BY), grid(a.nblocks);
   if (stage == 1)
     hipLaunchKernelGGL((k_stage<T, 1, BX, BY>), grid, block, 0, s, a);
-  else
+  else if (stage == 2)
     hipLaunchKernelGGL((k_stage<T, 2, BX, BY>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_stage<T, 3, BX, BY>), grid, block, 0, s, a);
 }
 
 template <typename T>
