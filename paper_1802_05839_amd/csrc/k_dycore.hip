@@ -92,7 +92,7 @@ __global__ __launch_bounds__(BX * BY) void k_stage(StageArgs<T> a) {
   __shared__ T s_q[NBUF][TN];
 
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
-  const int L = xcd_remap(blockIdx.x, a.nblocks);
+  const int L = a.reverse ? xcd_remap_rev(blockIdx.x, a.nblocks) : xcd_remap(blockIdx.x, a.nblocks);
   const int i0 = (L % a.nbx) * BX, j0 = (L / a.nbx) * BY;
   const int i = i0 + tx, j = j0 + ty;
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;

@@ -619,7 +619,7 @@ __global__ __launch_bounds__(256, 2) void k_physics_f32_split(PhysArgs<float> a)
     j = cc / nx;
   } else {
     const int nbx = (nx + 31) / 32;
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int L = a.reverse ? xcd_remap_rev(blockIdx.x, gridDim.x) : xcd_remap(blockIdx.x, gridDim.x);
     i = (L % nbx) * 32 + (tx & 31);
     j = (L / nbx) * 4 + ty;
     active = (i < nx) && (j < ny);

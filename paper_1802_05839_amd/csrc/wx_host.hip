@@ -289,6 +289,10 @@ struct Plan {
     const int tile = int(im->param[WX_PARAM_STAGE_TILE]);
     a.nbx = wx::stage_tiles_x(s->nx, tile);
     a.nblocks = a.nbx * wx::stage_tiles_y(s->ny, tile);
+    // stages walk their tiles forward, backward, forward and the physics
+    // backward, so each launch starts on the part of its input that the one
+    // before wrote last
+    a.reverse = n == 2 ? 1 : 0;
     WX_TRY(tm.begin(n));
     WX_HIP(wx::launch_stage<T>(a, n, tile, st));
     return tm.end();
@@ -329,12 +333,15 @@ struct Plan {
     a.list_cap = 0;
     a.run_if = nullptr;
     a.variant = int(im->param[WX_PARAM_PHYS_KERNEL]);
+    a.reverse = 0;
     return a;
   }
 
   int physics(int do_mass, Timer &tm) {
     WX_TRY(tm.begin(4));
-    WX_HIP(wx::launch_physics<T>(phys_args(0, do_mass, nullptr, nullptr), st));
+    wx::PhysArgs<T> pa = phys_args(0, do_mass, nullptr, nullptr);
+    pa.reverse = 1;
+    WX_HIP(wx::launch_physics<T>(pa, st));
     nparts = wx::phys_partials(sizeof(T), s->nx, s->ny, s->nz, int(impl_of(s)->param[WX_PARAM_PHYS_KERNEL]));
     return tm.end();
   }

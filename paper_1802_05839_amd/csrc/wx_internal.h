@@ -48,6 +48,15 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   const int x = b & 7, slot = b >> 3;
   return x * q + min(x, r) + slot;
 }
+// The same bands, each walked from its end: a launch that follows one walking
+// forward starts on what that launch wrote last, part of which the
+// memory-side cache still holds.
+__device__ __forceinline__ int xcd_remap_rev(int b, int n) {
+  const int q = n >> 3, r = n & 7;
+  const int x = b & 7, slot = b >> 3;
+  const int len = q + (x < r ? 1 : 0);
+  return x * q + min(x, r) + (len - 1 - slot);
+}
 
 // Neumaier-compensated FP64 accumulator (sum s, compensation c).
 struct Kahan {
@@ -86,6 +95,7 @@ struct StageArgs {
   Geom g;
   T h, rdx, k4;                    // stage step, 1/dx, biharmonic coefficient
   int nbx, nblocks;                // tiles in i, total tiles
+  int reverse;                     // walk each XCD's band of tiles from its end
 };
 
 template <typename T>
@@ -111,6 +121,7 @@ struct PhysArgs {
   int list_cap;
   const int *run_if;               // when set, the launch does nothing unless *run_if != 0
   int variant;                     // FP32 nz 16/58 kernel: PHYS_VARIANT_*
+  int reverse;                     // two-lane kernel, whole grid: walk each XCD's band from its end
 };
 
 // Variants of the FP32 register-column physics kernel (nz 16 and 58).
