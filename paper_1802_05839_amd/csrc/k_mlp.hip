@@ -98,6 +98,7 @@ struct GemmArgs {
   size_t split_stride;         // EP_PARTIAL_F32: elements between split slices
   const uint16_t *mask;        // EP_MASK_F32_BF16: BF16 activation, C's layout
   uint16_t *C2;                // EP_MASK_F32_BF16: BF16 copy of the output
+  float *colpart;              // EP_MASK_F32_BF16, optional: [M / 32][ldc] column sums of 32-row groups
 };
 
 // Tile (m0, n0, split) of linear block lin of a GEMM whose grid is nbn x nbm
@@ -156,6 +157,21 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs &a, const f32x16 &a
       static_cast<float *>(a.C)[z * a.split_stride + (size_t)m * a.ldc + n] = v;
     }
   };
+  if (EP == EP_MASK_F32_BF16 && a.colpart) {
+    // the wave's 32 rows of column n summed: the lane's 16 rows in r order
+    // (rows past M and masked entries are 0), then the half-wave holding rows
+    // 8 q + 0..3 plus the one holding rows 8 q + 4..7; the bias gradient is
+    // then a sum over M / 32 of these instead of M rows
+    float p = 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      p += (m < a.M && nok && bf2f(mk[r]) > 0.f) ? acc[r] : 0.f;
+    }
+    const float o = __shfl_xor(p, 32);
+    const float t = lane < 32 ? p + o : o + p;
+    if (lane < 32 && nok) a.colpart[(size_t)((m0 + wm) >> 5) * a.ldc + n] = t;
+  }
   // a wave whose 32 x 32 tile lies inside C stores with no per-row test:
   // divergent per-row branches would make every store wait for the one
   // before it (the vector-memory counter also counts stores)
@@ -362,13 +378,14 @@ __device__ __forceinline__ void colsum_block(const ColsumArgs &a, int b, const A
     ++jb;
   }
   const ColsumJob &J = a.job[jb];
+  const int rows = J.rows > 0 ? J.rows : a.rows;
   const int q = threadIdx.x & 3, g = threadIdx.x >> 2;
   const int c = b * 16 + 4 * q;
   float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
   if (J.vec) {
     if (c < J.cols) {
       int r = g;
-      for (; r + 15 * 64 < a.rows; r += 16 * 64) {
+      for (; r + 15 * 64 < rows; r += 16 * 64) {
         float4 x[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) x[u] = *reinterpret_cast<const float4 *>(J.a + (size_t)(r + 64 * u) * J.lda + c);
@@ -380,7 +397,7 @@ __device__ __forceinline__ void colsum_block(const ColsumArgs &a, int b, const A
           s3 += x[u].w;
         }
       }
-      for (; r < a.rows; r += 64) {
+      for (; r < rows; r += 64) {
         const float4 x = *reinterpret_cast<const float4 *>(J.a + (size_t)r * J.lda + c);
         s0 += x.x;
         s1 += x.y;
@@ -393,7 +410,7 @@ __device__ __forceinline__ void colsum_block(const ColsumArgs &a, int b, const A
     // with one load per row would wait a full round trip per row
     const int nc = min(4, J.cols - c);
     int r = g;
-    for (; r + 15 * 64 < a.rows; r += 16 * 64) {
+    for (; r + 15 * 64 < rows; r += 16 * 64) {
       float x[16][4];
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
@@ -409,7 +426,7 @@ __device__ __forceinline__ void colsum_block(const ColsumArgs &a, int b, const A
         s3 += x[u][3];
       }
     }
-    for (; r < a.rows; r += 64) {
+    for (; r < rows; r += 64) {
       const float *row = J.a + (size_t)r * J.lda + c;
       if (nc > 0) s0 += row[0];
       if (nc > 1) s1 += row[1];
@@ -518,7 +535,7 @@ static bool gemm_setup(const GemmSpec &g, GemmArgs &a, GemmGrid &grid) {
   a.k_split = (a.k_split + GBK - 1) / GBK * GBK;
   a.rows_a = g.rows_a; a.rows_b = g.rows_b; a.bias = g.bias;
   a.C = g.C; a.ldc = g.ldc; a.split_stride = g.split_stride;
-  a.mask = g.mask; a.C2 = g.C2;
+  a.mask = g.mask; a.C2 = g.C2; a.colpart = g.colpart;
   const int splits = g.splits > 1 ? (g.K + a.k_split - 1) / a.k_split : 1;
   // a gather over k goes through a per-block index table of GKIDX entries
   if (((!g.a_kcontig && g.rows_a) || (!g.b_kcontig && g.rows_b)) && a.k_split > GKIDX) return false;

@@ -87,6 +87,7 @@ struct Work {
   uint16_t *h1, *h2, *d3b, *g2b, *g1b;
   float *y, *d3f, *g2f, *g1f, *row_loss;
   float *part3, *part2, *part1;            // split-K slices of dW3, dW2, dW1
+  float *cp2, *cp1;                        // 32-row column sums of the hidden gradients
   size_t total;
   static constexpr int kSplitRows = 256;   // batch rows per dW split
 };
@@ -114,6 +115,8 @@ Work work_layout(void *base, int B) {
   w.part3 = reinterpret_cast<float *>(take(splits * MLP_NOUTP * MLP_NHID * 4));
   w.part2 = reinterpret_cast<float *>(take(splits * MLP_NHID * MLP_NHID * 4));
   w.part1 = reinterpret_cast<float *>(take(splits * MLP_NHID * MLP_KIN * 4));
+  w.cp2 = reinterpret_cast<float *>(take(size_t((B + 31) / 32) * MLP_NHID * 4));
+  w.cp1 = reinterpret_cast<float *>(take(size_t((B + 31) / 32) * MLP_NHID * 4));
   w.total = off;
   return w;
 }
@@ -165,13 +168,13 @@ GemmSpec weight_grad(const uint16_t *d, int ldd, int nout, const uint16_t *act, 
 // Hidden-layer gradient: g = (sum_n d[m][n] W[n][k]) * (h[m][k] > 0), with W
 // given transposed as [k][n]; FP32 into out and its BF16 operand into out16.
 GemmSpec input_grad(const uint16_t *d, int ldd, int nred, const uint16_t *wt, int kout, int B, const uint16_t *h,
-                    float *out, uint16_t *out16) {
+                    float *out, uint16_t *out16, float *colpart) {
   GemmSpec g{};
   g.a_kcontig = g.b_kcontig = true;
   g.A = d; g.lda = ldd; g.B = wt; g.ldb = nred;
   g.M = B; g.N = kout; g.K = nred; g.splits = 1;
   g.C = out; g.ldc = kout; g.epilogue = GEMM_MASK_F32_BF16;
-  g.mask = h; g.C2 = out16;
+  g.mask = h; g.C2 = out16; g.colpart = colpart;
   return g;
 }
 
@@ -220,13 +223,13 @@ int forward_backward(void *blob, void *work, const void *x, const float *y, cons
   MLP_HIP(launch_gemm_pair(weight_grad(w.d3b, MLP_NOUTP, MLP_NOUTP, w.h2, nullptr, MLP_NHID, MLP_NHID, B, w.part3,
                                        sec<float>(blob, WX_MLP_GRAD + 4), &gf.sj[0]),
                            input_grad(w.d3b, MLP_NOUTP, MLP_NOUTP, sec<uint16_t>(blob, WX_MLP_W3T_BF16), MLP_NHID, B,
-                                      w.h2, w.g2f, w.g2b),
+                                      w.h2, w.g2f, w.g2b, w.cp2),
                            st));
   // hidden layer 2's weights and hidden layer 1: both read its delta
   MLP_HIP(launch_gemm_pair(weight_grad(w.g2b, MLP_NHID, MLP_NHID, w.h1, nullptr, MLP_NHID, MLP_NHID, B, w.part2,
                                        sec<float>(blob, WX_MLP_GRAD + 2), &gf.sj[1]),
                            input_grad(w.g2b, MLP_NHID, MLP_NHID, sec<uint16_t>(blob, WX_MLP_W2T_BF16), MLP_NHID, B,
-                                      w.h1, w.g1f, w.g1b),
+                                      w.h1, w.g1f, w.g1b, w.cp1),
                            st));
   MLP_HIP(launch_gemm(weight_grad(w.g1b, MLP_NHID, MLP_NHID, xs, rows, MLP_KIN, MLP_KIN, B, w.part1,
                                   sec<float>(blob, WX_MLP_GRAD + 0), &gf.sj[2]),
@@ -238,8 +241,9 @@ int forward_backward(void *blob, void *work, const void *x, const float *y, cons
   cs.rows = B;
   cs.njobs = 4;
   cs.job[0] = {w.d3f, MLP_NOUTP, MLP_NOUTP, sec<float>(blob, WX_MLP_GRAD + 5), MLP_NOUTP / COLSUM_COLS, 1};
-  cs.job[1] = {w.g2f, MLP_NHID, MLP_NHID, sec<float>(blob, WX_MLP_GRAD + 3), MLP_NHID / COLSUM_COLS, 1};
-  cs.job[2] = {w.g1f, MLP_NHID, MLP_NHID, sec<float>(blob, WX_MLP_GRAD + 1), MLP_NHID / COLSUM_COLS, 1};
+  // (the hidden layers' bias gradients from their GEMMs' 32-row column sums)
+  cs.job[1] = {w.cp2, MLP_NHID, MLP_NHID, sec<float>(blob, WX_MLP_GRAD + 3), MLP_NHID / COLSUM_COLS, 1, (B + 31) / 32};
+  cs.job[2] = {w.cp1, MLP_NHID, MLP_NHID, sec<float>(blob, WX_MLP_GRAD + 1), MLP_NHID / COLSUM_COLS, 1, (B + 31) / 32};
   cs.job[3] = {w.row_loss, 1, 1, loss_sum, 1, 0};
   if (adam) {
     gf.adam = *adam;

@@ -105,9 +105,11 @@ struct GemmSpec {
   size_t split_stride;
   int epilogue;
   // GEMM_MASK_F32_BF16: C (FP32) and C2 (BF16) = acc where mask (BF16, same
-  // layout as C) is > 0, else 0
+  // layout as C) is > 0, else 0; with colpart set also colpart[m / 32][n] =
+  // the sum of C over rows m / 32 * 32 .. + 31 (a fixed order)
   const uint16_t *mask;
   uint16_t *C2;
+  float *colpart;
 };
 
 hipError_t launch_gemm(const GemmSpec &g, hipStream_t s);
@@ -135,11 +137,12 @@ struct AdamArgs {
 // Column sums of up to four matrices (fixed order), run inside launch_grad_finish.
 constexpr int COLSUM_COLS = 16;  // columns per column-sum block
 struct ColsumJob {
-  const float *a;   // [rows][lda]
+  const float *a;   // [rows][lda]; rows = ColsumArgs::rows unless this job's rows > 0
   int cols, lda;
   float *out;       // [cols]
   int blocks;       // (cols + COLSUM_COLS - 1) / COLSUM_COLS
   int vec;          // cols and lda multiples of 4, a 16-byte aligned
+  int rows;         // > 0: this job's row count
 };
 struct ColsumArgs {
   ColsumJob job[4];
