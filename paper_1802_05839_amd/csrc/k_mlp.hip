@@ -16,7 +16,12 @@
 // are staged through LDS in [row][k] order (k contiguous) so each lane feeds
 // the matrix core with one 16-byte LDS read per operand and instruction;
 // global operands may be k-contiguous (row-major [rows][K]) or row-contiguous
-// ([K][rows]); the latter are transposed on the way into LDS.
+// ([K][rows]); the latter are transposed on the way into LDS (with a chunk
+// swizzle against bank conflicts).  Each thread's 16-byte operand chunks
+// travel four k steps ahead in registers, so a step's global round trip
+// overlaps the matrix work of the steps before it.  Two independent GEMMs
+// (a weight gradient and the hidden gradient reading the same delta) can
+// share one launch.
 // Every output element is produced by one lane with a fixed k order, and a
 // split over K writes partial tiles that a second kernel sums in a fixed order,
 // so results are bitwise reproducible.
