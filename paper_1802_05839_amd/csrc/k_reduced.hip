@@ -240,7 +240,16 @@ __global__ __launch_bounds__(KIJ_BX *KIJ_BY) void k_rw_step_kij(RwArgs a) {
 
 }  // namespace
 
-int rw_chunk(int nz) { return nz < 16 ? nz : 16; }
+// Levels per interior block: 16, or 8 when 16-level chunks would leave fewer
+// than 1024 interior blocks (four per CU), where more and shorter columns
+// keep more loads in flight (128^3: 1.40 -> 1.12 ms per 100 steps; at 256^3
+// and 256^2 x 512, 16 levels are 4% and 3% faster).  The cells computed do
+// not depend on the chunking.
+int rw_chunk(int nx, int ny, int nz, int bx, int by) {
+  const long long tiles = (long long)((nx + bx - 1) / bx) * ((ny + by - 1) / by);
+  const int c = tiles * ((nz + 15) / 16) < 1024 ? 8 : 16;
+  return nz < c ? nz : c;
+}
 
 template <int BX, int BY>
 void launch_rw_shape(RwArgs a, hipStream_t s) {
@@ -266,7 +275,7 @@ hipError_t launch_rw_step(const double *e, double *out, const double *surf, cons
   a.nx = nx;
   a.ny = ny;
   a.nz = nz;
-  a.kchunk = rw_chunk(nz);
+  a.kchunk = rw_chunk(nx, ny, nz, kij ? KIJ_BX : bx, kij ? KIJ_BY : by);
   a.tiles_x = a.tiles_y = 0;
   a.nu = nu;
   // the weights as the printed program forms them: 1 - (n nu), two roundings
