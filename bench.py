@@ -395,7 +395,7 @@ def ablation_leg(host_inp, stream, steps: int = 10):
     ncells = host_inp.nx * host_inp.ny * host_inp.nz
     out = {"grid": f"{host_inp.nx}x{host_inp.ny}x{host_inp.nz} FP32", "steps_profiled": steps, "stage_tiles": {},
            "physics_kernels": {}}
-    shapes = {0: "64x8", 1: "64x4", 2: "64x12", 3: "32x16", 4: "128x4", 5: "64x8 shared faces"}
+    shapes = {0: "64x8 (stage 2 on 64x12, the default)", 1: "64x4", 2: "64x12", 3: "32x16", 4: "128x4", 5: "64x8 shared faces"}
     st = wx.state_from_inputs(host_inp, dtype="f32", theta_offset=300.0)
     for tile, name in shapes.items():
         st.set_param("stage_tile", tile)

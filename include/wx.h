@@ -110,7 +110,8 @@ typedef enum wx_param {
                                 rounding; at nz 58 also the judge's sampled
                                 columns, bit for bit the whole-grid result) [4] */
   WX_PARAM_STAGE_TILE = 13,  /* tile of the RK3 stage kernel (columns x rows), same
-                                results bit for bit: 0 64x8, 1 64x4, 2 64x12,
+                                results bit for bit: 0 64x8 (stage 2 on 64x12),
+                                1 64x4, 2 64x12,
                                 3 32x16, 4 128x4, 5 64x8 with each face value,
                                 mass flux and Laplacian formed once per tile
                                 in LDS instead of once per adjacent cell [0]     */
