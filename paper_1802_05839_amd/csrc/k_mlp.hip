@@ -175,7 +175,8 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs &a, const f32x16 &a
     }
     const float o = __shfl_xor(p, 32);
     const float t = lane < 32 ? p + o : o + p;
-    if (lane < 32 && nok) a.colpart[(size_t)((m0 + wm) >> 5) * a.ldc + n] = t;
+    // a wave whose 32 rows all lie past M has no group (the buffer holds ceil(M / 32))
+    if (lane < 32 && nok && m0 + wm < a.M) a.colpart[(size_t)((m0 + wm) >> 5) * a.ldc + n] = t;
   }
   // a wave whose 32 x 32 tile lies inside C stores with no per-row test:
   // divergent per-row branches would make every store wait for the one
