@@ -103,6 +103,32 @@ def test_forward_matches_oracle(n):
     assert np.all(y[:, NOUT:] == 0)
 
 
+@pytest.mark.parametrize("batch", [1, 257])
+def test_training_step_stays_inside_its_workspace(batch):
+    # the workspace of wx_mlp_forward_backward is exactly wx_mlp_work_bytes;
+    # a guard band after it (batches whose last 64-row tile ends with a
+    # 32-row group past the batch) must come back untouched
+    _say(f"case: workspace bounds batch={batch}")
+    torch = _torch()
+    rng = np.random.default_rng(90 + batch)
+    m = wx.Mlp()
+    m.init(3)
+    nbytes = int(m.lib.wx_mlp_work_bytes(batch))
+    guard = 1 << 16
+    buf = torch.full((nbytes + guard,), 0xA5, dtype=torch.uint8, device="cuda")
+    m._work, m._work_batch = buf[:nbytes], batch
+    nrows = batch + 5
+    x = _bf16_rows(rng, nrows)
+    t = np.zeros((nrows, NOUTP), dtype=np.float32)
+    t[:, :NOUT] = rng.normal(0, 1, (nrows, NOUT))
+    rows = rng.permutation(nrows)[:batch].astype(np.int32)
+    m.forward_backward(_to_bf16_tensor(x), torch.from_numpy(t).cuda(), torch.from_numpy(rows).cuda())
+    m.train_step(_to_bf16_tensor(x), torch.from_numpy(t).cuda(), torch.from_numpy(rows).cuda(), 1e-3, 1)
+    torch.cuda.synchronize()
+    tail = buf[nbytes:].cpu().numpy()
+    assert np.all(tail == 0xA5), f"{int(np.sum(tail != 0xA5))} guard bytes written"
+
+
 @pytest.mark.parametrize("batch", [1, 257, 300, 4096])
 def test_gradients_match_oracle(batch):
     _say(f"case: gradients batch={batch}")
