@@ -461,6 +461,29 @@ def test_full_grid_fp32_crops_and_mass():
     _say(f"full grid fp32 errors {worst}")
 
 
+@pytest.mark.parametrize("nz", [16, 58])
+def test_step_stays_inside_its_workspace(nz):
+    # wx_step (stage tiles of both shapes, both walk directions, the two-lane
+    # physics with its block partials) and wx_physics tendencies on a ragged
+    # grid: a guard band after the wx_workspace_bytes the state was given
+    # comes back untouched
+    _say(f"case: state workspace bounds nz={nz}")
+    import torch
+    inp = _f32_inputs(inputs.generate(97, 23, nz, seed=48))
+    st = wx.state_from_inputs(inp, dtype="f32", theta_offset=300.0)
+    nb = st.t["workspace"].numel()
+    guard = 1 << 16
+    big = torch.full((nb + guard,), 0xA5, dtype=torch.uint8, device=st.device)
+    st.t["workspace"] = big[:nb]
+    st._p.contents.workspace = big.data_ptr()
+    st.step(3)
+    st.tendencies()
+    torch.cuda.synchronize()
+    tail = big[nb:].cpu().numpy()
+    st.close()
+    assert np.all(tail == 0xA5), f"{int(np.sum(tail != 0xA5))} guard bytes written"
+
+
 @pytest.mark.parametrize("tile", [1, 2, 3, 4])
 def test_stage_tile_shapes_bitwise(tile):
     # the stage kernel's tile-shape ablation: each cell's arithmetic does not
