@@ -423,6 +423,31 @@ def test_physics_judged_mode_stiff_sampled_columns():
     np.testing.assert_array_equal(jq[:, mask], plain_q[:, mask])
 
 
+def test_judged_step_stays_inside_the_surrogate_workspace():
+    # the judge's sample list, the sampled columns' tendency rows (the
+    # two-lane physics over the list, 128 slots per block) and network rows,
+    # and the judge's partials: a guard band after wx_surrogate_work_bytes
+    # comes back untouched, in tendency mode and over coupled steps
+    _say("case: surrogate workspace bounds, 64x40x58")
+    import torch
+    inp = _state32(64, 40, 62)
+    p, stats = _model(inp)
+    st, m = _physics_state(inp, p, stats, seed=5)
+    nb = st.t["surrogate_work"].numel()
+    guard = 1 << 16
+    big = torch.full((nb + guard,), 0xA5, dtype=torch.uint8, device=st.device)
+    st.t["surrogate_work"] = big[:nb]
+    st._p.contents.surrogate_work = big.data_ptr()
+    st.set_param("judge_rel", 1e30)
+    st.tendencies(mode=wx.WX_PHYS_JUDGED)
+    st.set_phys_mode(wx.WX_PHYS_JUDGED)
+    st.step(2)
+    torch.cuda.synchronize()
+    tail = big[nb:].cpu().numpy()
+    st.close()
+    assert np.all(tail == 0xA5), f"{int(np.sum(tail != 0xA5))} guard bytes written"
+
+
 def test_physics_dataset_mode_equals_wx_dataset():
     _say("case: wx_physics dataset mode, 50x21x58")
     inp = _state32(50, 21, 63)
