@@ -165,6 +165,25 @@ def test_full_grid_fp32_sampled_against_oracle():
         assert e <= 2e-5, (n, worst)
 
 
+@pytest.mark.parametrize("kernel", [0, 1, 2])
+def test_run_stays_inside_its_workspace(kernel):
+    # an odd number of short steps (the result copied back from the second
+    # field set) on a ragged grid: a guard band after wx_hevi_workspace_bytes
+    # comes back untouched
+    import torch
+    _say(f"case: HEVI workspace bounds kernel {kernel}")
+    f = inputs.hevi_fields(97, 45, 58, seed=9).astype(np.float32)
+    hv = wx.Hevi(f, inputs.HEVI_TAU_DEFAULT, dtype="f32", kernel=kernel)
+    nb = hv.ws.numel()
+    guard = 1 << 16
+    big = torch.full((nb + guard,), 0xA5, dtype=torch.uint8, device=hv.device)
+    hv.ws = big[:nb]
+    hv.run(3)
+    torch.cuda.synchronize()
+    tail = big[nb:].cpu().numpy()
+    assert np.all(tail == 0xA5), f"{int(np.sum(tail != 0xA5))} guard bytes written"
+
+
 def test_bad_arguments_are_rejected():
     _say("case: HEVI argument errors")
     f = inputs.hevi_fields(8, 8, 4, seed=12)
