@@ -24,43 +24,64 @@ __global__ void k_sample_count(int ncol, uint64_t seed, uint64_t t, unsigned rat
   if (threadIdx.x == 0) block_count[blockIdx.x] = n;
 }
 
-// Exclusive scan of the block counts (one block); total into *n_out.
+// Exclusive scan of the block counts (one block); total into *n_out.  Each
+// thread sums a run of counts (loads eight at a time), the 256 run sums are
+// scanned in LDS by doubling steps, and each thread writes its run's offsets.
 __global__ void k_sample_scan(const int *block_count, int nb, int *block_off, int *n_out) {
   __shared__ int part[256];
   const int t = threadIdx.x;
   const int per = (nb + 255) / 256;
-  const int b0 = t * per, b1 = min(nb, b0 + per);
-  int s = 0;
-  for (int b = b0; b < b1; ++b) s += block_count[b];
+  const int b0 = min(nb, t * per), b1 = min(nb, b0 + per);
+  int s = 0, b = b0;
+  for (; b + 8 <= b1; b += 8) {
+    int v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = block_count[b + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; b < b1; ++b) s += block_count[b];
   part[t] = s;
   __syncthreads();
-  if (t == 0) {
-    int run = 0;
-    for (int q = 0; q < 256; ++q) {
-      const int v = part[q];
-      part[q] = run;
-      run += v;
-    }
-    *n_out = run;
+  for (int w = 1; w < 256; w <<= 1) {
+    const int v = t >= w ? part[t - w] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
   }
-  __syncthreads();
-  int run = part[t];
-  for (int b = b0; b < b1; ++b) {
+  if (t == 255) *n_out = part[255];
+  int run = part[t] - s;
+  for (b = b0; b + 8 <= b1; b += 8) {
+    int v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = block_count[b + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      block_off[b + u] = run;
+      run += v[u];
+    }
+  }
+  for (; b < b1; ++b) {
     block_off[b] = run;
     run += block_count[b];
   }
 }
 
+// Slot of each sampled column: its block's offset plus the sampled columns
+// before it in the block (a ballot within the wavefront, the earlier
+// wavefronts' counts from LDS), so the list is in column order.
 __global__ void k_sample_write(int ncol, uint64_t seed, uint64_t t, unsigned rate, const int *block_off, int cap,
                                int *list) {
-  __shared__ int flags[256];
+  __shared__ int wcount[4];
   const int c = blockIdx.x * 256 + threadIdx.x;
-  const int s = (c < ncol && judge_sampled(seed, t, unsigned(c), rate)) ? 1 : 0;
-  flags[threadIdx.x] = s;
+  const bool s = c < ncol && judge_sampled(seed, t, unsigned(c), rate);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned long long m = __ballot(s);
+  if (lane == 0) wcount[w] = __popcll(m);
   __syncthreads();
   if (s) {
-    int before = 0;
-    for (int q = 0; q < threadIdx.x; ++q) before += flags[q];
+    int before = __popcll(m & ((1ull << lane) - 1ull));
+    for (int q = 0; q < w; ++q) before += wcount[q];
     const int slot = block_off[blockIdx.x] + before;
     if (slot < cap) list[slot] = c;
   }
@@ -82,13 +103,29 @@ __global__ void k_judge_part(const float *y_hat, const float *t_ref, const int *
   const int n = min(*n_list, cap);
   const long long total = (long long)n * TEND_ROW;
   double e[2] = {0.0, 0.0};
-  for (long long x = (long long)blockIdx.x * 256 + t; x < total; x += (long long)JUDGE_BLOCKS * 256) {
+  // elements x = first, first + stride, ... summed in that order; their loads
+  // go out eight at a time (a loop with one load pair per element waits a
+  // memory round trip per element)
+  constexpr long long stride = (long long)JUDGE_BLOCKS * 256;
+  auto add = [&](long long x, float yh, float tr) {
     const int o = int(x % TEND_ROW);
-    if (o >= 2 * nz) continue;
-    const double pred = double(y_hat[x]) * ystd[o] + ymean[o];
-    const double d = pred - double(t_ref[x]);
+    if (o >= 2 * nz) return;
+    const double pred = double(yh) * ystd[o] + ymean[o];
+    const double d = pred - double(tr);
     e[o >= nz] += d * d;
+  };
+  long long x = (long long)blockIdx.x * 256 + t;
+  for (; x + 7 * stride < total; x += 8 * stride) {
+    float yh[8], tr[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      yh[u] = y_hat[x + u * stride];
+      tr[u] = t_ref[x + u * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) add(x + u * stride, yh[u], tr[u]);
   }
+  for (; x < total; x += stride) add(x, y_hat[x], t_ref[x]);
   sh[0][t] = e[0];
   sh[1][t] = e[1];
   __syncthreads();
@@ -118,9 +155,25 @@ __global__ void k_judge_cols(const float *y_hat, const float *t_ref, const int *
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= min(*n_list, cap)) return;
   double e[2] = {0.0, 0.0};
-  for (int o = 0; o < 2 * nz; ++o) {
-    const double pred = double(y_hat[(size_t)s * TEND_ROW + o]) * ystd[o] + ymean[o];
-    const double d = pred - double(t_ref[(size_t)s * TEND_ROW + o]);
+  // outputs in order, their loads eight at a time
+  const float *yr = y_hat + (size_t)s * TEND_ROW, *tr = t_ref + (size_t)s * TEND_ROW;
+  int o = 0;
+  for (; o + 8 <= 2 * nz; o += 8) {
+    float a[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a[u] = yr[o + u];
+      b[u] = tr[o + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double d = (double(a[u]) * ystd[o + u] + ymean[o + u]) - double(b[u]);
+      e[o + u >= nz] += d * d;
+    }
+  }
+  for (; o < 2 * nz; ++o) {
+    const double pred = double(yr[o]) * ystd[o] + ymean[o];
+    const double d = pred - double(tr[o]);
     e[o >= nz] += d * d;
   }
   int *cnt = reinterpret_cast<int *>(part + JUDGE_COUNT_OFF);
