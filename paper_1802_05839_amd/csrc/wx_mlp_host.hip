@@ -150,12 +150,12 @@ int forward_layers(const void *blob, const uint16_t *x, const int *rows, int n, 
 // act_rows is null) as split-K partial slices; *job describes their ordered
 // sum into out (run by launch_grad_finish).
 GemmSpec weight_grad(const uint16_t *d, int ldd, int nout, const uint16_t *act, const int *act_rows, int lda, int kin,
-                     int B, float *part, float *out, SplitJob *job) {
+                     int B, float *part, float *out, SplitJob *job, int split_rows = Work::kSplitRows) {
   GemmSpec g{};
   g.a_kcontig = g.b_kcontig = false;
   g.A = d; g.lda = ldd; g.B = act; g.ldb = lda; g.rows_b = act_rows;
   g.M = nout; g.N = kin; g.K = B;
-  g.splits = (B + Work::kSplitRows - 1) / Work::kSplitRows;
+  g.splits = (B + split_rows - 1) / split_rows;
   g.C = part; g.ldc = kin; g.split_stride = size_t(nout) * kin;
   g.epilogue = GEMM_PARTIAL_F32;
   const int k_split = ((B + g.splits - 1) / g.splits + 31) / 32 * 32;
@@ -227,7 +227,7 @@ int forward_backward(void *blob, void *work, const void *x, const float *y, cons
                            st));
   // hidden layer 2's weights and hidden layer 1: both read its delta
   MLP_HIP(launch_gemm_pair(weight_grad(w.g2b, MLP_NHID, MLP_NHID, w.h1, nullptr, MLP_NHID, MLP_NHID, B, w.part2,
-                                       sec<float>(blob, WX_MLP_GRAD + 2), &gf.sj[1]),
+                                       sec<float>(blob, WX_MLP_GRAD + 2), &gf.sj[1], 2 * Work::kSplitRows),
                            input_grad(w.g2b, MLP_NHID, MLP_NHID, sec<uint16_t>(blob, WX_MLP_W2T_BF16), MLP_NHID, B,
                                       w.h1, w.g1f, w.g1b, w.cp1),
                            st));
