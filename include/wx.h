@@ -339,6 +339,14 @@ int wx_mlp_adam(void *blob, float lr, int t, void *stream);
 int wx_mlp_train_step(void *blob, void *work, const void *x, const float *y, const int32_t *rows, int batch,
                       float lr, int t, float *loss_sum, void *stream);
 
+/* The row order of a training epoch, drawn on the device: out[i] = P(i) for
+ * i < m, where P is a permutation of 0..n-1 fixed by (seed, epoch): a
+ * four-round Feistel network on the smallest even bit width holding n, whose
+ * round function is SplitMix64 of (seed, epoch, round, half), walked until it
+ * lands below n.  Deterministic, one independent evaluation per element.
+ * out: device int32[m], 0 <= m <= n <= 2^30; WX_E_INVAL otherwise. */
+int wx_mlp_shuffle(uint64_t seed, uint64_t epoch, int n, int m, int32_t *out, void *stream);
+
 /* Inference: y_out [n][128] FP32 normalised outputs for x [n][320] BF16.
  * work: wx_mlp_infer_work_bytes(n). */
 size_t wx_mlp_infer_work_bytes(int n);

@@ -531,6 +531,33 @@ __global__ void k_he_init(float *w, int ld, int fan_out, int fan_in, uint64_t se
   w[(size_t)r * ld + c] = (2.0f * u - 1.0f) * bound;
 }
 
+// Epoch shuffle: element i of a Feistel permutation of [0, 2^(2h)) (four
+// rounds, SplitMix64 round function keyed by seed, epoch and round), applied
+// again while the value is >= n (cycle walking keeps it a permutation of
+// [0, n)).
+__device__ __forceinline__ uint32_t feistel(uint32_t x, int h, uint64_t key) {
+  const uint32_t mask = (1u << h) - 1u;
+  uint32_t l = x >> h, r = x & mask;
+#pragma unroll
+  for (int round = 0; round < 4; ++round) {
+    const uint32_t f = uint32_t(splitmix64(key ^ (uint64_t(round) << 56) ^ uint64_t(r))) & mask;
+    const uint32_t nl = r, nr = l ^ f;
+    l = nl;
+    r = nr;
+  }
+  return (l << h) | r;
+}
+
+__global__ void k_shuffle(uint64_t key, int h, int n, int m, int32_t *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  uint32_t x = uint32_t(i);
+  do {
+    x = feistel(x, h, key);
+  } while (x >= uint32_t(n));
+  out[i] = int32_t(x);
+}
+
 }  // namespace
 
 // Kernel arguments and grid of a GEMM; false if the spec is not supported.
@@ -585,6 +612,15 @@ hipError_t launch_loss(const float *y, const float *t, const int *rows, int batc
                        float *d32, uint16_t *d16, float *row_loss, hipStream_t s) {
   if (nout > 128) return hipErrorInvalidValue;       // a wave covers 128 padded outputs
   hipLaunchKernelGGL(k_loss, dim3((batch + 3) / 4), dim3(256), 0, s, y, t, rows, batch, nout, ldy, d32, d16, row_loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_shuffle(uint64_t seed, uint64_t epoch, int n, int m, int32_t *out, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  int h = 1;
+  while ((1ll << (2 * h)) < (long long)n) ++h;
+  const uint64_t key = splitmix64(seed) ^ splitmix64(epoch ^ 0x5851F42D4C957F2Dull);
+  hipLaunchKernelGGL(k_shuffle, dim3((m + 255) / 256), dim3(256), 0, s, key, h, n, m, out);
   return hipGetLastError();
 }
 

@@ -351,6 +351,13 @@ int wx_mlp_train_step(void *blob, void *work, const void *x, const float *y, con
   return forward_backward(blob, work, x, y, rows, batch, loss_sum, &aa, stream);
 }
 
+int wx_mlp_shuffle(uint64_t seed, uint64_t epoch, int n, int m, int32_t *out, void *stream) {
+  if (n < 0 || n > (1 << 30) || m < 0 || m > n) return fail(WX_E_INVAL, "need 0 <= m <= n <= 2^30");
+  if (m > 0 && !out) return fail(WX_E_INVAL, "out is NULL");
+  MLP_HIP(launch_shuffle(seed, epoch, n, m, out, static_cast<hipStream_t>(stream)));
+  return WX_OK;
+}
+
 size_t wx_mlp_infer_work_bytes(int n) {
   if (n < 1) return 0;
   return 2 * a256(size_t(n) * MLP_NHID * 2);

@@ -37,7 +37,7 @@ __host__ __device__ __forceinline__ size_t frag_index(int r, int c, int K) {
 }
 
 // SplitMix64 output for state increment x (Steele, Lea & Flood 2014).
-__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+__host__ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   uint64_t z = x + 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
@@ -170,6 +170,7 @@ struct GradFinishArgs {
   int sj_seg[3], cs_seg[4];
 };
 hipError_t launch_grad_finish(const GradFinishArgs &a, hipStream_t s);
+hipError_t launch_shuffle(uint64_t seed, uint64_t epoch, int n, int m, int32_t *out, hipStream_t s);
 
 hipError_t launch_adam_multi(const AdamArgs &a, hipStream_t s);
 hipError_t launch_to_bf16(const float *w, size_t n, uint16_t *wb, uint16_t *wbt, uint16_t *wbp, int rows, int cols,

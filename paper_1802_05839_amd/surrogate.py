@@ -80,34 +80,18 @@ def train(mlp: "wx.Mlp", x, y, epochs: int = EPOCHS, batch: int = 4096, lr: floa
     t = 0
     dev = x.device
     stream = torch.cuda.current_stream(dev)
-
-    def order(ep):
-        perm = np.random.Generator(np.random.PCG64(np.random.SeedSequence([shuffle_seed, ep]))).permutation(n)
-        return torch.from_numpy(perm[: nb * batch].astype(np.int32))
-
-    # the next epoch's shuffle is drawn on the host and copied (pinned, on the
-    # same stream) while the GPU runs the current epoch; the per-epoch losses
-    # stay on the device until the end, so nothing waits for the GPU
-    pinned = [torch.empty(nb * batch, dtype=torch.int32).pin_memory() for _ in range(2)]
-    rows = [torch.empty(nb * batch, dtype=torch.int32, device=dev) for _ in range(2)]
-    copied = [torch.cuda.Event(), torch.cuda.Event()]
+    # each epoch's row order is drawn on the device (wx_mlp_shuffle), in
+    # stream order before the epoch's steps; the per-epoch losses stay on the
+    # device until the end, so the host never waits for the GPU
+    rows = torch.empty(nb * batch, dtype=torch.int32, device=dev)
     losses = torch.zeros(epochs, dtype=torch.float32, device=dev)
-    pinned[0].copy_(order(0))
-    rows[0].copy_(pinned[0], non_blocking=True)
-    copied[0].record(stream)
     for ep in range(epochs):
-        cur = rows[ep % 2]
+        wx.shuffle(shuffle_seed, ep, n, rows, stream)
         lr_ep = lr * 0.5 * (1.0 + np.cos(np.pi * ep / epochs))
         for b in range(nb):
             t += 1
-            mlp.train_step(x, y, cur[b * batch:(b + 1) * batch], lr_ep, t)
+            mlp.train_step(x, y, rows[b * batch:(b + 1) * batch], lr_ep, t)
         losses[ep:ep + 1].copy_(mlp._loss)
-        if ep + 1 < epochs:
-            nxt = (ep + 1) % 2
-            copied[nxt].synchronize()           # the pinned buffer's previous copy is done
-            pinned[nxt].copy_(order(ep + 1))
-            rows[nxt].copy_(pinned[nxt], non_blocking=True)
-            copied[nxt].record(stream)
     hist = (losses / float(batch * wx.MLP_NOUT)).cpu().tolist()
     if log:
         for ep, last in enumerate(hist):

@@ -33,7 +33,7 @@ EXPORTS = ("wx_create", "wx_destroy", "wx_last_error", "wx_workspace_bytes", "wx
            "wx_copy_probe", "wx_features", "wx_dataset", "wx_surrogate_rows", "wx_mlp_bytes", "wx_mlp_offset",
            "wx_mlp_init", "wx_mlp_refresh", "wx_mlp_norm_scratch_bytes", "wx_mlp_fit_norm",
            "wx_mlp_normalize", "wx_mlp_work_bytes", "wx_mlp_forward_backward", "wx_mlp_adam",
-           "wx_mlp_train_step", "wx_mlp_infer_work_bytes", "wx_mlp_infer",
+           "wx_mlp_train_step", "wx_mlp_shuffle", "wx_mlp_infer_work_bytes", "wx_mlp_infer",
            "wx_surrogate_work_bytes", "wx_rw_step", "wx_rw_run", "wx_rw_run_kij", "wx_mass_noalloc",
            "wx_rw_run_block", "wx_hevi_grid_init", "wx_hevi_workspace_bytes", "wx_hevi_run")
 
@@ -134,6 +134,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.wx_mlp_adam.argtypes = [vp, ctypes.c_float, ctypes.c_int, vp]
     lib.wx_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, ctypes.c_int,
                                       vp, vp]
+    lib.wx_mlp_shuffle.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, vp, vp]
     lib.wx_mlp_infer_work_bytes.argtypes = [ctypes.c_int]
     lib.wx_mlp_infer.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp]
     lib.wx_surrogate_work_bytes.argtypes = [sp]
@@ -447,6 +448,15 @@ def bf16_bits_to_float(t):
     """Device int16 tensor of BF16 bit patterns -> float32 tensor (exact)."""
     torch = _torch()
     return (t.to(torch.int32) << 16).view(torch.float32)
+
+
+def shuffle(seed: int, epoch: int, n: int, out, stream=None) -> None:
+    """Training row order of one epoch, drawn on the device (wx_mlp_shuffle):
+    out[i] = P(i) for the first out.numel() elements of a permutation P of
+    0..n-1 fixed by (seed, epoch).  out: int32 CUDA tensor."""
+    lib = load_library()
+    _check(lib.wx_mlp_shuffle(int(seed), int(epoch), int(n), int(out.numel()), out.data_ptr(),
+                              _stream_ptr(stream)), "wx_mlp_shuffle")
 
 
 class Mlp:

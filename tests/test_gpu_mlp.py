@@ -103,6 +103,34 @@ def test_forward_matches_oracle(n):
     assert np.all(y[:, NOUT:] == 0)
 
 
+@pytest.mark.parametrize("n,m", [(1, 1), (7, 7), (1000, 1000), (2048000, 2048000), (5000, 4096)])
+def test_device_shuffle_is_a_seeded_permutation(n, m):
+    # wx_mlp_shuffle: the first m values of a permutation of 0..n-1, the same
+    # for the same (seed, epoch), another for the next epoch; m > n is refused
+    _say(f"case: shuffle n={n} m={m}")
+    torch = _torch()
+    a = torch.empty(m, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    c = torch.empty(n, dtype=torch.int32, device="cuda")
+    wx.shuffle(5, 3, n, a)
+    wx.shuffle(5, 3, n, b)
+    wx.shuffle(5, 4, n, c)
+    torch.cuda.synchronize()
+    a, b, c = a.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy()
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(np.sort(c), np.arange(n))
+    assert np.unique(a).size == m and a.min() >= 0 and a.max() < n
+    if m == n:
+        np.testing.assert_array_equal(np.sort(a), np.arange(n))
+    if n >= 1000:
+        assert not np.array_equal(a[:m], c[:m])
+        # a shuffle, not a near-identity: few fixed points
+        assert np.sum(a == np.arange(m)) < max(10, m // 100)
+    if m > 1:
+        with pytest.raises(wx.WxError):
+            wx.shuffle(5, 3, m - 1, torch.empty(m, dtype=torch.int32, device="cuda"))
+
+
 @pytest.mark.parametrize("batch", [1, 257])
 def test_training_step_stays_inside_its_workspace(batch):
     # the workspace of wx_mlp_forward_backward is exactly wx_mlp_work_bytes;
