@@ -509,8 +509,8 @@ def main() -> int:
                          "thread blocks")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the I/J decomposition is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(no I/J decomposition or halo exchange between GPUs)", file=sys.stderr)
         return 2
 
     import torch
