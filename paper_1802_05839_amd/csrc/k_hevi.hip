@@ -269,9 +269,11 @@ __global__ __launch_bounds__(256) void k_hevi_stage_reg(HeviArgs<T> a) {
 // back-substitutes outward.  Every right-hand side is formed from the same
 // operands as in the one-sided kernels.  Half a column per lane halves the
 // registers per lane (218 at nz = 58: two waves per SIMD) and the length of each
-// dependent chain.  32 x 8 columns per block (eight rows: the neighbour rows
-// that the divergence reads from outside the block are an eighth of its own;
-// four rows took 1.4% longer, two 8%); a lane past the grid edge works
+// dependent chain.  32 x R columns per block, R = blockDim.y: 8 for the
+// second stage (the neighbour rows its divergence reads from outside the
+// block are an eighth of its own), 4 for the first, which reads fewer fields
+// (2.46 ms per short step with 8 rows for both, 2.43 with 8 and 4, 2.54 with
+// 4 and 8, 2.48 with 8 and 2); a lane past the grid edge works
 // on column nx-1 (the same values and the same stores).
 template <typename T, bool FULL, int NZ>
 __global__ __launch_bounds__(512) void k_hevi_stage_split(HeviArgs<T> a) {
@@ -289,7 +291,7 @@ __global__ __launch_bounds__(512) void k_hevi_stage_split(HeviArgs<T> a) {
   const int nx = a.g.nx, ny = a.g.ny;
   const int nbx = (nx + 31) / 32;
   const int L = xcd_remap(blockIdx.x, gridDim.x);
-  const int i = (L % nbx) * 32 + (int(threadIdx.x) & 31), j = (L / nbx) * 8 + int(threadIdx.y);
+  const int i = (L % nbx) * 32 + (int(threadIdx.x) & 31), j = (L / nbx) * int(blockDim.y) + int(threadIdx.y);
   if (j >= ny) return;                     // whole waves
   const bool up = threadIdx.x >= 32;
   const int ic = min(i, nx - 1);
@@ -456,13 +458,15 @@ hipError_t launch_hevi_stage(const HeviArgs<T> &a, bool full, int kernel, hipStr
   const int nb = ((a.g.nx + 63) / 64) * ((a.g.ny + 3) / 4);
   const bool fixed = a.g.nz == 58 || a.g.nz == 16;
   if (kernel == 2 && fixed) {
-    const int nb2 = ((a.g.nx + 31) / 32) * ((a.g.ny + 7) / 8);
+    // 32 x 8 columns per block for the second stage, 32 x 4 for the first
+    const int rows = full ? 8 : 4;
+    const int nb2 = ((a.g.nx + 31) / 32) * ((a.g.ny + rows - 1) / rows);
     if (a.g.nz == 58) {
-      if (full) hipLaunchKernelGGL((k_hevi_stage_split<T, true, 58>), dim3(nb2), dim3(64, 8), 0, s, a);
-      else hipLaunchKernelGGL((k_hevi_stage_split<T, false, 58>), dim3(nb2), dim3(64, 8), 0, s, a);
+      if (full) hipLaunchKernelGGL((k_hevi_stage_split<T, true, 58>), dim3(nb2), dim3(64, rows), 0, s, a);
+      else hipLaunchKernelGGL((k_hevi_stage_split<T, false, 58>), dim3(nb2), dim3(64, rows), 0, s, a);
     } else {
-      if (full) hipLaunchKernelGGL((k_hevi_stage_split<T, true, 16>), dim3(nb2), dim3(64, 8), 0, s, a);
-      else hipLaunchKernelGGL((k_hevi_stage_split<T, false, 16>), dim3(nb2), dim3(64, 8), 0, s, a);
+      if (full) hipLaunchKernelGGL((k_hevi_stage_split<T, true, 16>), dim3(nb2), dim3(64, rows), 0, s, a);
+      else hipLaunchKernelGGL((k_hevi_stage_split<T, false, 16>), dim3(nb2), dim3(64, rows), 0, s, a);
     }
     return hipGetLastError();
   }
